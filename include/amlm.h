@@ -1,0 +1,225 @@
+/*
+ * amlm.h -- C ABI of the MI355X (gfx950) temporal pattern miner.
+ *
+ * Given a temporal transaction multigraph (accounts are vertices, each
+ * transaction is a directed edge src -> dst with an integer timestamp), the
+ * library attaches to every edge exact uint32 counts of the laundering
+ * patterns of the paper's multi-stage framework (Section 5): windowed
+ * fan-out / fan-in, scatter-gather through at least k intermediates,
+ * gather-scatter, and time-respecting cycles of length 2..L inside a window
+ * delta.  The counts are the per-transaction features of Section 8 ("the
+ * number of instances of each pattern the transaction participates in").
+ *
+ * Definitions.  Edge i = (src_i -> dst_i, ts_i).  Self-loops (src == dst)
+ * are removed from every pattern ("differentiate ... eliminating
+ * self-connections", Section 6) and their rows are all zero.  For an anchor
+ * edge e = (u -> v, t) the window is [t - delta, t] (Find_Start(t - delta)
+ * and the break on timestamps past t, Section 6):
+ *
+ *   FAN_OUT(e)  out-edges of u with timestamp in [t - delta, t]
+ *   FAN_IN(e)   in-edges of v with timestamp in [t - delta, t]
+ *   S(e)        distinct s != v with an edge s -> u at a time in [t-delta, t)
+ *   M_e(s)      distinct m with edges s -> m at time a and m -> v at time b,
+ *               t - delta <= a < b <= t
+ *   SG_k(e)     number of s in S(e) with |M_e(s)| >= k   (Section 5,
+ *               scatter-gather decomposition; Section 4, "at least N")
+ *   GS_k(e)     |S(e)| if |S(e)| >= k and u has at least k distinct
+ *               destinations at times in (tau, t], tau being the earliest
+ *               time of an edge into u from S(e) in the window; else 0
+ *   CYC_l(e)    number of l-edge cycles that contain e (2 <= l <= L): edges
+ *               c_1..c_l, dst(c_i) = src(c_{i+1}) cyclically, strictly
+ *               increasing timestamps, ts(c_l) - ts(c_1) <= delta, all l
+ *               vertices distinct (Section 5, cycle decomposition; Section
+ *               6, classical temporal motifs as a special case)
+ *
+ * Stage outputs are vertex sets (Algorithm 1), so S, M and the gather-scatter
+ * destinations count distinct accounts; FAN counts edges; cycles are edge
+ * sets (parallel edges give distinct cycles).  A count that would exceed
+ * 2^32 - 1 makes the call fail with AMLM_E_RANGE.
+ *
+ * Output layout: counts[col * n_edges + i] for edge i, with one column per
+ * requested pattern in the order FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.
+ *
+ * Threading: a handle may be used by one host thread at a time.  Errors are
+ * reported by the returned status; amlm_last_error() gives a thread-local
+ * message for the last failing call on the calling thread.
+ */
+#ifndef AMLM_H
+#define AMLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMLM_OK = 0,
+    AMLM_E_INVALID = 1, /* bad argument: vertex id >= n_vertices, L outside 2..8,
+                           k == 0, delta < 0, null pointer, unknown pattern bit */
+    AMLM_E_RANGE = 2,   /* timestamp span >= 2^31 - 1 seconds, or a count overflow */
+    AMLM_E_NOMEM = 3,   /* device allocation failed or over the server's HBM budget */
+    AMLM_E_DEVICE = 4,  /* a HIP runtime error; sticky on the handle */
+    AMLM_E_ORDER = 5,   /* a stream batch is not strictly later than what came before */
+    AMLM_E_BUSY = 6     /* no free server slot and the caller asked not to wait */
+} amlm_status;
+
+/* pattern bits */
+#define AMLM_FAN_OUT 1u
+#define AMLM_FAN_IN 2u
+#define AMLM_SG 4u
+#define AMLM_GS 8u
+#define AMLM_CYCLES 16u
+#define AMLM_ALL 31u
+
+/* schedules for the scatter-gather and cycle work (never change a count) */
+#define AMLM_SCHED_STATIC 0u  /* anchors in time order, one wave per anchor,
+                                 chunks taken by atomic work stealing */
+#define AMLM_SCHED_LEARNED 1u /* the cost model's predicted work bins anchors
+                                 into lane / wave granularity, heavy first */
+
+typedef struct {
+    uint32_t patterns;      /* OR of AMLM_FAN_OUT .. AMLM_CYCLES */
+    int64_t delta;          /* window length, same unit as the timestamps, >= 0 */
+    uint32_t max_cycle_len; /* L, 2..8 (ignored without AMLM_CYCLES) */
+    uint32_t k;             /* >= 1: SG / GS threshold (ignored without SG|GS) */
+    uint32_t schedule;      /* AMLM_SCHED_* */
+} amlm_params;
+
+typedef struct amlm_graph amlm_graph;
+
+/*
+ * Build the device graph store: validates ids and the time span, then builds
+ * time-sorted out- and in-adjacency (CSR / CSC), a neighbour-sorted copy of
+ * the in-adjacency and the same-neighbour time links the kernels use.
+ *
+ * src, dst: n_edges vertex ids (< n_vertices).  ts: n_edges timestamps (any
+ * int64; max - min must be < 2^31 - 1).  amount: optional, carried and
+ * ignored by every pattern (may be NULL).  inputs_on_device: 0 if the four
+ * pointers are host memory (copied), 1 if they are device memory on the
+ * current device (read, not retained).  hip_stream: a hipStream_t (NULL =
+ * default stream); the call synchronises that stream before returning.
+ * n_edges may be 0.  n_edges must be < 2^32 - 1.  On success *out owns its
+ * device memory until amlm_graph_destroy.
+ */
+amlm_status amlm_graph_create(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                              const float *amount, uint64_t n_edges, uint32_t n_vertices,
+                              int inputs_on_device, void *hip_stream, amlm_graph **out);
+
+/* Rebuild the same handle from a new edge list of any size (device buffers
+ * are reused when they are large enough).  Same arguments and errors as
+ * amlm_graph_create.  Queued on hip_stream; synchronises it on return. */
+amlm_status amlm_graph_rebuild(amlm_graph *g, const uint32_t *src, const uint32_t *dst,
+                               const int64_t *ts, uint64_t n_edges, uint32_t n_vertices,
+                               int inputs_on_device, void *hip_stream);
+
+void amlm_graph_destroy(amlm_graph *g);
+
+/* n_edges, number of non-self-loop edges, and the timestamp base (min ts) */
+amlm_status amlm_graph_info(const amlm_graph *g, uint64_t *n_edges, uint64_t *n_valid,
+                            uint32_t *n_vertices, int64_t *t_base);
+
+/* Number of output columns for these parameters (0 on invalid parameters). */
+uint32_t amlm_num_columns(const amlm_params *p);
+
+/*
+ * Mine every edge of g.  counts_dev: caller-owned device memory of
+ * amlm_num_columns(p) * n_edges uint32 on the graph's device, layout
+ * [col][edge].  Asynchronous on hip_stream (NULL = default stream): the
+ * host is not synchronised and the counts are valid once the stream has
+ * reached this point.  Parameter errors are reported before any device
+ * work.  A count overflow (> 2^32 - 1) is detected on the device and
+ * reported as AMLM_E_RANGE by the next call on the handle that
+ * synchronises (amlm_graph_sync).
+ */
+amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, void *hip_stream);
+
+/* Synchronise hip_stream and report device-side errors of earlier mining
+ * calls on g (AMLM_E_RANGE for a count overflow). Clears the error word. */
+amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream);
+
+/*
+ * Per-anchor work of the plain (static-schedule) miner: work_dev[i] for edge
+ * i is the number of adjacency entries the scatter-gather and cycle stages
+ * read for anchor i (slice elements scanned plus partial paths expanded).
+ * These are the cost model's training labels.  work_dev: device uint32
+ * [n_edges].  Counts are written to counts_dev exactly as amlm_mine does.
+ */
+amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
+                           uint32_t *work_dev, void *hip_stream);
+
+/*
+ * Mine n_graphs independent graphs in one launch sequence (captured once
+ * into a hipGraph per distinct batch shape and replayed).  gs[i], ps[i],
+ * counts_dev[i] are as for amlm_mine; each graph keeps its own delta, L and
+ * k, but all must request the same pattern set and schedule.
+ */
+amlm_status amlm_mine_batch(amlm_graph *const *gs, const amlm_params *ps, uint32_t *const *counts_dev,
+                            uint32_t n_graphs, void *hip_stream);
+
+/* ---- learned cost model (scheduling only; never changes a count) ---- */
+
+/*
+ * Train the 12 -> 64 -> 64 -> 1 MLP (BF16 weights, FP32 accumulation) on the
+ * per-anchor work labels of the given graphs, on the GPU, with the library's
+ * own forward / backward / Adam kernels, and keep it as the process-wide
+ * model.  If out_path is not NULL the weights are also written there.
+ * epochs, batch: training loop shape (0 = defaults: 4 epochs, 4096).
+ * Deterministic for a fixed seed.
+ */
+amlm_status amlm_costmodel_train(amlm_graph *const *train_graphs, const amlm_params *ps, uint32_t n,
+                                 uint32_t epochs, uint32_t batch, uint64_t seed,
+                                 const char *out_path, void *hip_stream);
+amlm_status amlm_costmodel_load(const char *path);
+amlm_status amlm_costmodel_save(const char *path);
+
+/* ---- streaming server (continuous batching) ---- */
+
+typedef struct amlm_server amlm_server;
+
+/*
+ * A server keeps the edges of `resident` plus every submitted batch in HBM
+ * and mines each submitted batch incrementally: the new edges' own columns
+ * come from instances that end at them; cycles closed by a new edge also
+ * credit older edges, which are reported as sparse deltas.  Batches must be
+ * strictly later in time than everything before them (AMLM_E_ORDER
+ * otherwise).  hbm_budget_bytes bounds the device memory the in-flight
+ * batches may hold (0 = no bound); max_slots bounds how many batches are
+ * mined concurrently, each on its own HIP stream.
+ */
+amlm_status amlm_server_create(amlm_graph *resident, const amlm_params *p, uint64_t hbm_budget_bytes,
+                               uint32_t max_slots, amlm_server **out);
+
+/* Copy a batch of n host edges, order it after the previous batches, and
+ * start mining it as soon as a slot and budget are free (blocking when
+ * wait != 0, else AMLM_E_BUSY).  *ticket identifies the batch. */
+amlm_status amlm_server_submit(amlm_server *s, const uint32_t *src, const uint32_t *dst,
+                               const int64_t *ts, uint64_t n, int wait, uint64_t *ticket);
+
+/*
+ * Wait for a batch.  new_counts_host: [ncols][n] for the batch's own edges
+ * (host memory, may be NULL).  Deltas for older edges: up to cap entries of
+ * (edge id, column, increment); *n_deltas gets the total number (entries
+ * past cap are dropped; call again with a larger cap is not supported, so
+ * size cap generously).  Edge ids of stream edges continue after the
+ * resident graph's: n_edges + running index.
+ */
+amlm_status amlm_server_wait(amlm_server *s, uint64_t ticket, uint32_t *new_counts_host,
+                             uint64_t *n_deltas, uint64_t *delta_eid, uint32_t *delta_col,
+                             uint32_t *delta_val, uint64_t cap);
+
+/* Per-ticket timing (host wall clock, seconds): submit -> admitted ->
+ * finished. */
+amlm_status amlm_server_ticket_times(amlm_server *s, uint64_t ticket, double *t_submit,
+                                     double *t_admit, double *t_done);
+
+void amlm_server_destroy(amlm_server *s);
+
+/* Thread-local message describing the last error on this thread. */
+const char *amlm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMLM_H */

@@ -1,0 +1,485 @@
+/*
+ * oracle.c -- plain, slow, single-threaded CPU reference for the per-edge
+ * pattern counts.  TEST INFRASTRUCTURE ONLY: it is called by the tests, by the
+ * smoke check and by the benchmark's CPU-baseline leg, never by the product
+ * path.  It shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes (the paper's Section 5 stage compositions, Algorithm 1's
+ * nested-loop semantics, and the readings listed in the design notes where
+ * the paper is silent):
+ *
+ *   edge i = (src_i -> dst_i, ts_i); self-loops (src == dst) take part in
+ *   nothing and get all-zero rows (the "differentiate" primitive that removes
+ *   self-connections, Section 6).  For anchor e = (u -> v, t), window
+ *   W = [t - delta, t] (Find_Start(t - delta) then break once a timestamp
+ *   exceeds t, Section 6 input specification and the scatter-gather example).
+ *
+ *   FAN_OUT(e) = #{out-edges of u with ts in W}
+ *   FAN_IN(e)  = #{in-edges of v with ts in W}
+ *   S(e)       = distinct senders s != v of an edge s -> u, ts in [t-delta, t)
+ *                (scatter-gather example: for_all over N0.in_neigh, skip N2 == N1)
+ *   M_e(s)     = distinct m with a: s -> m, b: m -> v,
+ *                t - delta <= ts_a < ts_b <= t
+ *                (the intersection N2.out_neigh with N1.in_neigh; Section 3's
+ *                per-intermediate partial order t_i < t_{i+1})
+ *   SG_k(e)    = #{s in S(e) : |M_e(s)| >= k}   ("at least N", Section 4)
+ *   GS_k(e)    = |S(e)| if |S(e)| >= k and |D(e)| >= k, else 0, with
+ *                tau = earliest ts of an edge into u from s != v in [t-delta, t)
+ *                and D(e) = distinct d with u -> d, tau < ts <= t
+ *                ("integration occurs after placement", Section 4)
+ *   CYC_l(e)   = number of l-cycles containing e, 2 <= l <= L: l edges
+ *                c_1..c_l with dst(c_i) = src(c_{i+1}) cyclically, strictly
+ *                increasing timestamps, ts(c_l) - ts(c_1) <= delta and
+ *                pairwise distinct vertices (the classical temporal motif
+ *                special case, Section 6; cycle decomposition, Section 5)
+ *
+ * Stage outputs are vertex sets (Algorithm 1: the output of a stage is nodes,
+ * not edges), so S, M and D count distinct vertices; FAN counts edges; cycles
+ * are edge sets, so parallel edges give distinct cycles.  Every count is
+ * accumulated in 64 bits and clamped to 2^32 - 1 on output.
+ *
+ * Columns, in this order, for the requested patterns only:
+ *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.   Layout [ncols][n_edges].
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_FAN_OUT 1u
+#define OR_FAN_IN 2u
+#define OR_SG 4u
+#define OR_GS 8u
+#define OR_CYC 16u
+
+typedef struct {
+    uint64_t n;
+    uint32_t nv;
+    const uint32_t *src, *dst;
+    const int64_t *ts;
+    uint64_t *out_ptr, *in_ptr; /* nv + 1 */
+    uint64_t *out_e, *in_e;     /* valid edge ids per row, sorted by (ts, id) */
+} og_graph;
+
+/* ---- sorting valid edge ids by (ts, id) ---------------------------------- */
+static const int64_t *g_sort_ts;
+static int cmp_ts_id(const void *a, const void *b) {
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    if (g_sort_ts[x] != g_sort_ts[y]) return g_sort_ts[x] < g_sort_ts[y] ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int og_build(og_graph *g, uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst,
+                    const int64_t *ts) {
+    memset(g, 0, sizeof(*g));
+    g->n = n; g->nv = nv; g->src = src; g->dst = dst; g->ts = ts;
+    uint64_t nvalid = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        if (src[i] >= nv || dst[i] >= nv) return 1;
+        if (src[i] != dst[i]) nvalid++;
+    }
+    uint64_t *order = (uint64_t *)malloc(sizeof(uint64_t) * (nvalid ? nvalid : 1));
+    g->out_ptr = (uint64_t *)calloc((size_t)nv + 1, sizeof(uint64_t));
+    g->in_ptr = (uint64_t *)calloc((size_t)nv + 1, sizeof(uint64_t));
+    g->out_e = (uint64_t *)malloc(sizeof(uint64_t) * (nvalid ? nvalid : 1));
+    g->in_e = (uint64_t *)malloc(sizeof(uint64_t) * (nvalid ? nvalid : 1));
+    uint64_t *fo = (uint64_t *)calloc((size_t)nv + 1, sizeof(uint64_t));
+    uint64_t *fi = (uint64_t *)calloc((size_t)nv + 1, sizeof(uint64_t));
+    if (!order || !g->out_ptr || !g->in_ptr || !g->out_e || !g->in_e || !fo || !fi) return 2;
+    uint64_t m = 0;
+    for (uint64_t i = 0; i < n; i++)
+        if (src[i] != dst[i]) order[m++] = i;
+    g_sort_ts = ts;
+    qsort(order, nvalid, sizeof(uint64_t), cmp_ts_id);
+    for (uint64_t j = 0; j < nvalid; j++) {
+        g->out_ptr[src[order[j]] + 1]++;
+        g->in_ptr[dst[order[j]] + 1]++;
+    }
+    for (uint32_t x = 0; x < nv; x++) {
+        g->out_ptr[x + 1] += g->out_ptr[x];
+        g->in_ptr[x + 1] += g->in_ptr[x];
+    }
+    /* appending in (ts, id) order keeps every row in (ts, id) order */
+    for (uint64_t j = 0; j < nvalid; j++) {
+        uint64_t i = order[j];
+        g->out_e[g->out_ptr[src[i]] + fo[src[i]]++] = i;
+        g->in_e[g->in_ptr[dst[i]] + fi[dst[i]]++] = i;
+    }
+    free(order); free(fo); free(fi);
+    return 0;
+}
+
+static void og_free(og_graph *g) {
+    free(g->out_ptr); free(g->in_ptr); free(g->out_e); free(g->in_e);
+}
+
+/* first position p in row [b, e) of edge ids with ts[id] >= x */
+static uint64_t lower_ts(const og_graph *g, const uint64_t *row, uint64_t b, uint64_t e, int64_t x) {
+    while (b < e) {
+        uint64_t mid = b + (e - b) / 2;
+        if (g->ts[row[mid]] < x) b = mid + 1; else e = mid;
+    }
+    return b;
+}
+/* first position p in row [b, e) with ts[id] > x */
+static uint64_t upper_ts(const og_graph *g, const uint64_t *row, uint64_t b, uint64_t e, int64_t x) {
+    while (b < e) {
+        uint64_t mid = b + (e - b) / 2;
+        if (g->ts[row[mid]] <= x) b = mid + 1; else e = mid;
+    }
+    return b;
+}
+
+static uint32_t clamp32(uint64_t x) { return x > 0xffffffffull ? 0xffffffffu : (uint32_t)x; }
+
+uint32_t oracle_num_columns(uint32_t patterns, uint32_t L) {
+    uint32_t c = 0;
+    if (patterns & OR_FAN_OUT) c++;
+    if (patterns & OR_FAN_IN) c++;
+    if (patterns & OR_SG) c++;
+    if (patterns & OR_GS) c++;
+    if (patterns & OR_CYC) c += L - 1;
+    return c;
+}
+
+/* scratch for the distinct-vertex sets (stamp arrays, one entry per vertex) */
+typedef struct {
+    uint64_t *stamp_s, *stamp_b, *stamp_m, *stamp_d;
+    int64_t *maxb;
+    uint64_t *slist;
+    uint64_t clock;
+} og_scratch;
+
+static int scratch_init(og_scratch *s, uint32_t nv) {
+    size_t nn = (size_t)nv + 1;
+    s->stamp_s = (uint64_t *)calloc(nn, 8); s->stamp_b = (uint64_t *)calloc(nn, 8);
+    s->stamp_m = (uint64_t *)calloc(nn, 8); s->stamp_d = (uint64_t *)calloc(nn, 8);
+    s->maxb = (int64_t *)calloc(nn, 8); s->slist = (uint64_t *)calloc(nn, 8);
+    s->clock = 0;
+    return (s->stamp_s && s->stamp_b && s->stamp_m && s->stamp_d && s->maxb && s->slist) ? 0 : 2;
+}
+static void scratch_free(og_scratch *s) {
+    free(s->stamp_s); free(s->stamp_b); free(s->stamp_m); free(s->stamp_d); free(s->maxb); free(s->slist);
+}
+
+/* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k (written to out4). */
+static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k,
+                     uint64_t out4[4]) {
+    uint32_t u = g->src[e], v = g->dst[e];
+    int64_t t = g->ts[e], lo = t - delta;
+    out4[0] = out4[1] = out4[2] = out4[3] = 0;
+    if (u == v) return;
+
+    /* FAN: sizes of the window slices (rows are sorted by timestamp) */
+    uint64_t ob = g->out_ptr[u], oe = g->out_ptr[u + 1];
+    uint64_t ib = g->in_ptr[v], ie = g->in_ptr[v + 1];
+    out4[0] = upper_ts(g, g->out_e, ob, oe, t) - lower_ts(g, g->out_e, ob, oe, lo);
+    out4[1] = upper_ts(g, g->in_e, ib, ie, t) - lower_ts(g, g->in_e, ib, ie, lo);
+
+    /* S(e): distinct senders into u in [lo, t), excluding v */
+    uint64_t ub_ = g->in_ptr[u], ue_ = g->in_ptr[u + 1];
+    uint64_t p0 = lower_ts(g, g->in_e, ub_, ue_, lo), p1 = lower_ts(g, g->in_e, ub_, ue_, t);
+    uint64_t cs = ++sc->clock, nS = 0;
+    int have_tau = 0;
+    int64_t tau = 0;
+    for (uint64_t p = p0; p < p1; p++) {
+        uint64_t a = g->in_e[p];
+        uint32_t s = g->src[a];
+        if (s == v) continue;
+        if (!have_tau) { have_tau = 1; tau = g->ts[a]; } /* rows are time-sorted */
+        if (sc->stamp_s[s] != cs) { sc->stamp_s[s] = cs; sc->slist[nS++] = s; }
+    }
+
+    /* SG_k: latest gather time into v per in-neighbour m, over [lo, t] */
+    uint64_t cb = ++sc->clock;
+    uint64_t q0 = lower_ts(g, g->in_e, ib, ie, lo), q1 = upper_ts(g, g->in_e, ib, ie, t);
+    for (uint64_t p = q0; p < q1; p++) {
+        uint64_t b = g->in_e[p];
+        uint32_t m = g->src[b];
+        if (sc->stamp_b[m] != cb) { sc->stamp_b[m] = cb; sc->maxb[m] = g->ts[b]; }
+        else if (g->ts[b] > sc->maxb[m]) sc->maxb[m] = g->ts[b];
+    }
+    uint64_t sg = 0;
+    for (uint64_t i = 0; i < nS; i++) {
+        uint32_t s = (uint32_t)sc->slist[i];
+        uint64_t cm = ++sc->clock, nm = 0;
+        uint64_t sb = g->out_ptr[s], se = g->out_ptr[s + 1];
+        uint64_t r0 = lower_ts(g, g->out_e, sb, se, lo), r1 = lower_ts(g, g->out_e, sb, se, t);
+        for (uint64_t p = r0; p < r1; p++) {
+            uint64_t a = g->out_e[p];
+            uint32_t m = g->dst[a];
+            if (sc->stamp_b[m] == cb && g->ts[a] < sc->maxb[m] && sc->stamp_m[m] != cm) {
+                sc->stamp_m[m] = cm;
+                nm++;
+            }
+        }
+        if (nm >= k) sg++;
+    }
+    out4[2] = sg;
+
+    /* GS_k: distinct destinations of u strictly after tau, up to t */
+    if (nS >= k && have_tau) {
+        uint64_t cd = ++sc->clock, nd = 0;
+        uint64_t d0 = upper_ts(g, g->out_e, ob, oe, tau), d1 = upper_ts(g, g->out_e, ob, oe, t);
+        for (uint64_t p = d0; p < d1; p++) {
+            uint32_t d = g->dst[g->out_e[p]];
+            if (sc->stamp_d[d] != cd) { sc->stamp_d[d] = cd; nd++; }
+        }
+        if (nd >= k) out4[3] = nS;
+    }
+}
+
+/* ---- cycles anchored on their last edge, credited to every member edge ---- */
+typedef struct {
+    const og_graph *g;
+    int64_t t, lo;
+    uint32_t u, L;
+    uint64_t anchor;
+    uint64_t path_e[16];
+    uint32_t path_v[16];
+    uint64_t *acc; /* [L-1][n] accumulators, column l-2 */
+} cyc_ctx;
+
+static void cyc_dfs(cyc_ctx *c, uint32_t h, uint32_t d, int64_t tlast) {
+    const og_graph *g = c->g;
+    uint64_t rb = g->out_ptr[h], re = g->out_ptr[h + 1];
+    /* first hop: [lo, t); later hops: (tlast, t) */
+    uint64_t p0 = d == 0 ? lower_ts(g, g->out_e, rb, re, c->lo) : upper_ts(g, g->out_e, rb, re, tlast);
+    uint64_t p1 = lower_ts(g, g->out_e, rb, re, c->t);
+    for (uint64_t p = p0; p < p1; p++) {
+        uint64_t j = g->out_e[p];
+        uint32_t w = g->dst[j];
+        if (w == c->u) {
+            uint32_t l = d + 2; /* d path edges + closing edge j + anchor */
+            uint64_t *col = c->acc + (uint64_t)(l - 2) * g->n;
+            for (uint32_t q = 0; q < d; q++) col[c->path_e[q]]++;
+            col[j]++;
+            col[c->anchor]++;
+        } else if (d + 1 <= c->L - 2) {
+            int seen = 0;
+            for (uint32_t q = 0; q <= d; q++)
+                if (c->path_v[q] == w) { seen = 1; break; }
+            if (seen) continue;
+            c->path_e[d] = j;
+            c->path_v[d + 1] = w;
+            cyc_dfs(c, w, d + 1, g->ts[j]);
+        }
+    }
+}
+
+static int check_params(uint32_t patterns, int64_t delta, uint32_t L, uint32_t k) {
+    if (delta < 0) return 3;
+    if ((patterns & (OR_SG | OR_GS)) && k == 0) return 3;
+    if ((patterns & OR_CYC) && (L < 2 || L > 8)) return 3;
+    return 0;
+}
+
+/*
+ * Full mining of every edge.  counts: [ncols][n] uint32 (caller-owned).
+ * Returns 0 on success, 1 on an out-of-range vertex id, 2 on allocation
+ * failure, 3 on invalid parameters.
+ */
+int oracle_mine(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint32_t *counts) {
+    int rc = check_params(patterns, delta, L, k);
+    if (rc) return rc;
+    og_graph g;
+    og_scratch sc;
+    if ((rc = og_build(&g, n, nv, src, dst, ts))) return rc;
+    if ((rc = scratch_init(&sc, nv))) return rc;
+    uint32_t ncols = oracle_num_columns(patterns, L);
+    memset(counts, 0, sizeof(uint32_t) * (size_t)ncols * n);
+    uint32_t col = 0;
+    int c_fo = -1, c_fi = -1, c_sg = -1, c_gs = -1, c_cy = -1;
+    if (patterns & OR_FAN_OUT) c_fo = col++;
+    if (patterns & OR_FAN_IN) c_fi = col++;
+    if (patterns & OR_SG) c_sg = col++;
+    if (patterns & OR_GS) c_gs = col++;
+    if (patterns & OR_CYC) c_cy = col;
+    if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS)) {
+        for (uint64_t e = 0; e < n; e++) {
+            uint64_t r[4];
+            anchored(&g, &sc, e, delta, k, r);
+            if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = clamp32(r[0]);
+            if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = clamp32(r[1]);
+            if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = clamp32(r[2]);
+            if (c_gs >= 0) counts[(uint64_t)c_gs * n + e] = clamp32(r[3]);
+        }
+    }
+    if (c_cy >= 0) {
+        uint64_t *acc = (uint64_t *)calloc((size_t)(L - 1) * (n ? n : 1), sizeof(uint64_t));
+        if (!acc) { og_free(&g); scratch_free(&sc); return 2; }
+        cyc_ctx c;
+        memset(&c, 0, sizeof(c));
+        c.g = &g; c.L = L; c.acc = acc;
+        for (uint64_t e = 0; e < n; e++) {
+            if (src[e] == dst[e]) continue;
+            c.u = src[e]; c.t = ts[e]; c.lo = ts[e] - delta; c.anchor = e;
+            c.path_v[0] = dst[e];
+            cyc_dfs(&c, dst[e], 0, 0);
+        }
+        for (uint32_t l = 0; l + 1 < L; l++)
+            for (uint64_t e = 0; e < n; e++)
+                counts[(uint64_t)(c_cy + l) * n + e] = clamp32(acc[(uint64_t)l * n + e]);
+        free(acc);
+    }
+    og_free(&g);
+    scratch_free(&sc);
+    return 0;
+}
+
+/* ---- cycles through one edge at any position (sampled checks) ----------- */
+/*
+ * Enumerate the cycle read from e onwards: e, f_1, ..., f_{l-1}, a simple path
+ * v -> ... -> u.  In cycle order the timestamps rise everywhere except at the
+ * single wrap from c_l back to c_1, so the path is a rising run of edges later
+ * than t (they follow e), then a rising run earlier than t (they precede e).
+ * The span condition is c_l - c_1 <= delta, c_l being the last edge of the
+ * first run (or e) and c_1 the first edge of the second run (or e).
+ */
+typedef struct {
+    const og_graph *g;
+    uint64_t e;
+    int64_t t, delta;
+    uint32_t u, L;
+    uint32_t path_v[16];
+    uint64_t cnt[9];
+} thr_ctx;
+
+static void thr_dfs(thr_ctx *c, uint32_t h, uint32_t d, int phase, int64_t tprev, int64_t c_last,
+                    int64_t c_first) {
+    /* d edges taken after e; h = head; phase 0 = rising after t, 1 = rising before t */
+    const og_graph *g = c->g;
+    uint64_t rb = g->out_ptr[h], re = g->out_ptr[h + 1];
+    /* every edge of a cycle through e lies within delta of t */
+    uint64_t pb = lower_ts(g, g->out_e, rb, re, c->t - c->delta);
+    uint64_t pe = upper_ts(g, g->out_e, rb, re, c->t + c->delta);
+    for (uint64_t p = pb; p < pe; p++) {
+        uint64_t j = g->out_e[p];
+        int64_t tj = g->ts[j];
+        uint32_t w = g->dst[j];
+        int nphase;
+        int64_t nlast = c_last, nfirst = c_first;
+        if (phase == 0 && tj > tprev && tj > c->t) {
+            nphase = 0;
+            nlast = tj;
+        } else if (tj < c->t && ((phase == 0) || tj > tprev)) {
+            nphase = 1;
+            if (phase == 0) nfirst = tj;
+        } else {
+            continue;
+        }
+        if (nlast - nfirst > c->delta) continue;
+        if (w == c->u) {
+            uint32_t l = d + 2;
+            if (l <= c->L) c->cnt[l]++;
+            continue;
+        }
+        if (d + 2 >= c->L) continue; /* a longer path could not close within L */
+        int seen = 0;
+        for (uint32_t q = 0; q <= d; q++)
+            if (c->path_v[q] == w) { seen = 1; break; }
+        if (seen) continue;
+        c->path_v[d + 1] = w;
+        thr_dfs(c, w, d + 1, nphase, tj, nlast, nfirst);
+    }
+}
+
+/*
+ * Sampled mining: the same columns as oracle_mine but only for the listed
+ * edges (rows of out: [ncols][n_sel]).  Cycle columns are computed by the
+ * through-edge enumeration above, independently of oracle_mine's
+ * last-edge-anchored search.
+ */
+int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst,
+                         const int64_t *ts, uint32_t patterns, int64_t delta, uint32_t L, uint32_t k,
+                         const uint64_t *sel, uint64_t n_sel, uint32_t *out) {
+    int rc = check_params(patterns, delta, L, k);
+    if (rc) return rc;
+    og_graph g;
+    og_scratch sc;
+    if ((rc = og_build(&g, n, nv, src, dst, ts))) return rc;
+    if ((rc = scratch_init(&sc, nv))) return rc;
+    uint32_t ncols = oracle_num_columns(patterns, L);
+    memset(out, 0, sizeof(uint32_t) * (size_t)ncols * n_sel);
+    for (uint64_t i = 0; i < n_sel; i++) {
+        uint64_t e = sel[i];
+        if (e >= n) { og_free(&g); scratch_free(&sc); return 3; }
+        uint32_t col = 0;
+        uint64_t r[4];
+        anchored(&g, &sc, e, delta, k, r);
+        if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[0]);
+        if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[1]);
+        if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[2]);
+        if (patterns & OR_GS) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[3]);
+        if ((patterns & OR_CYC) && src[e] != dst[e]) {
+            thr_ctx c;
+            memset(&c, 0, sizeof(c));
+            c.g = &g; c.e = e; c.t = ts[e]; c.delta = delta; c.u = src[e]; c.L = L;
+            c.path_v[0] = dst[e];
+            thr_dfs(&c, dst[e], 0, 0, ts[e], ts[e], ts[e]);
+            for (uint32_t l = 2; l <= L; l++) out[(uint64_t)(col + l - 2) * n_sel + i] = clamp32(c.cnt[l]);
+        }
+    }
+    og_free(&g);
+    scratch_free(&sc);
+    return 0;
+}
+
+/*
+ * Number of distinct l-cycles, each counted once from its FIRST edge c_1:
+ * a forward search over strictly later edges with timestamps up to
+ * ts(c_1) + delta that closes back at src(c_1).  Used for the identity
+ * sum_e CYC_l(e) = l * C_l.  Output cnt[l] for l = 2..L (cnt has L+1 slots).
+ */
+typedef struct {
+    const og_graph *g;
+    int64_t t1, delta;
+    uint32_t s0, L;
+    uint32_t path_v[16];
+    uint64_t *cnt;
+} fwd_ctx;
+
+/* m = edges on the path so far; path_v[0..m] = s0, ..., h */
+static void fwd_dfs(fwd_ctx *c, uint32_t h, uint32_t m, int64_t tprev) {
+    const og_graph *g = c->g;
+    uint64_t rb = g->out_ptr[h], re = g->out_ptr[h + 1];
+    uint64_t p0 = upper_ts(g, g->out_e, rb, re, tprev);
+    uint64_t p1 = upper_ts(g, g->out_e, rb, re, c->t1 + c->delta);
+    for (uint64_t p = p0; p < p1; p++) {
+        uint64_t j = g->out_e[p];
+        uint32_t w = g->dst[j];
+        if (w == c->s0) {
+            if (m + 1 <= c->L) c->cnt[m + 1]++;
+            continue;
+        }
+        if (m + 2 > c->L) continue;
+        int seen = 0;
+        for (uint32_t q = 0; q <= m; q++)
+            if (c->path_v[q] == w) { seen = 1; break; }
+        if (seen) continue;
+        c->path_v[m + 1] = w;
+        fwd_dfs(c, w, m + 1, g->ts[j]);
+    }
+}
+
+int oracle_count_cycles_first(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst,
+                              const int64_t *ts, int64_t delta, uint32_t L, uint64_t *cnt) {
+    int rc = check_params(OR_CYC, delta, L, 1);
+    if (rc) return rc;
+    og_graph g;
+    if ((rc = og_build(&g, n, nv, src, dst, ts))) return rc;
+    memset(cnt, 0, sizeof(uint64_t) * (L + 1));
+    fwd_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.g = &g; c.delta = delta; c.L = L; c.cnt = cnt;
+    for (uint64_t e = 0; e < n; e++) {
+        if (src[e] == dst[e]) continue;
+        c.s0 = src[e];
+        c.t1 = ts[e];
+        c.path_v[0] = src[e];
+        c.path_v[1] = dst[e];
+        fwd_dfs(&c, dst[e], 1, ts[e]);
+    }
+    og_free(&g);
+    return 0;
+}
