@@ -134,16 +134,28 @@ uint32_t amlm_num_columns(const amlm_params *p);
  */
 amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, void *hip_stream);
 
+/* Stage timing with HIP events on the mining stream (for benchmarks).
+ * After amlm_set_timing(g, 1), every amlm_graph_rebuild / amlm_mine on g
+ * records its stages; amlm_stage_times waits for the last recorded events and
+ * returns milliseconds per stage in ms[8]: 0 graph build, 1 anchor pass,
+ * 2 work-list compaction, 3 scatter-gather kernel, 4 cycle kernel, 5 cost
+ * model inference and binning; -1 for a stage that did not run. */
+amlm_status amlm_set_timing(amlm_graph *g, int enable);
+amlm_status amlm_stage_times(amlm_graph *g, float *ms);
+
 /* Synchronise hip_stream and report device-side errors of earlier mining
  * calls on g (AMLM_E_RANGE for a count overflow). Clears the error word. */
 amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream);
 
 /*
- * Per-anchor work of the plain (static-schedule) miner: work_dev[i] for edge
- * i is the number of adjacency entries the scatter-gather and cycle stages
- * read for anchor i (slice elements scanned plus partial paths expanded).
- * These are the cost model's training labels.  work_dev: device uint32
- * [n_edges].  Counts are written to counts_dev exactly as amlm_mine does.
+ * Per-anchor work of the plain (static-schedule) miner, in algorithmic bytes:
+ * work_dev[i] for edge i is what the scatter-gather / gather-scatter stage
+ * reads for anchor i (its senders' window, the staged gather window, the
+ * senders' out-windows and the scatter window), and work_dev[n_edges + i]
+ * what the cycle stage reads for searches rooted at anchor i (partial paths
+ * expanded and their time slices, closing searches).  These are the cost
+ * model's training labels and the roofline's byte counts.  work_dev: device
+ * uint32 [2][n_edges].  Counts are written to counts_dev as amlm_mine does.
  */
 amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
                            uint32_t *work_dev, void *hip_stream);

@@ -42,6 +42,8 @@ def _load():
         lib.oracle_num_columns.restype = u32
         lib.oracle_mine.argtypes = [u64, u32, p, p, p, u32, i64, u32, u32, p]
         lib.oracle_mine.restype = ctypes.c_int
+        lib.oracle_mine_range.argtypes = [u64, u32, p, p, p, u32, i64, u32, u32, u64, u64, p, p]
+        lib.oracle_mine_range.restype = ctypes.c_int
         lib.oracle_mine_selected.argtypes = [u64, u32, p, p, p, u32, i64, u32, u32, p, u64, p]
         lib.oracle_mine_selected.restype = ctypes.c_int
         lib.oracle_count_cycles_first.argtypes = [u64, u32, p, p, p, i64, u32, p]
@@ -77,6 +79,20 @@ def mine(src, dst, ts, n_vertices: int, patterns: int = ALL, delta: int = 86400,
     _check(lib.oracle_mine(n, n_vertices, src.ctypes.data, dst.ctypes.data, ts.ctypes.data,
                            patterns, delta, L, k, out.ctypes.data))
     return out
+
+
+def mine_range(src, dst, ts, n_vertices: int, a_lo: int, a_hi: int, patterns: int = ALL,
+               delta: int = 86400, L: int = 4, k: int = 2):
+    """Anchors restricted to edge ids [a_lo, a_hi); returns (counts, seconds
+    spent in the anchor loops)."""
+    lib = _load()
+    src, dst, ts = _arrays(src, dst, ts)
+    n = src.shape[0]
+    out = np.zeros((num_columns(patterns, L), n), dtype=np.uint32)
+    sec = ctypes.c_double()
+    _check(lib.oracle_mine_range(n, n_vertices, src.ctypes.data, dst.ctypes.data, ts.ctypes.data,
+                                 patterns, delta, L, k, a_lo, a_hi, out.ctypes.data, ctypes.byref(sec)))
+    return out, sec.value
 
 
 def mine_selected(src, dst, ts, n_vertices: int, sel, patterns: int = ALL, delta: int = 86400,

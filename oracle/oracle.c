@@ -41,9 +41,11 @@
  * Columns, in this order, for the requested patterns only:
  *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.   Layout [ncols][n_edges].
  */
+#define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define OR_FAN_OUT 1u
 #define OR_FAN_IN 2u
@@ -273,15 +275,28 @@ static int check_params(uint32_t patterns, int64_t delta, uint32_t L, uint32_t k
     return 0;
 }
 
+static double now_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 /*
- * Full mining of every edge.  counts: [ncols][n] uint32 (caller-owned).
+ * Mining with the anchors restricted to edge ids [a_lo, a_hi): the anchored
+ * columns of those edges, and every cycle whose LAST edge is one of them,
+ * credited to all of its edges.  Over disjoint ranges the results add up to
+ * the full mining.  counts: [ncols][n] uint32 (caller-owned).  seconds, if not
+ * NULL, receives the wall time of the anchor loops (graph set-up excluded).
  * Returns 0 on success, 1 on an out-of-range vertex id, 2 on allocation
  * failure, 3 on invalid parameters.
  */
-int oracle_mine(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
-                uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint32_t *counts) {
+int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                      uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint64_t a_lo, uint64_t a_hi,
+                      uint32_t *counts, double *seconds) {
     int rc = check_params(patterns, delta, L, k);
     if (rc) return rc;
+    if (a_hi > n) a_hi = n;
+    if (a_lo > a_hi) a_lo = a_hi;
     og_graph g;
     og_scratch sc;
     if ((rc = og_build(&g, n, nv, src, dst, ts))) return rc;
@@ -295,8 +310,14 @@ int oracle_mine(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *ds
     if (patterns & OR_SG) c_sg = col++;
     if (patterns & OR_GS) c_gs = col++;
     if (patterns & OR_CYC) c_cy = col;
+    uint64_t *acc = NULL;
+    if (c_cy >= 0) {
+        acc = (uint64_t *)calloc((size_t)(L - 1) * (n ? n : 1), sizeof(uint64_t));
+        if (!acc) { og_free(&g); scratch_free(&sc); return 2; }
+    }
+    double t0 = now_s();
     if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS)) {
-        for (uint64_t e = 0; e < n; e++) {
+        for (uint64_t e = a_lo; e < a_hi; e++) {
             uint64_t r[4];
             anchored(&g, &sc, e, delta, k, r);
             if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = clamp32(r[0]);
@@ -306,25 +327,33 @@ int oracle_mine(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *ds
         }
     }
     if (c_cy >= 0) {
-        uint64_t *acc = (uint64_t *)calloc((size_t)(L - 1) * (n ? n : 1), sizeof(uint64_t));
-        if (!acc) { og_free(&g); scratch_free(&sc); return 2; }
         cyc_ctx c;
         memset(&c, 0, sizeof(c));
         c.g = &g; c.L = L; c.acc = acc;
-        for (uint64_t e = 0; e < n; e++) {
+        for (uint64_t e = a_lo; e < a_hi; e++) {
             if (src[e] == dst[e]) continue;
             c.u = src[e]; c.t = ts[e]; c.lo = ts[e] - delta; c.anchor = e;
             c.path_v[0] = dst[e];
             cyc_dfs(&c, dst[e], 0, 0);
         }
+    }
+    double t1 = now_s();
+    if (c_cy >= 0) {
         for (uint32_t l = 0; l + 1 < L; l++)
             for (uint64_t e = 0; e < n; e++)
                 counts[(uint64_t)(c_cy + l) * n + e] = clamp32(acc[(uint64_t)l * n + e]);
         free(acc);
     }
+    if (seconds) *seconds = t1 - t0;
     og_free(&g);
     scratch_free(&sc);
     return 0;
+}
+
+/* Full mining of every edge (see oracle_mine_range). */
+int oracle_mine(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint32_t *counts) {
+    return oracle_mine_range(n, nv, src, dst, ts, patterns, delta, L, k, 0, n, counts, NULL);
 }
 
 /* ---- cycles through one edge at any position (sampled checks) ----------- */

@@ -1,0 +1,217 @@
+"""MI355X-native temporal pattern miner (thin Python binding of libamlm.so).
+
+Every step of the mining path runs in the HIP library; this module only
+marshals arguments.  PyTorch supplies device memory and streams.  If the
+library has not been built the import of :func:`lib` raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamlm.so")
+
+AMLM_FAN_OUT, AMLM_FAN_IN, AMLM_SG, AMLM_GS, AMLM_CYCLES = 1, 2, 4, 8, 16
+AMLM_ALL = 31
+AMLM_SCHED_STATIC, AMLM_SCHED_LEARNED = 0, 1
+STATUS = {0: "AMLM_OK", 1: "AMLM_E_INVALID", 2: "AMLM_E_RANGE", 3: "AMLM_E_NOMEM",
+          4: "AMLM_E_DEVICE", 5: "AMLM_E_ORDER", 6: "AMLM_E_BUSY"}
+
+# every symbol the C header declares
+EXPORTS = [
+    "amlm_graph_create", "amlm_graph_rebuild", "amlm_graph_destroy", "amlm_graph_info",
+    "amlm_num_columns", "amlm_mine", "amlm_graph_sync", "amlm_mine_work", "amlm_mine_batch",
+    "amlm_costmodel_train", "amlm_costmodel_load", "amlm_costmodel_save",
+    "amlm_server_create", "amlm_server_submit", "amlm_server_wait", "amlm_server_ticket_times",
+    "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
+]
+
+
+class AmlmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class amlm_params(ctypes.Structure):
+    _fields_ = [("patterns", ctypes.c_uint32), ("delta", ctypes.c_int64),
+                ("max_cycle_len", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("schedule", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libamlm.so (built by ``paper_2604_12241_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        p, u32, u64, i64, st = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int
+        pp = ctypes.POINTER(amlm_params)
+        sig = {
+            "amlm_graph_create": (st, [p, p, p, p, u64, u32, ctypes.c_int, p, ctypes.POINTER(p)]),
+            "amlm_graph_rebuild": (st, [p, p, p, p, u64, u32, ctypes.c_int, p]),
+            "amlm_graph_destroy": (None, [p]),
+            "amlm_graph_info": (st, [p, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32),
+                                     ctypes.POINTER(i64)]),
+            "amlm_num_columns": (u32, [pp]),
+            "amlm_mine": (st, [p, pp, p, p]),
+            "amlm_graph_sync": (st, [p, p]),
+            "amlm_mine_work": (st, [p, pp, p, p, p]),
+            "amlm_mine_batch": (st, [p, pp, p, u32, p]),
+            "amlm_costmodel_train": (st, [p, pp, u32, u32, u32, u64, ctypes.c_char_p, p]),
+            "amlm_costmodel_load": (st, [ctypes.c_char_p]),
+            "amlm_costmodel_save": (st, [ctypes.c_char_p]),
+            "amlm_server_create": (st, [p, pp, u64, u32, ctypes.POINTER(p)]),
+            "amlm_server_submit": (st, [p, p, p, p, u64, ctypes.c_int, ctypes.POINTER(u64)]),
+            "amlm_server_wait": (st, [p, u64, p, ctypes.POINTER(u64), p, p, p, u64]),
+            "amlm_server_ticket_times": (st, [p, u64, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
+            "amlm_server_destroy": (None, [p]),
+            "amlm_last_error": (ctypes.c_char_p, []),
+            "amlm_set_timing": (st, [p, ctypes.c_int]),
+            "amlm_stage_times": (st, [p, ctypes.POINTER(ctypes.c_float)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise AmlmError(status, lib().amlm_last_error().decode())
+
+
+def params(patterns=AMLM_ALL, delta=86400, L=4, k=2, schedule=AMLM_SCHED_STATIC) -> amlm_params:
+    return amlm_params(patterns, int(delta), int(L), int(k), int(schedule))
+
+
+def amlm_num_columns(p: amlm_params) -> int:
+    return int(lib().amlm_num_columns(ctypes.byref(p)))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor or host pointer of a numpy array."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return ctypes.c_void_p(x.ctypes.data)
+    return ctypes.c_void_p(int(x.data_ptr()))
+
+
+class Graph:
+    """Owns an ``amlm_graph`` handle (device graph store)."""
+
+    def __init__(self, src, dst, ts, n_vertices: int, amount=None, stream=None):
+        import torch
+        self.handle = ctypes.c_void_p()
+        on_dev = not isinstance(src, np.ndarray)
+        if on_dev:
+            src = src.contiguous(); dst = dst.contiguous(); ts = ts.contiguous()
+            assert src.dtype == torch.int32 and dst.dtype == torch.int32 and ts.dtype == torch.int64
+            n = int(src.numel())
+        else:
+            src = np.ascontiguousarray(src, dtype=np.uint32)
+            dst = np.ascontiguousarray(dst, dtype=np.uint32)
+            ts = np.ascontiguousarray(ts, dtype=np.int64)
+            n = int(src.shape[0])
+        self._keep = (src, dst, ts)
+        _check(lib().amlm_graph_create(_ptr(src), _ptr(dst), _ptr(ts), _ptr(amount), n, int(n_vertices),
+                                       1 if on_dev else 0, _stream_handle(stream), ctypes.byref(self.handle)))
+        self._keep = None
+        self.n_edges = n
+        self.n_vertices = int(n_vertices)
+
+    def info(self):
+        ne, nv_, nvert, tb = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_int64()
+        _check(lib().amlm_graph_info(self.handle, ctypes.byref(ne), ctypes.byref(nv_), ctypes.byref(nvert),
+                                     ctypes.byref(tb)))
+        return {"n_edges": ne.value, "n_valid": nv_.value, "n_vertices": nvert.value, "t_base": tb.value}
+
+    def rebuild(self, src, dst, ts, n_vertices: int, stream=None):
+        on_dev = not isinstance(src, np.ndarray)
+        n = int(src.numel()) if on_dev else int(src.shape[0])
+        if not on_dev:
+            src = np.ascontiguousarray(src, dtype=np.uint32)
+            dst = np.ascontiguousarray(dst, dtype=np.uint32)
+            ts = np.ascontiguousarray(ts, dtype=np.int64)
+        _check(lib().amlm_graph_rebuild(self.handle, _ptr(src), _ptr(dst), _ptr(ts), n, int(n_vertices),
+                                        1 if on_dev else 0, _stream_handle(stream)))
+        self.n_edges = n
+        self.n_vertices = int(n_vertices)
+
+    def close(self):
+        if self.handle:
+            lib().amlm_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def amlm_mine(g: Graph, p: amlm_params, counts=None, stream=None):
+    """Mine every edge; returns an int32 tensor [ncols, n_edges] (bit pattern
+    of the uint32 counts) on the current device."""
+    import torch
+    ncols = amlm_num_columns(p)
+    if ncols == 0:
+        _check(lib().amlm_mine(g.handle, ctypes.byref(p), None, _stream_handle(stream)))
+    if counts is None:
+        counts = torch.empty((ncols, g.n_edges), dtype=torch.int32, device="cuda")
+    assert counts.is_contiguous() and counts.numel() >= ncols * g.n_edges
+    _check(lib().amlm_mine(g.handle, ctypes.byref(p), _ptr(counts), _stream_handle(stream)))
+    return counts
+
+
+def amlm_mine_work(g: Graph, p: amlm_params, counts=None, work=None, stream=None):
+    import torch
+    ncols = amlm_num_columns(p)
+    if counts is None:
+        counts = torch.empty((ncols, g.n_edges), dtype=torch.int32, device="cuda")
+    if work is None:
+        work = torch.empty((2, g.n_edges), dtype=torch.int32, device="cuda")
+    _check(lib().amlm_mine_work(g.handle, ctypes.byref(p), _ptr(counts), _ptr(work), _stream_handle(stream)))
+    return counts, work
+
+
+STAGES = ["build", "anchor", "lists", "sg", "cyc", "model", "unused6", "unused7"]
+
+
+def amlm_set_timing(g: Graph, enable: bool = True):
+    _check(lib().amlm_set_timing(g.handle, 1 if enable else 0))
+
+
+def amlm_stage_times(g: Graph) -> dict:
+    arr = (ctypes.c_float * 8)()
+    _check(lib().amlm_stage_times(g.handle, arr))
+    return {STAGES[i]: float(arr[i]) for i in range(8) if arr[i] >= 0}
+
+
+def amlm_graph_sync(g: Graph, stream=None):
+    _check(lib().amlm_graph_sync(g.handle, _stream_handle(stream)))
+
+
+def to_u32(t) -> np.ndarray:
+    """Device int32 tensor holding uint32 bit patterns -> numpy uint32."""
+    return t.cpu().numpy().view(np.uint32)

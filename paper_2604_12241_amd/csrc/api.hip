@@ -1,0 +1,418 @@
+// C ABI: graph store lifetime and the plain mining entry points.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "api_internal.h"
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+extern "C" const char *amlm_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ helpers
+
+DeviceInfo &device_info() {
+  static DeviceInfo info;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      info.num_cu = prop.multiProcessorCount;
+      snprintf(info.name, sizeof(info.name), "%s", prop.gcnArchName);
+    }
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sg_ptr(), kSgThreads, 0) == hipSuccess && occ > 0)
+      info.sg_occ = occ;
+    occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_cyc_ptr(), kCycThreads, 0) == hipSuccess && occ > 0)
+      info.cyc_occ = occ;
+  });
+  return info;
+}
+
+static amlm_status dalloc(amlm_graph *g, void **p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    *p = nullptr;
+    return AMLM_E_NOMEM;
+  }
+  g->allocs.push_back(*p);
+  g->device_bytes += bytes;
+  return AMLM_OK;
+}
+
+#define A_TRY(x)                    \
+  do {                              \
+    amlm_status st_ = (x);          \
+    if (st_ != AMLM_OK) return st_; \
+  } while (0)
+
+static void free_all(amlm_graph *g) {
+  for (void *p : g->allocs) (void)hipFree(p);
+  g->allocs.clear();
+  g->device_bytes = 0;
+  g->cap_e = 0;
+  g->cap_v = 0;
+  g->ms = MineScratch();
+}
+
+// Allocate the graph's arrays for E edges and V vertices.
+static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
+  if (E <= g->cap_e && V <= g->cap_v && g->cap_e) return AMLM_OK;
+  free_all(g);
+  uint64_t e = std::max<uint64_t>(E, 1);
+  uint64_t v1 = (uint64_t)V + 1;
+  GraphArrays &a = g->arr;
+  A_TRY(dalloc(g, (void **)&a.src, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.dst, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.t, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.anc, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.pos_out, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.pos_in, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.out_ptr, 4 * v1));
+  A_TRY(dalloc(g, (void **)&a.out_nbr, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.out_eid, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.out_t, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.out_prv, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.in_ptr, 4 * v1));
+  A_TRY(dalloc(g, (void **)&a.in_nbr, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.in_eid, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.in_t, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.in_nxt, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.inn_key, 8 * e));
+  A_TRY(dalloc(g, (void **)&a.inn_eid, 4 * e));
+  BuildBuffers &b = g->bb;
+  A_TRY(dalloc(g, (void **)&b.ka, 4 * e));
+  A_TRY(dalloc(g, (void **)&b.kb, 4 * e));
+  A_TRY(dalloc(g, (void **)&b.va, 4 * e));
+  A_TRY(dalloc(g, (void **)&b.vb, 4 * e));
+  size_t hw = radix_hist_words(e);
+  A_TRY(dalloc(g, (void **)&b.hist, 4 * hw));
+  A_TRY(dalloc(g, (void **)&b.hist2, 4 * hw));
+  size_t tw = std::max(scan_tmp_words(hw), scan_tmp_words(v1));
+  A_TRY(dalloc(g, (void **)&b.scan_tmp, 4 * tw));
+  A_TRY(dalloc(g, (void **)&b.stats, 8 * 8));
+  A_TRY(dalloc(g, (void **)&g->err_dev, 64));
+  A_TRY(dalloc(g, (void **)&g->ts_stage, 8 * e));
+  g->cap_e = E;
+  g->cap_v = V;
+  return AMLM_OK;
+}
+
+amlm_status alloc_mine_scratch(amlm_graph *g) {
+  MineScratch &ms = g->ms;
+  uint64_t ev = std::max<uint64_t>(g->Ev, 1);
+  if (ms.flags && ms.cap_ev >= ev) return AMLM_OK;
+  if (ms.flags) {
+    // grow: the old buffers stay owned by the graph until it is freed
+  }
+  uint32_t nb = (uint32_t)((ev + kFlagTile - 1) / kFlagTile);
+  A_TRY(dalloc(g, (void **)&ms.flags, ev));
+  A_TRY(dalloc(g, (void **)&ms.list_sg, 4 * ev));
+  A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * ev));
+  A_TRY(dalloc(g, (void **)&ms.bcnt_sg, 4 * (size_t)nb));
+  A_TRY(dalloc(g, (void **)&ms.bcnt_cy, 4 * (size_t)nb));
+  A_TRY(dalloc(g, (void **)&ms.boff_sg, 4 * (size_t)nb));
+  A_TRY(dalloc(g, (void **)&ms.boff_cy, 4 * (size_t)nb));
+  A_TRY(dalloc(g, (void **)&ms.scan_tmp, 4 * scan_tmp_words(nb)));
+  A_TRY(dalloc(g, (void **)&ms.ctr, 4 * kCtrWords));
+  ms.cap_ev = ev;
+  return AMLM_OK;
+}
+
+GraphView graph_view(const amlm_graph *g) {
+  const GraphArrays &a = g->arr;
+  GraphView v;
+  v.V = g->V;
+  v.E = (uint32_t)g->E;
+  v.Ev = g->Ev;
+  v.src = a.src;
+  v.dst = a.dst;
+  v.t = a.t;
+  v.anc = a.anc;
+  v.pos_out = a.pos_out;
+  v.pos_in = a.pos_in;
+  v.out_ptr = a.out_ptr;
+  v.out_nbr = a.out_nbr;
+  v.out_eid = a.out_eid;
+  v.out_t = a.out_t;
+  v.out_prv = a.out_prv;
+  v.in_ptr = a.in_ptr;
+  v.in_nbr = a.in_nbr;
+  v.in_eid = a.in_eid;
+  v.in_t = a.in_t;
+  v.in_nxt = a.in_nxt;
+  v.inn_key = a.inn_key;
+  v.inn_eid = a.inn_eid;
+  return v;
+}
+
+// ------------------------------------------------------------------ graph
+
+static amlm_status do_build(amlm_graph *g, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                            uint64_t n_edges, uint32_t n_vertices, int on_device, hipStream_t s) {
+  if (n_edges >= 0xffffffffull) {
+    set_error("n_edges must be < 2^32 - 1");
+    return AMLM_E_INVALID;
+  }
+  if (n_edges && (!src || !dst || !ts)) {
+    set_error("null edge array");
+    return AMLM_E_INVALID;
+  }
+  A_TRY(alloc_graph(g, n_edges, n_vertices));
+  GraphArrays &a = g->arr;
+  const int64_t *ts_dev = ts;
+  if (n_edges) {
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(a.src, src, 4 * n_edges, kind, s));
+    HIP_TRY(hipMemcpyAsync(a.dst, dst, 4 * n_edges, kind, s));
+    if (!on_device) {
+      HIP_TRY(hipMemcpyAsync(g->ts_stage, ts, 8 * n_edges, kind, s));
+      ts_dev = g->ts_stage;
+    }
+  }
+  ValidateResult vr;
+  HIP_TRY(validate_edges(a.src, a.dst, ts_dev, n_edges, n_vertices, g->bb.stats, &vr, s));
+  if (vr.bad_ids) {
+    set_error(std::to_string(vr.bad_ids) + " edge endpoints are >= n_vertices");
+    return AMLM_E_INVALID;
+  }
+  uint64_t span = n_edges ? (uint64_t)(vr.tmax - vr.tmin) : 0;
+  if (n_edges && (vr.tmax < vr.tmin || span >= 0x7fffffffull)) {
+    set_error("timestamp span must be < 2^31 - 1");
+    return AMLM_E_RANGE;
+  }
+  g->E = n_edges;
+  g->V = n_vertices;
+  g->Ev = (uint32_t)(n_edges - vr.self_loops);
+  g->t_base = vr.tmin;
+  g->t_span = span;
+  int t_bits = bits_for(span);
+  HIP_TRY(g->timer.begin(kStBuild, s));
+  HIP_TRY(build_graph(a, ts_dev, vr.tmin, (uint32_t)n_edges, g->Ev, n_vertices, t_bits, vr.unsorted == 0,
+                      vr.self_loops, g->bb, s));
+  HIP_TRY(g->timer.end(kStBuild, s));
+  HIP_TRY(launch_fill_u32(g->err_dev, 0, 16, s));
+  A_TRY(alloc_mine_scratch(g));
+  HIP_TRY(hipStreamSynchronize(s));
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_graph_create(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                                         const float *amount, uint64_t n_edges, uint32_t n_vertices,
+                                         int inputs_on_device, void *hip_stream, amlm_graph **out) {
+  (void)amount;  // carried by the caller; no pattern reads it
+  if (!out) {
+    set_error("out is null");
+    return AMLM_E_INVALID;
+  }
+  *out = nullptr;
+  amlm_graph *g = new amlm_graph();
+  HIP_TRY(hipGetDevice(&g->device));
+  amlm_status st = do_build(g, src, dst, ts, n_edges, n_vertices, inputs_on_device, (hipStream_t)hip_stream);
+  if (st != AMLM_OK) {
+    free_all(g);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_graph_rebuild(amlm_graph *g, const uint32_t *src, const uint32_t *dst,
+                                          const int64_t *ts, uint64_t n_edges, uint32_t n_vertices,
+                                          int inputs_on_device, void *hip_stream) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  return do_build(g, src, dst, ts, n_edges, n_vertices, inputs_on_device, (hipStream_t)hip_stream);
+}
+
+extern "C" void amlm_graph_destroy(amlm_graph *g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  free_all(g);
+  if (g->timer.ev[0])
+    for (hipEvent_t &e : g->timer.ev) (void)hipEventDestroy(e);
+  delete g;
+}
+
+extern "C" amlm_status amlm_graph_info(const amlm_graph *g, uint64_t *n_edges, uint64_t *n_valid,
+                                       uint32_t *n_vertices, int64_t *t_base) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  if (n_edges) *n_edges = g->E;
+  if (n_valid) *n_valid = g->Ev;
+  if (n_vertices) *n_vertices = g->V;
+  if (t_base) *t_base = g->t_base;
+  return AMLM_OK;
+}
+
+// ------------------------------------------------------------------ mining
+
+amlm_status check_params(const amlm_params *p) {
+  if (!p) {
+    set_error("null params");
+    return AMLM_E_INVALID;
+  }
+  if (p->patterns == 0 || (p->patterns & ~AMLM_ALL)) {
+    set_error("patterns must be a non-empty subset of AMLM_ALL");
+    return AMLM_E_INVALID;
+  }
+  if (p->delta < 0) {
+    set_error("delta must be >= 0");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_CYCLES) && (p->max_cycle_len < 2 || p->max_cycle_len > 8)) {
+    set_error("max_cycle_len must be in 2..8");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & (AMLM_SG | AMLM_GS)) && p->k == 0) {
+    set_error("k must be >= 1");
+    return AMLM_E_INVALID;
+  }
+  if (p->schedule > AMLM_SCHED_LEARNED) {
+    set_error("unknown schedule");
+    return AMLM_E_INVALID;
+  }
+  return AMLM_OK;
+}
+
+extern "C" uint32_t amlm_num_columns(const amlm_params *p) {
+  if (check_params(p) != AMLM_OK) return 0;
+  uint32_t c = 0;
+  if (p->patterns & AMLM_FAN_OUT) c++;
+  if (p->patterns & AMLM_FAN_IN) c++;
+  if (p->patterns & AMLM_SG) c++;
+  if (p->patterns & AMLM_GS) c++;
+  if (p->patterns & AMLM_CYCLES) c += p->max_cycle_len - 1;
+  return c;
+}
+
+MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, uint32_t *work) {
+  MineParams mp;
+  mp.g = graph_view(g);
+  mp.delta = p->delta;
+  mp.L = (p->patterns & AMLM_CYCLES) ? p->max_cycle_len : 2;
+  mp.k = p->k ? p->k : 1;
+  int c = 0;
+  mp.col_fo = (p->patterns & AMLM_FAN_OUT) ? c++ : -1;
+  mp.col_fi = (p->patterns & AMLM_FAN_IN) ? c++ : -1;
+  mp.col_sg = (p->patterns & AMLM_SG) ? c++ : -1;
+  mp.col_gs = (p->patterns & AMLM_GS) ? c++ : -1;
+  mp.col_cyc = (p->patterns & AMLM_CYCLES) ? c : -1;
+  mp.counts = counts;
+  mp.stride = g->E;
+  mp.work = work;
+  mp.err = g->err_dev;
+  return mp;
+}
+
+MineLaunch default_launch(const amlm_graph *g) {
+  DeviceInfo &di = device_info();
+  MineLaunch cfg;
+  cfg.sg_blocks = (uint32_t)(di.num_cu * di.sg_occ);
+  cfg.cyc_blocks = (uint32_t)(di.num_cu * di.cyc_occ);
+  // chunk so that each wave takes ~16 grabs on average
+  uint64_t waves = (uint64_t)cfg.sg_blocks * (kSgThreads / AMLM_WAVE);
+  uint64_t ch = g->Ev / std::max<uint64_t>(waves * 64, 1);
+  cfg.sg_chunk = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ch, 1), 256);
+  if (g->tune.sg_chunk) cfg.sg_chunk = g->tune.sg_chunk;
+  if (g->tune.sg_blocks) cfg.sg_blocks = g->tune.sg_blocks;
+  if (g->tune.cyc_blocks) cfg.cyc_blocks = g->tune.cyc_blocks;
+  return cfg;
+}
+
+amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
+                        hipStream_t s) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  A_TRY(check_params(p));
+  if (g->E && !counts_dev) {
+    set_error("null counts");
+    return AMLM_E_INVALID;
+  }
+  if (g->sticky != AMLM_OK) {
+    set_error("graph has a sticky device error");
+    return g->sticky;
+  }
+  uint32_t ncols = amlm_num_columns(p);
+  HIP_TRY(launch_fill_u32(counts_dev, 0, (uint64_t)ncols * g->E, s));
+  if (work_dev) HIP_TRY(launch_fill_u32(work_dev, 0, 2 * g->E, s));
+  A_TRY(alloc_mine_scratch(g));
+  MineParams mp = make_params(g, p, counts_dev, work_dev);
+  MineLaunch cfg = default_launch(g);
+  HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, void *hip_stream) {
+  return mine_common(g, p, counts_dev, nullptr, (hipStream_t)hip_stream);
+}
+
+extern "C" amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
+                                      void *hip_stream) {
+  if (g && g->E && !work_dev) {
+    set_error("null work");
+    return AMLM_E_INVALID;
+  }
+  return mine_common(g, p, counts_dev, work_dev, (hipStream_t)hip_stream);
+}
+
+extern "C" amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, g->err_dev, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err) {
+    HIP_TRY(launch_fill_u32(g->err_dev, 0, 1, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    set_error("a cycle count exceeded 2^32 - 1");
+    return AMLM_E_RANGE;
+  }
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_set_timing(amlm_graph *g, int enable) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  if (enable && !g->timer.ev[0])
+    for (hipEvent_t &e : g->timer.ev) HIP_TRY(hipEventCreate(&e));
+  g->timer.on = enable != 0;
+  for (bool &u : g->timer.used) u = false;
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_stage_times(amlm_graph *g, float *ms) {
+  if (!g || !ms) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  for (int st = 0; st < kNumStages; st++) {
+    ms[st] = -1.0f;
+    if (!g->timer.used[st]) continue;
+    HIP_TRY(hipEventSynchronize(g->timer.ev[2 * st + 1]));
+    HIP_TRY(hipEventElapsedTime(&ms[st], g->timer.ev[2 * st], g->timer.ev[2 * st + 1]));
+  }
+  return AMLM_OK;
+}

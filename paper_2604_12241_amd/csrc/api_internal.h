@@ -1,0 +1,46 @@
+// Host-side graph handle and helpers shared by the C ABI translation units.
+#pragma once
+
+#include <vector>
+
+#include "mine.h"
+
+struct DeviceInfo {
+  int num_cu = 256;
+  int sg_occ = 4;
+  int cyc_occ = 3;
+  char name[64] = "gfx950";
+};
+DeviceInfo &device_info();
+
+struct TuneParams {
+  uint32_t sg_chunk = 0, sg_blocks = 0, cyc_blocks = 0;  // 0 = default
+};
+
+struct amlm_graph {
+  int device = 0;
+  uint64_t E = 0;
+  uint32_t V = 0, Ev = 0;
+  int64_t t_base = 0;
+  uint64_t t_span = 0;
+  uint64_t cap_e = 0;
+  uint32_t cap_v = 0;
+  GraphArrays arr{};
+  BuildBuffers bb{};
+  int64_t *ts_stage = nullptr;
+  uint32_t *err_dev = nullptr;
+  MineScratch ms{};
+  TuneParams tune{};
+  StageTimer timer{};
+  amlm_status sticky = AMLM_OK;
+  std::vector<void *> allocs;
+  uint64_t device_bytes = 0;
+};
+
+amlm_status check_params(const amlm_params *p);
+GraphView graph_view(const amlm_graph *g);
+MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, uint32_t *work);
+MineLaunch default_launch(const amlm_graph *g);
+amlm_status alloc_mine_scratch(amlm_graph *g);
+amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
+                        hipStream_t s);

@@ -1,0 +1,397 @@
+// Graph store construction on the GPU: validation, relative times, an LSD
+// radix sort of our own, and the time-sorted CSR / CSC plus the
+// neighbour-sorted in-index with same-pair time links.
+#include "internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr uint32_t kTile = kThreads * kItems;  // 4096 elements per block
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// stats[0] = min ts (biased to unsigned order), [1] = max ts (biased),
+// [2] = ids >= V, [3] = self-loops, [4] = i with ts[i] > ts[i+1]
+__global__ void k_validate(const uint32_t *src, const uint32_t *dst, const int64_t *ts, uint64_t E, uint32_t V,
+                           unsigned long long *stats) {
+  const unsigned long long bias = 0x8000000000000000ull;
+  unsigned long long mn = ~0ull, mx = 0ull, bad = 0, loops = 0, unsorted = 0;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < E; i += stride) {
+    unsigned long long b = (unsigned long long)ts[i] ^ bias;
+    mn = b < mn ? b : mn;
+    mx = b > mx ? b : mx;
+    uint32_t s = src[i], d = dst[i];
+    bad += (s >= V) | (d >= V);
+    loops += (s == d);
+    if (i + 1 < E) unsorted += ts[i] > ts[i + 1];
+  }
+  // wave reduction then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long a = __shfl_xor(mn, o, AMLM_WAVE);
+    mn = a < mn ? a : mn;
+    a = __shfl_xor(mx, o, AMLM_WAVE);
+    mx = a > mx ? a : mx;
+    bad += __shfl_xor(bad, o, AMLM_WAVE);
+    loops += __shfl_xor(loops, o, AMLM_WAVE);
+    unsorted += __shfl_xor(unsorted, o, AMLM_WAVE);
+  }
+  if (lane_id() == 0) {
+    atomicMin(&stats[0], mn);
+    atomicMax(&stats[1], mx);
+    if (bad) atomicAdd(&stats[2], bad);
+    if (loops) atomicAdd(&stats[3], loops);
+    if (unsorted) atomicAdd(&stats[4], unsorted);
+  }
+}
+
+__global__ void k_init_stats(unsigned long long *stats) {
+  if (threadIdx.x == 0) {
+    stats[0] = ~0ull;
+    stats[1] = 0;
+    stats[2] = stats[3] = stats[4] = 0;
+  }
+}
+
+// relative times, edge copies, and the first sort key:
+// key = self_loop << t_bits | t_rel, value = edge id
+__global__ void k_reltime(const int64_t *ts, int64_t tmin, const uint32_t *src, const uint32_t *dst, uint32_t E,
+                          int t_bits, int32_t *t, uint32_t *key, uint32_t *val, int with_time_key) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  int32_t tr = (int32_t)(ts[i] - tmin);
+  t[i] = tr;
+  uint32_t loop = src[i] == dst[i];
+  key[i] = with_time_key ? ((loop << t_bits) | (uint32_t)tr) : loop;
+  val[i] = i;
+}
+
+// ---------------------------------------------------------------- scan
+constexpr uint32_t kScanBlock = 2048;  // elements per block (256 threads x 8)
+
+__global__ void k_scan_block(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *block_sums) {
+  __shared__ uint32_t wsum[kThreads / AMLM_WAVE];
+  uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
+  uint32_t base = blockIdx.x * kScanBlock + tid * 8;
+  uint32_t v[8], s = 0;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    uint32_t idx = base + j;
+    v[j] = idx < n ? in[idx] : 0;
+    s += v[j];
+  }
+  uint32_t incl = wave_incl_scan(s);
+  if (lane_id() == AMLM_WAVE - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (uint32_t q = 0; q < w; q++) woff += wsum[q];
+  uint32_t run = woff + incl - s;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    uint32_t idx = base + j;
+    if (idx < n) out[idx] = run;
+    run += v[j];
+  }
+  if (tid == kThreads - 1 && block_sums) block_sums[blockIdx.x] = woff + incl;
+}
+
+__global__ void k_scan_add(uint32_t *out, uint32_t n, const uint32_t *block_offsets) {
+  uint32_t b = blockIdx.x;
+  uint32_t add = block_offsets[b];
+  uint32_t base = b * kScanBlock;
+  for (uint32_t j = threadIdx.x; j < kScanBlock; j += blockDim.x) {
+    uint32_t idx = base + j;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+__global__ void k_scan_total(const uint32_t *in, const uint32_t *out, uint32_t n, uint32_t *total) {
+  if (threadIdx.x == 0) *total = n ? out[n - 1] + in[n - 1] : 0;
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kThreads) void k_rs_hist(const uint32_t *keys, uint32_t n, int shift,
+                                                      uint32_t *hist, uint32_t nblocks) {
+  __shared__ uint32_t h[kThreads / AMLM_WAVE][256];
+  uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
+  for (int q = 0; q < kThreads / AMLM_WAVE; q++) h[q][tid] = 0;
+  __syncthreads();
+  uint32_t base = blockIdx.x * kTile;
+#pragma unroll 4
+  for (int j = 0; j < kItems; j++) {
+    uint32_t idx = base + j * kThreads + tid;
+    if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  uint32_t s = 0;
+  for (int q = 0; q < kThreads / AMLM_WAVE; q++) s += h[q][tid];
+  hist[tid * nblocks + blockIdx.x] = s;
+}
+
+// Stable scatter: ranks follow the (iteration, wave, lane) order, which is
+// the input order inside the tile.
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                                                         uint32_t *vout, uint32_t n, int shift,
+                                                         const uint32_t *offs, uint32_t nblocks) {
+  constexpr int NW = kThreads / AMLM_WAVE;
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[NW][256];
+  uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
+  run[tid] = offs[tid * nblocks + blockIdx.x];
+  for (int q = 0; q < NW; q++) wc[q][tid] = 0;
+  __syncthreads();
+  uint32_t base = blockIdx.x * kTile;
+  uint64_t lt = lanemask_lt();
+  for (int j = 0; j < kItems; j++) {
+    uint32_t idx = base + j * kThreads + tid;
+    bool valid = idx < n;
+    uint32_t key = valid ? kin[idx] : 0u;
+    uint32_t val = valid ? vin[idx] : 0u;
+    uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      uint32_t bit = (d >> b) & 1u;
+      uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    uint32_t rank = __popcll(peers & lt);
+    if (valid && rank == 0) wc[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (uint32_t q = 0; q < w; q++) pos += wc[q][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    for (int q = 0; q < NW; q++) {
+      tot += wc[q][tid];
+      wc[q][tid] = 0;
+    }
+    run[tid] += tot;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- CSR pieces
+__global__ void k_gather_key(const uint32_t *keysrc, const uint32_t *ids, uint32_t *key, uint32_t *val, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t e = ids[i];
+  key[i] = keysrc[e];
+  val[i] = e;
+}
+
+// row pointers from sorted row keys: ptr[x] = first position with key >= x
+__global__ void k_row_ptr(const uint32_t *keys, uint32_t n, uint32_t V, uint32_t *ptr) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > n) return;
+  int64_t kp = p < n ? (int64_t)keys[p] : (int64_t)V;
+  int64_t kprev = p > 0 ? (int64_t)keys[p - 1] : -1;
+  for (int64_t x = kprev + 1; x <= kp; x++) ptr[x] = p;
+}
+
+__global__ void k_fill_rows(const uint32_t *eids, const uint32_t *other, const int32_t *t, uint32_t n,
+                            uint32_t *nbr, int32_t *tt, uint32_t *pos) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint32_t e = eids[p];
+  nbr[p] = other[e];
+  tt[p] = t[e];
+  pos[e] = p;
+}
+
+__global__ void k_inn_keys(const uint32_t *eids, const uint32_t *src, const int32_t *t, uint32_t n, uint64_t *key) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  uint32_t e = eids[q];
+  key[q] = nbr_key(src[e], t[e]);
+}
+
+// same-pair time links from the (dst, src, time)-sorted index
+__global__ void k_links(const uint32_t *dkeys, const uint64_t *inn_key, const uint32_t *inn_eid, uint32_t n,
+                        const uint32_t *pos_in, const uint32_t *pos_out, int32_t *in_nxt, int32_t *out_prv) {
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  uint32_t d = dkeys[q];
+  uint64_t k = inn_key[q];
+  uint32_t s = (uint32_t)(k >> 32);
+  int32_t nxt = AMLM_INT_MAX, prv = AMLM_INT_MIN;
+  if (q + 1 < n && dkeys[q + 1] == d && (uint32_t)(inn_key[q + 1] >> 32) == s) nxt = (int32_t)(uint32_t)inn_key[q + 1];
+  if (q > 0 && dkeys[q - 1] == d && (uint32_t)(inn_key[q - 1] >> 32) == s) prv = (int32_t)(uint32_t)inn_key[q - 1];
+  uint32_t e = inn_eid[q];
+  in_nxt[pos_in[e]] = nxt;
+  out_prv[pos_out[e]] = prv;
+}
+
+inline uint32_t nblk(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+
+}  // namespace
+
+// ====================================================================== host
+
+int bits_for(uint64_t max_value) {
+  int b = 0;
+  while (b < 64 && (max_value >> b) != 0) b++;
+  return b;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t blocks = (uint32_t)std::min<uint64_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+size_t scan_tmp_words(uint64_t n) {
+  size_t w = 0;
+  while (n > kScanBlock) {
+    n = (n + kScanBlock - 1) / kScanBlock;
+    w += 2 * n + 64;
+  }
+  return w + 64;
+}
+
+static hipError_t scan_rec(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tmp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t nb = nblk(n, kScanBlock);
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kThreads), 0, s, in, out, n, (uint32_t *)nullptr);
+    return hipGetLastError();
+  }
+  uint32_t *sums = tmp, *sums_scan = tmp + nb, *rest = tmp + 2 * nb + 64;
+  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kThreads), 0, s, in, out, n, sums);
+  hipError_t e = scan_rec(sums, sums_scan, nb, rest, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kThreads), 0, s, out, n, sums_scan);
+  return hipGetLastError();
+}
+
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *total, uint32_t *tmp,
+                              hipStream_t s) {
+  hipError_t e = scan_rec(in, out, n, tmp, s);
+  if (e != hipSuccess) return e;
+  if (total) {
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, in, out, n, total);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+size_t radix_hist_words(uint64_t n) { return (size_t)256 * nblk(n ? n : 1, kTile) + 64; }
+
+hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t n, int bits,
+                            uint32_t *hist, uint32_t *hist2, uint32_t *scan_tmp, hipStream_t s,
+                            uint32_t **kout, uint32_t **vout) {
+  uint32_t *kin = ka, *vin = va, *ko = kb, *vo = vb;
+  if (n > 1) {
+    uint32_t nb = nblk(n, kTile);
+    for (int shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, kin, n, shift, hist, nb);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      e = scan_exclusive_u32(hist, hist2, 256 * nb, nullptr, scan_tmp, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, kin, vin, ko, vo, n, shift, hist2, nb);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      std::swap(kin, ko);
+      std::swap(vin, vo);
+    }
+  }
+  *kout = kin;
+  *vout = vin;
+  return hipSuccess;
+}
+
+hipError_t validate_edges(const uint32_t *src, const uint32_t *dst, const int64_t *ts, uint64_t E, uint32_t V,
+                          uint64_t *stats_dev, ValidateResult *res, hipStream_t s) {
+  unsigned long long *st = (unsigned long long *)stats_dev;
+  hipLaunchKernelGGL(k_init_stats, dim3(1), dim3(64), 0, s, st);
+  if (E) {
+    uint32_t blocks = (uint32_t)std::min<uint64_t>((E + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, src, dst, ts, E, V, st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  unsigned long long h[5];
+  e = hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  const unsigned long long bias = 0x8000000000000000ull;
+  res->tmin = E ? (int64_t)(h[0] ^ bias) : 0;
+  res->tmax = E ? (int64_t)(h[1] ^ bias) : 0;
+  res->bad_ids = h[2];
+  res->self_loops = h[3];
+  res->unsorted = h[4];
+  return hipSuccess;
+}
+
+hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, uint32_t E, uint32_t Ev, uint32_t V,
+                       int t_bits, bool time_sorted, uint64_t n_self, BuildBuffers &bb, hipStream_t s) {
+  hipError_t e;
+#define CK(x)                       \
+  do {                              \
+    e = (x);                        \
+    if (e != hipSuccess) return e;  \
+  } while (0)
+  const int vbits = bits_for(V ? V - 1 : 0);
+  // 1. relative times and the anchor order (valid edges by (time, id))
+  if (E) {
+    int with_time = time_sorted ? 0 : 1;
+    hipLaunchKernelGGL(k_reltime, dim3(nblk(E, 256)), dim3(256), 0, s, ts, tmin, a.src, a.dst, E, t_bits, a.t,
+                       bb.ka, bb.va, with_time);
+    CK(hipGetLastError());
+    int sort_bits = time_sorted ? (n_self ? 1 : 0) : t_bits + 1;
+    uint32_t *ks, *vs;
+    CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, E, sort_bits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
+    CK(hipMemcpyAsync(a.anc, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
+  }
+  // 2. CSR: stable sort of the anchor order by source
+  CK(launch_fill_u32(a.out_ptr, 0, (uint64_t)V + 1, s));
+  CK(launch_fill_u32(a.in_ptr, 0, (uint64_t)V + 1, s));
+  if (Ev) {
+    uint32_t *ks, *vs;
+    hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.src, a.anc, bb.ka, bb.va, Ev);
+    CK(hipGetLastError());
+    CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
+    hipLaunchKernelGGL(k_row_ptr, dim3(nblk((uint64_t)Ev + 1, 256)), dim3(256), 0, s, ks, Ev, V, a.out_ptr);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(a.out_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.out_eid, a.dst, a.t, Ev, a.out_nbr,
+                       a.out_t, a.pos_out);
+    CK(hipGetLastError());
+    // 3. CSC: stable sort of the anchor order by destination
+    hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.anc, bb.ka, bb.va, Ev);
+    CK(hipGetLastError());
+    CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
+    hipLaunchKernelGGL(k_row_ptr, dim3(nblk((uint64_t)Ev + 1, 256)), dim3(256), 0, s, ks, Ev, V, a.in_ptr);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(a.in_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.in_eid, a.src, a.t, Ev, a.in_nbr,
+                       a.in_t, a.pos_in);
+    CK(hipGetLastError());
+    // 4. CSC-N: stable sort of the CSR order (source, time, id) by destination
+    hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.out_eid, bb.ka, bb.va, Ev);
+    CK(hipGetLastError());
+    CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
+    CK(hipMemcpyAsync(a.inn_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_inn_keys, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.inn_eid, a.src, a.t, Ev, a.inn_key);
+    CK(hipGetLastError());
+    // 5. same-pair links (ks still holds the destination of every CSC-N entry)
+    hipLaunchKernelGGL(k_links, dim3(nblk(Ev, 256)), dim3(256), 0, s, ks, a.inn_key, a.inn_eid, Ev, a.pos_in,
+                       a.pos_out, a.in_nxt, a.out_prv);
+    CK(hipGetLastError());
+  }
+#undef CK
+  return hipSuccess;
+}

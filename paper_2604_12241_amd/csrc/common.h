@@ -1,0 +1,88 @@
+// Device-side helpers and the graph store layout shared by the build and the
+// mining kernels.  gfx950 (CDNA4): 64-lane wavefronts, 64-bit ballot masks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define AMLM_WAVE 64
+#define AMLM_INT_MAX 0x7fffffff
+#define AMLM_INT_MIN (-0x7fffffff - 1)
+
+// Device error word bits (sticky until amlm_graph_sync reads them).
+#define AMLM_ERR_OVERFLOW 1u   // a count went past 2^32 - 1
+
+// Graph store in HBM.  All positions and edge ids fit in 32 bits.
+//  * anchors: valid (non-self-loop) edge ids in (time, id) order
+//  * CSR (out): rows by source, each row sorted by (time, id); per entry the
+//    destination, the time, the edge id and the time of the previous edge of
+//    the same (source, destination) pair (AMLM_INT_MIN if none)
+//  * CSC (in): rows by destination, sorted by (time, id); per entry the
+//    source, time, edge id and the time of the next edge of the same pair
+//    (AMLM_INT_MAX if none)
+//  * CSC-N: the CSC rows re-sorted by (source, time); 64-bit keys
+//    (source << 32 | time) for binary search, and the edge ids
+struct GraphView {
+  uint32_t V;
+  uint32_t E;   // all edges, including self-loops
+  uint32_t Ev;  // non-self-loop edges
+  const uint32_t *src, *dst;
+  const int32_t *t;  // time relative to the minimum timestamp
+  const uint32_t *anc;
+  const uint32_t *pos_out, *pos_in;  // edge id -> CSR / CSC position
+  const uint32_t *out_ptr, *out_nbr, *out_eid;
+  const int32_t *out_t, *out_prv;
+  const uint32_t *in_ptr, *in_nbr, *in_eid;
+  const int32_t *in_t, *in_nxt;
+  const uint64_t *inn_key;
+  const uint32_t *inn_eid;
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+// first index in [b, e) with a[i] >= x
+__device__ __forceinline__ uint32_t lower_bound_i32(const int32_t *a, uint32_t b, uint32_t e, int32_t x) {
+  while (b < e) {
+    uint32_t m = b + ((e - b) >> 1);
+    if (a[m] < x) b = m + 1; else e = m;
+  }
+  return b;
+}
+// first index in [b, e) with a[i] > x
+__device__ __forceinline__ uint32_t upper_bound_i32(const int32_t *a, uint32_t b, uint32_t e, int32_t x) {
+  while (b < e) {
+    uint32_t m = b + ((e - b) >> 1);
+    if (a[m] <= x) b = m + 1; else e = m;
+  }
+  return b;
+}
+// first index in [b, e) with a[i] >= x
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t *a, uint32_t b, uint32_t e, uint64_t x) {
+  while (b < e) {
+    uint32_t m = b + ((e - b) >> 1);
+    if (a[m] < x) b = m + 1; else e = m;
+  }
+  return b;
+}
+
+__device__ __forceinline__ uint64_t nbr_key(uint32_t nbr, int32_t t) {
+  return ((uint64_t)nbr << 32) | (uint32_t)t;
+}
+
+// Wave-wide inclusive scan of a 32-bit value (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < AMLM_WAVE; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, AMLM_WAVE);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// Saturation-checked credit: adds inc to *p and flags an overflow.
+__device__ __forceinline__ void credit(uint32_t *p, uint32_t inc, uint32_t *err) {
+  uint32_t old = atomicAdd(p, inc);
+  if (old + inc < old) atomicOr(err, AMLM_ERR_OVERFLOW);
+}

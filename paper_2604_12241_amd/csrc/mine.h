@@ -1,0 +1,81 @@
+// Mining launch interface shared by the C ABI, batching and serving code.
+#pragma once
+
+#include "internal.h"
+
+constexpr uint8_t kFlagSG = 1, kFlagCYC = 2;
+// senders-window slices up to this length are classified by the anchor lane
+constexpr uint32_t kAnchorScanCap = 16;
+
+constexpr int kSgThreads = 256;
+constexpr int kBloomLog2Max = 16;                       // 64 Kbit filter
+constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
+constexpr uint32_t kBloomBitsPerEntry = 16;             // ~1.4% false positives
+
+constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
+constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
+
+constexpr uint32_t kFlagThreads = 256, kFlagItems = 16, kFlagTile = kFlagThreads * kFlagItems;
+
+// device counter words
+constexpr uint32_t kCtrSgWork = 0;
+constexpr uint32_t kCtrCycWork = 1;
+constexpr uint32_t kCtrNSg = 32, kCtrNCy = 33;
+constexpr uint32_t kCtrWords = 64;
+
+struct MineParams {
+  GraphView g;
+  int64_t delta;
+  uint32_t L, k;
+  int col_fo, col_fi, col_sg, col_gs, col_cyc;  // -1 when not requested
+  uint32_t *counts;
+  uint64_t stride;   // row stride of counts (= number of edges)
+  uint32_t *work;    // optional per-edge algorithmic bytes: [0, E) scatter-gather
+                     // stage, [E, 2E) cycle stage
+  uint32_t *err;     // device error word
+};
+
+struct MineScratch {
+  uint8_t *flags = nullptr;
+  uint32_t *list_sg = nullptr, *list_cy = nullptr;
+  uint32_t *bcnt_sg = nullptr, *bcnt_cy = nullptr, *boff_sg = nullptr, *boff_cy = nullptr;
+  uint32_t *scan_tmp = nullptr;
+  uint32_t *ctr = nullptr;
+  uint64_t cap_ev = 0;
+};
+
+struct MineLaunch {
+  uint32_t sg_blocks, sg_chunk, cyc_blocks;
+};
+
+// Optional HIP-event timing of the stages (recorded on the mining stream).
+enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kNumStages = 8 };
+struct StageTimer {
+  bool on = false;
+  hipEvent_t ev[2 * kNumStages] = {};
+  bool used[kNumStages] = {};
+  hipError_t begin(int st, hipStream_t s) { return on ? hipEventRecord(ev[2 * st], s) : hipSuccess; }
+  hipError_t end(int st, hipStream_t s) {
+    if (!on) return hipSuccess;
+    used[st] = true;
+    return hipEventRecord(ev[2 * st + 1], s);
+  }
+};
+
+hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &cfg, hipStream_t s,
+                       StageTimer *tm = nullptr);
+
+// kernel handles for occupancy queries
+const void *k_sg_ptr();
+const void *k_cyc_ptr();
+
+// Algorithmic bytes per unit of work (what each stage must read, at the
+// width of the fields it needs), used for the work counters and the roofline:
+constexpr uint32_t kBytesAnchorSg = 16;      // anchor (edge id, u, v, t)
+constexpr uint32_t kBytesSenderEntry = 12;   // in-window of u: neighbour, next-same-pair time, time
+constexpr uint32_t kBytesGatherEntry = 4;    // in-window of v: neighbour id
+constexpr uint32_t kBytesJoinEntry = 4;      // out-window of a sender: neighbour id
+constexpr uint32_t kBytesScatterEntry = 4;   // out-window of u after tau: previous-same-pair time
+constexpr uint32_t kBytesPathNode = 16;      // a partial path (head, time, edge, parent)
+constexpr uint32_t kBytesPathEntry = 12;     // out-slice entry of a path head: neighbour, time, edge id
+constexpr uint32_t kBytesClosureSearch = 16; // closing-edge binary search result

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact.
+
+Every count is an integer, so every comparison is exact equality.  Small
+graphs are compared on every edge; the full-size workloads are compared on
+sampled edges that the oracle computes one by one (cycle columns by an
+independent through-edge enumeration).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_12241_amd as A
+from paper_2604_12241_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def gpu_mine(g, delta, L, k, patterns=A.AMLM_ALL, schedule=A.AMLM_SCHED_STATIC, on_device=False):
+    if on_device:
+        src = torch.from_numpy(g.src.view(np.int32)).cuda()
+        dst = torch.from_numpy(g.dst.view(np.int32)).cuda()
+        ts = torch.from_numpy(g.ts).cuda()
+        G = A.Graph(src, dst, ts, g.n_vertices)
+    else:
+        G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    p = A.params(patterns, delta, L, k, schedule)
+    c = A.amlm_mine(G, p)
+    A.amlm_graph_sync(G)
+    out = A.to_u32(c)
+    G.close()
+    return out
+
+
+def oracle_mine(g, delta, L, k, patterns=oracle.ALL):
+    return oracle.mine(g.src, g.dst, g.ts, g.n_vertices, patterns, delta, L, k)
+
+
+def assert_same(gpu, ref, what=""):
+    if not np.array_equal(gpu, ref):
+        bad = np.argwhere(gpu != ref)
+        c, i = bad[0]
+        raise AssertionError(f"{what}: {bad.shape[0]} mismatches, first col {c} edge {i}: "
+                             f"gpu {gpu[c, i]} oracle {ref[c, i]}")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_dense(seed):
+    rng = np.random.default_rng(500 + seed)
+    g = W.random_small(seed, n_edges=int(rng.integers(30, 400)), n_vertices=int(rng.integers(3, 20)),
+                       t_range=int(rng.integers(5, 80)))
+    for (delta, L, k) in [(int(rng.integers(0, 60)), int(rng.integers(2, 9)), int(rng.integers(1, 5))),
+                          (30, 5, 2), (1000, 8, 1)]:
+        assert_same(gpu_mine(g, delta, L, k), oracle_mine(g, delta, L, k), f"seed {seed} d{delta} L{L} k{k}")
+
+
+def test_tiny_workload_and_permutation():
+    g = W.tiny(101)
+    ref = oracle_mine(g, 86400, 4, 3)
+    assert_same(gpu_mine(g, 86400, 4, 3), ref, "tiny")
+    gp, perm = W.permute(g, 5)
+    assert_same(gpu_mine(gp, 86400, 4, 3, on_device=True), ref[:, perm], "tiny permuted")
+
+
+@pytest.mark.parametrize("scale,L,k", [(0.02, 6, 2), (0.01, 8, 1), (0.01, 3, 4)])
+def test_mid_scaled_full(scale, L, k):
+    g = W.mid(202, scale=scale)
+    assert_same(gpu_mine(g, 86400, L, k), oracle_mine(g, 86400, L, k), f"mid scale {scale}")
+
+
+def test_pattern_subsets():
+    g = W.mid(203, scale=0.005)
+    full = oracle_mine(g, 86400, 5, 2)
+    cols = {A.AMLM_FAN_OUT: [0], A.AMLM_FAN_IN: [1], A.AMLM_SG: [2], A.AMLM_GS: [3],
+            A.AMLM_CYCLES: [4, 5, 6, 7]}
+    for pat in [A.AMLM_FAN_OUT, A.AMLM_GS, A.AMLM_SG | A.AMLM_CYCLES, A.AMLM_FAN_IN | A.AMLM_GS]:
+        want = sorted(c for b, cs in cols.items() if pat & b for c in cs)
+        assert_same(gpu_mine(g, 86400, 5, 2, patterns=pat), full[want], f"patterns {pat}")
+
+
+def test_edge_cases():
+    T0 = W.T0
+    # empty graph
+    e = W.EdgeList(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.int64),
+                   np.zeros(0, np.float32), 5)
+    assert gpu_mine(e, 10, 4, 2).shape == (7, 0)
+    # only self-loops
+    s = W.EdgeList(np.array([1, 2, 2], np.uint32), np.array([1, 2, 2], np.uint32),
+                   np.array([T0, T0, T0 + 1], np.int64), np.zeros(3, np.float32), 3)
+    assert gpu_mine(s, 10, 4, 2).sum() == 0
+    # single edge, one vertex pair
+    one = W.EdgeList(np.array([0], np.uint32), np.array([1], np.uint32), np.array([T0], np.int64),
+                     np.zeros(1, np.float32), 2)
+    assert_same(gpu_mine(one, 0, 2, 1), oracle_mine(one, 0, 2, 1), "single")
+    # zero window, equal timestamps everywhere, many parallel edges
+    rng = np.random.default_rng(4)
+    par = W.EdgeList(rng.integers(0, 3, 300).astype(np.uint32), rng.integers(0, 3, 300).astype(np.uint32),
+                     np.full(300, T0, np.int64), np.zeros(300, np.float32), 3)
+    for d in (0, 5):
+        assert_same(gpu_mine(par, d, 6, 2), oracle_mine(par, d, 6, 2), f"ties d{d}")
+    # timestamps spanning almost the whole int32 range of relative time
+    big = W.random_small(9, n_edges=200, n_vertices=6, t_range=20)
+    big.ts[::7] += 2**31 - 100
+    assert_same(gpu_mine(big, 2**31, 5, 2), oracle_mine(big, 2**31, 5, 2), "large span")
+    assert_same(gpu_mine(big, 10, 5, 2), oracle_mine(big, 10, 5, 2), "large span, small window")
+
+
+def test_errors():
+    T0 = W.T0
+    with pytest.raises(A.AmlmError) as ei:
+        A.Graph(np.array([0, 5], np.uint32), np.array([1, 0], np.uint32), np.array([T0, T0], np.int64), 3)
+    assert ei.value.status == 1
+    with pytest.raises(A.AmlmError) as ei:
+        A.Graph(np.array([0, 1], np.uint32), np.array([1, 0], np.uint32), np.array([0, 2**31], np.int64), 3)
+    assert ei.value.status == 2
+    G = A.Graph(np.array([0, 1], np.uint32), np.array([1, 0], np.uint32), np.array([T0, T0 + 1], np.int64), 2)
+    for bad in (A.params(L=1), A.params(L=9), A.params(k=0), A.params(delta=-5), A.params(patterns=0)):
+        with pytest.raises(A.AmlmError) as ei:
+            A.amlm_mine(G, bad, counts=torch.zeros((9, 2), dtype=torch.int32, device="cuda"))
+        assert ei.value.status == 1
+    G.close()
+
+
+def test_hub_heavy_cycles_spill():
+    """A hub with thousands of window out-edges and dense returns forces the
+    cycle search past its LDS pool, through the spill rounds."""
+    rng = np.random.default_rng(11)
+    n = 6000
+    nv = 40
+    src = rng.integers(0, nv, n).astype(np.uint32)
+    dst = rng.integers(0, nv, n).astype(np.uint32)
+    ts = W.T0 + rng.integers(0, 4000, n).astype(np.int64)
+    g = W.EdgeList(src, dst, ts, np.zeros(n, np.float32), nv)
+    assert_same(gpu_mine(g, 400, 5, 3), oracle_mine(g, 400, 5, 3), "dense spill")
+
+
+def test_deterministic_repeat():
+    g = W.mid(204, scale=0.01)
+    a = gpu_mine(g, 86400, 6, 2)
+    b = gpu_mine(g, 86400, 6, 2)
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def mid_full():
+    return W.mid(202)
+
+
+def _sampled(g, counts, delta, L, k, n_sample=400, seed=0):
+    rng = np.random.default_rng(seed)
+    sel = rng.choice(g.n_edges, n_sample, replace=False)
+    # add the heaviest anchors by fan-in / fan-out too
+    sel = np.unique(np.concatenate([sel, np.argsort(counts[0])[-20:], np.argsort(counts[1])[-20:],
+                                    np.argsort(counts[2])[-20:], np.nonzero(counts[4:].sum(axis=0))[0][:50]]))
+    ref = oracle.mine_selected(g.src, g.dst, g.ts, g.n_vertices, sel, oracle.ALL, delta, L, k)
+    assert_same(counts[:, sel], ref, "sampled")
+    return sel
+
+
+def test_mid_full_size_sampled(mid_full):
+    g = mid_full
+    c = gpu_mine(g, 86400, 6, 2)
+    _sampled(g, c, 86400, 6, 2)
+    # cycle identity over the whole graph: sum_e CYC_l(e) = l * C_l
+    cf = oracle.count_cycles_first(g.src, g.dst, g.ts, g.n_vertices, 86400, 6)
+    for l in range(2, 7):
+        assert int(c[4 + l - 2].astype(np.uint64).sum()) == l * int(cf[l])
