@@ -42,6 +42,22 @@ def make_workload(name):
     return g, delta, L, k
 
 
+def train_cost_model(delta, L, k, n_graphs=4):
+    """Cost model trained (untimed) on graphs of the 5M-edge generator
+    (seeds 202..), labels from the plain miner's work counters."""
+    import paper_2604_12241_amd as A
+    from paper_2604_12241_amd import workloads as W
+    t0 = time.time()
+    Gs = []
+    for i in range(n_graphs):
+        g = W.mid(202 + i)
+        Gs.append(A.Graph(g.src, g.dst, g.ts, g.n_vertices))
+    A.amlm_costmodel_train(Gs, [A.params(A.AMLM_ALL, delta, L, k)] * n_graphs, epochs=4, batch=4096, seed=1)
+    for G in Gs:
+        G.close()
+    log(f"[bench] cost model trained on {n_graphs} graphs of 5M edges in {time.time() - t0:.1f}s")
+
+
 def cpu_baseline(g, delta, L, k, target_s=12.0):
     """The oracle (single thread) on a bounded, contiguous range of anchors in
     the middle of the graph (time order); its one-off graph set-up is not
@@ -63,7 +79,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
-    ap.add_argument("--schedule", default="static", choices=["static", "learned"])
+    ap.add_argument("--schedule", default="learned", choices=["static", "learned"])
+    ap.add_argument("--train-graphs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -82,7 +99,10 @@ def main():
     ts = torch.from_numpy(g.ts).to(dev)
     stream = torch.cuda.current_stream()
     sched = A.AMLM_SCHED_LEARNED if args.schedule == "learned" else A.AMLM_SCHED_STATIC
+    if sched == A.AMLM_SCHED_LEARNED:
+        train_cost_model(delta, L, k, args.train_graphs)
     p = A.params(A.AMLM_ALL, delta, L, k, sched)
+    p_static = A.params(A.AMLM_ALL, delta, L, k, A.AMLM_SCHED_STATIC)
     G = A.Graph(src, dst, ts, g.n_vertices)
     E = g.n_edges
     counts = torch.empty((A.amlm_num_columns(p), E), dtype=torch.int32, device=dev)
@@ -93,28 +113,40 @@ def main():
     wk = work.cpu().numpy().view(np.uint32).astype(np.uint64)
     bytes_sg, bytes_cyc = int(wk[0].sum()), int(wk[1].sum())
 
-    def step():
+    def step(pp=p):
         G.rebuild(src, dst, ts, g.n_vertices)
-        A.amlm_mine(G, p, counts)
+        A.amlm_mine(G, pp, counts)
+
+    def timed(pp, steps):
+        A.amlm_set_timing(G, True)
+        stage_ms = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(pp)
+            for kname, v in A.amlm_stage_times(G).items():
+                stage_ms.setdefault(kname, []).append(v)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        A.amlm_set_timing(G, False)
+        A.amlm_graph_sync(G)
+        return (t1 - t0) / steps, {kname: float(np.mean(v)) for kname, v in stage_ms.items()}
 
     for _ in range(args.warmup):
         step()
     A.amlm_graph_sync(G)
-    A.amlm_set_timing(G, True)
-    stage_ms = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-        for kname, v in A.amlm_stage_times(G).items():
-            stage_ms.setdefault(kname, []).append(v)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    A.amlm_set_timing(G, False)
-    A.amlm_graph_sync(G)
-    dt = (t1 - t0) / args.steps
-    avg = {kname: float(np.mean(v)) for kname, v in stage_ms.items()}
+    dt, avg = timed(p, args.steps)
     mine_ms = sum(avg.get(s, 0.0) for s in ("anchor", "lists", "sg", "cyc", "model"))
+    static = None
+    if sched == A.AMLM_SCHED_LEARNED:
+        # the static schedule on the same graph and clock, for the comparison
+        check = counts.clone()
+        step(p_static)
+        A.amlm_graph_sync(G)
+        same = bool(torch.equal(check, counts))
+        dts, avgs = timed(p_static, args.steps)
+        static = {"value": E / dts, "ms_per_step": dts * 1e3, "stage_ms": avgs,
+                  "counts_identical_to_learned": same}
 
     # dominant kernel and its roofline
     cand = {"sg": bytes_sg, "cyc": bytes_cyc}
@@ -135,6 +167,9 @@ def main():
         "stage_ms": avg,
         "roofline": roof,
     }
+    if static is not None:
+        out["static_schedule"] = static
+        out["learned_over_static"] = (E / dt) / static["value"]
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, delta, L, k)

@@ -182,8 +182,23 @@ amlm_status amlm_mine_batch(amlm_graph *const *gs, const amlm_params *ps, uint32
 amlm_status amlm_costmodel_train(amlm_graph *const *train_graphs, const amlm_params *ps, uint32_t n,
                                  uint32_t epochs, uint32_t batch, uint64_t seed,
                                  const char *out_path, void *hip_stream);
+/* Load / save the process-wide model (weights, input mean and 1/std). */
 amlm_status amlm_costmodel_load(const char *path);
 amlm_status amlm_costmodel_save(const char *path);
+/* Copy the loaded model out: weights[5057] (FP32 master values, flat layout
+ * W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3), mean[12], inv_std[12].
+ * Any pointer may be NULL. */
+amlm_status amlm_costmodel_get(float *weights, float *mean, float *inv_std);
+
+/* Network primitives on host arrays (copied to and from the device).  The
+ * weights are rounded to BF16 (nearest even) before use; arithmetic is FP32.
+ * amlm_mlp_forward: y[i] = f(x[i]) for standardised inputs x[n][12].
+ * amlm_mlp_grad: gradient of mean_i (f(x[i]) - y[i])^2 with respect to the
+ * 5057 parameters, accumulated over samples in a fixed order (deterministic);
+ * *loss (may be NULL) receives the mean squared error. */
+amlm_status amlm_mlp_forward(const float *weights, const float *x, uint32_t n, float *y);
+amlm_status amlm_mlp_grad(const float *weights, const float *x, const float *y, uint32_t n, float *grad,
+                          float *loss);
 
 /* ---- streaming server (continuous batching) ---- */
 

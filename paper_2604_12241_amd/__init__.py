@@ -28,6 +28,7 @@ EXPORTS = [
     "amlm_costmodel_train", "amlm_costmodel_load", "amlm_costmodel_save",
     "amlm_server_create", "amlm_server_submit", "amlm_server_wait", "amlm_server_ticket_times",
     "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
+    "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
 ]
 
 
@@ -78,6 +79,9 @@ def lib():
             "amlm_server_destroy": (None, [p]),
             "amlm_last_error": (ctypes.c_char_p, []),
             "amlm_set_timing": (st, [p, ctypes.c_int]),
+            "amlm_costmodel_get": (st, [p, p, p]),
+            "amlm_mlp_forward": (st, [p, p, u32, p]),
+            "amlm_mlp_grad": (st, [p, p, p, u32, p, p]),
             "amlm_stage_times": (st, [p, ctypes.POINTER(ctypes.c_float)]),
         }
         for name, (res, args) in sig.items():
@@ -210,6 +214,52 @@ def amlm_stage_times(g: Graph) -> dict:
 
 def amlm_graph_sync(g: Graph, stream=None):
     _check(lib().amlm_graph_sync(g.handle, _stream_handle(stream)))
+
+
+MLP_PARAMS = 5057
+MLP_F = 12
+
+
+def amlm_costmodel_train(graphs, ps, epochs=0, batch=0, seed=1, out_path=None, stream=None):
+    n = len(graphs)
+    arr = (ctypes.c_void_p * n)(*[g.handle.value for g in graphs])
+    pa = (amlm_params * n)(*ps)
+    _check(lib().amlm_costmodel_train(arr, pa, n, epochs, batch, seed,
+                                      out_path.encode() if out_path else None, _stream_handle(stream)))
+
+
+def amlm_costmodel_load(path: str):
+    _check(lib().amlm_costmodel_load(path.encode()))
+
+
+def amlm_costmodel_save(path: str):
+    _check(lib().amlm_costmodel_save(path.encode()))
+
+
+def amlm_costmodel_get():
+    w = np.zeros(MLP_PARAMS, np.float32)
+    m = np.zeros(MLP_F, np.float32)
+    s = np.zeros(MLP_F, np.float32)
+    _check(lib().amlm_costmodel_get(_ptr(w), _ptr(m), _ptr(s)))
+    return w, m, s
+
+
+def amlm_mlp_forward(w, x):
+    w = np.ascontiguousarray(w, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.zeros(x.shape[0], np.float32)
+    _check(lib().amlm_mlp_forward(_ptr(w), _ptr(x), x.shape[0], _ptr(y)))
+    return y
+
+
+def amlm_mlp_grad(w, x, y):
+    w = np.ascontiguousarray(w, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = ctypes.c_float()
+    _check(lib().amlm_mlp_grad(_ptr(w), _ptr(x), _ptr(y), x.shape[0], _ptr(g), ctypes.byref(loss)))
+    return g, loss.value
 
 
 def to_u32(t) -> np.ndarray:

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "api_internal.h"
+#include "costmodel.h"
 
 static thread_local std::string g_last_error;
 
@@ -88,6 +89,7 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&a.in_eid, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_t, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_nxt, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.in_dst, 4 * e));
   A_TRY(dalloc(g, (void **)&a.inn_key, 8 * e));
   A_TRY(dalloc(g, (void **)&a.inn_eid, 4 * e));
   BuildBuffers &b = g->bb;
@@ -116,7 +118,10 @@ amlm_status alloc_mine_scratch(amlm_graph *g) {
     // grow: the old buffers stay owned by the graph until it is freed
   }
   uint32_t nb = (uint32_t)((ev + kFlagTile - 1) / kFlagTile);
-  A_TRY(dalloc(g, (void **)&ms.flags, ev));
+  A_TRY(dalloc(g, (void **)&ms.flags, 2 * ((ev + 3) & ~3ull)));
+  A_TRY(dalloc(g, (void **)&ms.sg_win, 16 * ev));
+  A_TRY(dalloc(g, (void **)&ms.feat, 4 * kMlpRaw * ev));
+  A_TRY(dalloc(g, (void **)&ms.pred, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.list_sg, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.bcnt_sg, 4 * (size_t)nb));
@@ -151,6 +156,7 @@ GraphView graph_view(const amlm_graph *g) {
   v.in_eid = a.in_eid;
   v.in_t = a.in_t;
   v.in_nxt = a.in_nxt;
+  v.in_dst = a.in_dst;
   v.inn_key = a.inn_key;
   v.inn_eid = a.inn_eid;
   return v;
@@ -325,10 +331,7 @@ MineLaunch default_launch(const amlm_graph *g) {
   MineLaunch cfg;
   cfg.sg_blocks = (uint32_t)(di.num_cu * di.sg_occ);
   cfg.cyc_blocks = (uint32_t)(di.num_cu * di.cyc_occ);
-  // chunk so that each wave takes ~16 grabs on average
-  uint64_t waves = (uint64_t)cfg.sg_blocks * (kSgThreads / AMLM_WAVE);
-  uint64_t ch = g->Ev / std::max<uint64_t>(waves * 64, 1);
-  cfg.sg_chunk = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(ch, 1), 256);
+  cfg.sg_chunk = AMLM_WAVE;  // anchors per work-stealing grab (<= 64)
   if (g->tune.sg_chunk) cfg.sg_chunk = g->tune.sg_chunk;
   if (g->tune.sg_blocks) cfg.sg_blocks = g->tune.sg_blocks;
   if (g->tune.cyc_blocks) cfg.cyc_blocks = g->tune.cyc_blocks;
@@ -356,6 +359,15 @@ amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_de
   A_TRY(alloc_mine_scratch(g));
   MineParams mp = make_params(g, p, counts_dev, work_dev);
   MineLaunch cfg = default_launch(g);
+  if (p->schedule == AMLM_SCHED_LEARNED) {
+    if (!global_model().loaded) {
+      set_error("the learned schedule needs a cost model (amlm_costmodel_train or _load)");
+      return AMLM_E_INVALID;
+    }
+    cfg.learned = true;
+    cfg.delta_hours = (float)p->delta / 3600.f;
+    cfg.bb = &g->bb;
+  }
   HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
   return AMLM_OK;
 }

@@ -32,7 +32,7 @@ struct GraphView {
   const uint32_t *pos_out, *pos_in;  // edge id -> CSR / CSC position
   const uint32_t *out_ptr, *out_nbr, *out_eid;
   const int32_t *out_t, *out_prv;
-  const uint32_t *in_ptr, *in_nbr, *in_eid;
+  const uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;  // in_dst: row (destination) of each entry
   const int32_t *in_t, *in_nxt;
   const uint64_t *inn_key;
   const uint32_t *inn_eid;
@@ -64,6 +64,73 @@ __device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t *a, uint32_t 
     if (a[m] < x) b = m + 1; else e = m;
   }
   return b;
+}
+
+// Galloping searches from a known position.  gallop_lower_left: first index
+// in [b, p] with a[i] >= x, given a[p] >= x.  gallop_lower_right: first index
+// in [p, e) with a[i] >= x (e if none), given that every a[i] before p is < x.
+__device__ __forceinline__ uint32_t gallop_lower_left(const int32_t *a, uint32_t b, uint32_t p, int32_t x) {
+  uint32_t hi = p, step = 1;
+  while (hi > b) {
+    uint32_t probe = hi - b > step ? hi - step : b;
+    if (a[probe] < x) return lower_bound_i32(a, probe + 1, hi, x);
+    hi = probe;
+    step <<= 1;
+  }
+  return b;
+}
+__device__ __forceinline__ uint32_t gallop_lower_right(const int32_t *a, uint32_t p, uint32_t e, int32_t x) {
+  uint32_t lo = p, step = 1;
+  while (lo < e) {
+    uint32_t probe = e - lo > step ? lo + step - 1 : e - 1;
+    if (a[probe] >= x) return lower_bound_i32(a, lo, probe, x);
+    lo = probe + 1;
+    step <<= 1;
+  }
+  return e;
+}
+
+// First index in [b, e) with a[i] > key, for sorted 64-bit keys.
+// Interpolation steps (on the key values) alternate with bisection steps, so
+// the search takes at most about twice the steps of a binary search and a
+// few steps when the keys are spread evenly; the last <= 8 entries are
+// compared with independent loads.
+__device__ __forceinline__ uint32_t upper_bound_u64_interp(const uint64_t *a, uint32_t b, uint32_t e, uint64_t key) {
+  if (b >= e) return b;
+  uint32_t lo = b, hi = e;  // answer in [lo, hi]
+  uint64_t klo = a[b], khi = a[e - 1];
+  if (key < klo) return b;
+  if (key >= khi) return e;
+  // here a[lo] <= key < a[hi - 1]; klo = a[lo], khi = a[hi - 1]
+  bool interp = true;
+  while (hi - lo > 8) {
+    uint32_t mid;
+    if (interp && khi > klo) {
+      double frac = (double)(key - klo) / (double)(khi - klo);
+      mid = lo + (uint32_t)(frac * (double)(hi - 1 - lo));
+      if (mid <= lo) mid = lo + 1;
+      if (mid >= hi - 1) mid = hi - 2;
+    } else {
+      mid = lo + ((hi - lo) >> 1);
+    }
+    interp = !interp;
+    uint64_t km = a[mid];
+    if (km <= key) {
+      lo = mid;
+      klo = km;
+    } else {
+      hi = mid + 1;
+      khi = km;
+    }
+  }
+  // answer = first i in (lo, hi) with a[i] > key (a[hi - 1] > key holds)
+  uint32_t ans = hi - 1;
+#pragma unroll
+  for (int j = 8; j >= 1; j--) {
+    uint32_t i = lo + (uint32_t)j;
+    if (i < hi - 1 && a[i] > key) ans = i;
+  }
+  return ans;
 }
 
 __device__ __forceinline__ uint64_t nbr_key(uint32_t nbr, int32_t t) {

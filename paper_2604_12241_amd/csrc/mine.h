@@ -7,10 +7,12 @@ constexpr uint8_t kFlagSG = 1, kFlagCYC = 2;
 // senders-window slices up to this length are classified by the anchor lane
 constexpr uint32_t kAnchorScanCap = 16;
 
-constexpr int kSgThreads = 256;
+constexpr int kSgThreads = 64;   // one wave per block
 constexpr int kBloomLog2Max = 16;                       // 64 Kbit filter
 constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
-constexpr uint32_t kBloomBitsPerEntry = 16;             // ~1.4% false positives
+constexpr uint32_t kBloomBitsPerEntry = 16;             // blocked, 3 bits per key: ~1% false positives
+constexpr int kJoinUnroll = 8;
+constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
 constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
@@ -36,7 +38,12 @@ struct MineParams {
 };
 
 struct MineScratch {
-  uint8_t *flags = nullptr;
+  uint8_t *flags = nullptr;   // [0, Ev): scatter-gather flag per CSC position;
+                              // then the cycle flag per time-order position
+  uint4 *sg_win = nullptr;    // per CSC position: senders window [p0, p1) in u's
+                              // in-row and v's in-window [r0, r1)
+  uint32_t *feat = nullptr;   // per CSC position: raw cost-model features [8]
+  float *pred = nullptr;      // per list item: predicted log-work
   uint32_t *list_sg = nullptr, *list_cy = nullptr;
   uint32_t *bcnt_sg = nullptr, *bcnt_cy = nullptr, *boff_sg = nullptr, *boff_cy = nullptr;
   uint32_t *scan_tmp = nullptr;
@@ -46,7 +53,13 @@ struct MineScratch {
 
 struct MineLaunch {
   uint32_t sg_blocks, sg_chunk, cyc_blocks;
+  bool learned = false;         // schedule scatter-gather chunks by the cost model
+  uint32_t learned_chunk = 16;  // anchors per chunk in the learned schedule
+  float delta_hours = 24.f;
+  BuildBuffers *bb = nullptr;   // sort buffers reused by the learned schedule
 };
+constexpr uint32_t kChunkKeyInvalid = 0x1ffffu;
+constexpr int kChunkKeyBits = 17;
 
 // Optional HIP-event timing of the stages (recorded on the mining stream).
 enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kNumStages = 8 };

@@ -4,13 +4,16 @@
 //            (Find_Starting_Edge, Algorithm 1), FAN_OUT / FAN_IN, the size of
 //            the sender set S(e) when its window slice is short, and the
 //            classification of the anchor into the scatter-gather and cycle
-//            work lists.
-//  k_sg      one wave per scatter-gather anchor (Section 5 scatter-gather
-//            decomposition, Section 6 compiled example): the wave scans the
-//            anchor's sender window, stages v's in-window in an LDS Bloom
-//            filter, then scans every sender's out-window, lanes flattened
-//            over (sender, entry) pairs; filter hits are confirmed by binary
-//            search in the neighbour-sorted in-index.  Also gather-scatter.
+//            work lists (kept in CSC order: grouped by v, time-sorted).
+//  k_sg      scatter-gather / gather-scatter (Section 5 scatter-gather
+//            decomposition, Section 6 compiled example).  A wave takes up to
+//            64 anchors; each run of anchors into the same v is a segment
+//            whose gather side (v's in-neighbours over the segment's window)
+//            is staged once in an LDS Bloom filter.  Senders are found lane-
+//            parallel over the anchors' sender windows; each sender's
+//            out-window is scanned with lanes flattened over (sender, entry)
+//            pairs; filter hits are queued and confirmed in batches by binary
+//            search in the neighbour-sorted in-index.
 //  k_cyc     bounded time-respecting cycle search (Section 5 cycle
 //            decomposition; Section 6 4-cycle example: expansion, then the
 //            closing intersection by binary search over sorted neighbour
@@ -18,6 +21,7 @@
 //            frames of up to 64 partial paths; each frame's time slices are
 //            flattened over the lanes and the surviving paths are compacted
 //            into the next frame with ballot + popcount.
+#include "costmodel.h"
 #include "mine.h"
 
 namespace {
@@ -31,7 +35,8 @@ __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_re
 __device__ __forceinline__ int32_t rfl(int32_t x) { return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x); }
 
 // ------------------------------------------------------------------ k_anchor
-__global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags) {
+__global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags_sg, uint8_t *flags_cy,
+                                                 uint4 *sg_win, uint32_t *feat) {
   const GraphView &g = mp.g;
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.Ev) return;
@@ -40,22 +45,28 @@ __global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags) {
   int32_t t = g.t[eid];
   int32_t lo = window_lo(t, mp.delta);
   uint8_t f = 0;
-  if (mp.col_fo >= 0) {
+  uint32_t fan_out = 0;
+  if (mp.col_fo >= 0 || feat) {
     uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1], pu = g.pos_out[eid];
     uint32_t hi = upper_bound_i32(g.out_t, pu + 1, re, t);
     uint32_t lb = lower_bound_i32(g.out_t, rs, pu, lo);
-    mp.counts[(uint64_t)mp.col_fo * mp.stride + eid] = hi - lb;
+    fan_out = hi - lb;
+    if (mp.col_fo >= 0) mp.counts[(uint64_t)mp.col_fo * mp.stride + eid] = fan_out;
   }
-  if (mp.col_fi >= 0) {
-    uint32_t rs = g.in_ptr[v], re = g.in_ptr[v + 1], pv = g.pos_in[eid];
-    uint32_t hi = upper_bound_i32(g.in_t, pv + 1, re, t);
-    uint32_t lb = lower_bound_i32(g.in_t, rs, pv, lo);
-    mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = hi - lb;
+  // v's in-window [lo, t] (FAN_IN, and the gather side of scatter-gather)
+  const uint32_t pv = g.pos_in[eid];
+  uint32_t vr0 = 0, vr1 = 0;
+  if (mp.col_fi >= 0 || mp.col_sg >= 0 || feat) {
+    uint32_t rs = g.in_ptr[v], re = g.in_ptr[v + 1];
+    vr1 = upper_bound_i32(g.in_t, pv + 1, re, t);
+    vr0 = lower_bound_i32(g.in_t, rs, pv, lo);
+    if (mp.col_fi >= 0) mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = vr1 - vr0;
   }
+  uint32_t p0 = 0, p1 = 0;
   if (mp.col_sg >= 0 || mp.col_gs >= 0) {
     uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
-    uint32_t p0 = lower_bound_i32(g.in_t, cs, ce, lo);
-    uint32_t p1 = lower_bound_i32(g.in_t, p0, ce, t);
+    p0 = lower_bound_i32(g.in_t, cs, ce, lo);
+    p1 = lower_bound_i32(g.in_t, p0, ce, t);
     if (p1 > p0) {
       if (p1 - p0 <= kAnchorScanCap) {
         uint32_t ns = 0;
@@ -78,162 +89,385 @@ __global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags) {
   if (mp.col_cyc >= 0) {
     uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
     uint32_t q0 = lower_bound_i32(g.out_t, vs, ve, lo);
-    if (q0 < ve && g.out_t[q0] < t) f |= kFlagCYC;
+    if (q0 < ve && g.out_t[q0] < t) flags_cy[p] = kFlagCYC;  // cycle roots stay in time order
   }
-  flags[p] = f;
+  if (f & kFlagSG) {
+    // scatter-gather anchors are listed in CSC order: grouped by v, time-sorted
+    flags_sg[pv] = kFlagSG;
+    sg_win[pv] = make_uint4(p0, p1, vr0, vr1);
+    if (feat) {
+      // raw cost-model features of this anchor (see costmodel.h)
+      uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
+      uint32_t q0 = lower_bound_i32(g.out_t, vs, ve, lo);
+      uint32_t q1 = lower_bound_i32(g.out_t, q0, ve, t);
+      uint32_t *o = feat + (uint64_t)pv * kMlpRaw;
+      o[0] = fan_out;
+      o[1] = vr1 - vr0;
+      o[2] = p1 - p0;
+      o[3] = q1 - q0;
+      o[4] = g.out_ptr[u + 1] - g.out_ptr[u];
+      o[5] = g.in_ptr[u + 1] - g.in_ptr[u];
+      o[6] = ve - vs;
+      o[7] = g.in_ptr[v + 1] - g.in_ptr[v];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ k_sg
-__device__ __forceinline__ uint32_t bloom_h1(uint32_t m) { return m * 0x9E3779B1u; }
-__device__ __forceinline__ uint32_t bloom_h2(uint32_t m) {
-  uint32_t x = m ^ (m >> 15);
-  x *= 0x85EBCA6Bu;
-  x ^= x >> 13;
-  return x * 0xC2B2AE35u;
-}
+constexpr uint32_t kCandCap = 2 * AMLM_WAVE;
 
 struct SgLds {
   uint32_t bloom[kBloomWordsMax];
-  uint32_t sb[AMLM_WAVE], soff[AMLM_WAVE], scnt[AMLM_WAVE], sid[AMLM_WAVE];
+  // anchors of the current chunk
+  uint32_t i_eid[AMLM_WAVE], i_u[AMLM_WAVE], i_p0[AMLM_WAVE], i_ns[AMLM_WAVE], i_sg[AMLM_WAVE];
+  uint32_t i_work[AMLM_WAVE], i_wlen[AMLM_WAVE];
+  uint32_t seg_off[AMLM_WAVE];  // exclusive offsets of the segment's sender windows
+  int32_t i_t[AMLM_WAVE], i_lo[AMLM_WAVE], i_tau[AMLM_WAVE];
+  uint32_t i_r0[AMLM_WAVE], i_r1[AMLM_WAVE];  // v's in-window [lo, t] of each anchor
+  // (anchor, sender) pairs of one batch
+  uint32_t pr_item[AMLM_WAVE], pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
+  // Bloom-positive candidates awaiting the exact check
+  uint32_t cq_pair[kCandCap], cq_pos[kCandCap];
 };
 
-__device__ void sg_item(const MineParams &mp, uint32_t p, SgLds &L) {
+// Register-blocked Bloom filter: a key selects one 32-bit word and sets
+// three bits inside it, so a test is a single LDS read.
+struct BloomProbe {
+  uint32_t word, mask;
+};
+__device__ __forceinline__ BloomProbe bloom_probe(uint32_t m, int wshift) {
+  uint32_t x = m * 0x9E3779B1u;
+  x ^= x >> 16;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  uint32_t y = x * 0xC2B2AE35u;
+  BloomProbe p;
+  p.word = x >> wshift;
+  p.mask = (1u << (y >> 27)) | (1u << ((y >> 22) & 31u)) | (1u << ((y >> 17) & 31u));
+  return p;
+}
+__device__ __forceinline__ bool bloom_test(const uint32_t *bloom, int wshift, uint32_t m) {
+  BloomProbe p = bloom_probe(m, wshift);
+  return (bloom[p.word] & p.mask) == p.mask;
+}
+__device__ __forceinline__ void bloom_insert(uint32_t *bloom, int wshift, uint32_t m) {
+  BloomProbe p = bloom_probe(m, wshift);
+  atomicOr(&bloom[p.word], p.mask);
+}
+
+// Owner of flattened index f: the largest a < n with off[a] <= f.
+__device__ __forceinline__ uint32_t owner_of(const uint32_t *off, uint32_t n, uint32_t f) {
+  uint32_t a = 0, b = n - 1;
+  while (a < b) {
+    uint32_t mid = (a + b + 1) >> 1;
+    if (off[mid] <= f) a = mid; else b = mid - 1;
+  }
+  return a;
+}
+
+// Confirm `take` queued candidates (from the top of the queue): the entry
+// must be the first (s, m) edge inside the window and m must have an edge to
+// v later than it and no later than the anchor.
+__device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint32_t take, uint32_t vrs,
+                          uint32_t vre) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
-  const uint64_t lt = lanemask_lt();
-  const uint32_t k = mp.k;
-  uint32_t eid = rfl(g.anc[p]);
-  uint32_t u = rfl(g.src[eid]), v = rfl(g.dst[eid]);
-  int32_t t = rfl(g.t[eid]);
-  int32_t lo = window_lo(t, mp.delta);
-  uint32_t cs = rfl(g.in_ptr[u]), ce = rfl(g.in_ptr[u + 1]);
-  uint32_t p0 = rfl(lower_bound_i32(g.in_t, cs, ce, lo));
-  uint32_t p1 = rfl(lower_bound_i32(g.in_t, p0, ce, t));
-  const bool need_join = mp.col_sg >= 0 && k >= 2;
-  int bloom_shift = -1;
-  uint32_t vrs = rfl(g.in_ptr[v]), vre = rfl(g.in_ptr[v + 1]);
-  uint32_t nS = 0, sg = 0, work = 0;
-  int32_t tau = AMLM_INT_MAX;
-  for (uint32_t c = p0; c < p1; c += AMLM_WAVE) {
-    uint32_t j = c + lane;
-    bool valid = j < p1;
-    uint32_t nb = valid ? g.in_nbr[j] : v;
-    bool not_v = valid && nb != v;
-    int32_t nx = not_v ? g.in_nxt[j] : 0;
-    int32_t tj = not_v ? g.in_t[j] : AMLM_INT_MAX;
-    uint64_t bnv = __ballot(not_v);
-    if (tau == AMLM_INT_MAX && bnv) tau = __shfl(tj, __ffsll((long long)bnv) - 1, AMLM_WAVE);
-    bool is_s = not_v && nx >= t;
-    uint64_t bs = __ballot(is_s);
-    uint32_t ns = __popcll(bs);
-    nS += ns;
-    work += kBytesSenderEntry * min((uint32_t)AMLM_WAVE, p1 - c);
-    if (!need_join || ns == 0) continue;
-    if (bloom_shift < 0) {
-      // stage the gather side: every in-neighbour of v inside [lo, t]
-      uint32_t r0 = rfl(lower_bound_i32(g.in_t, vrs, vre, lo));
-      uint32_t r1 = rfl(upper_bound_i32(g.in_t, r0, vre, t));
-      uint32_t nin = r1 - r0;
-      uint32_t want = nin * kBloomBitsPerEntry;
-      int lg = 9;
-      while (lg < kBloomLog2Max && (1u << lg) < want) lg++;
-      uint32_t words = (1u << lg) >> 5;
-      for (uint32_t q = lane; q < words; q += AMLM_WAVE) L.bloom[q] = 0;
-      bloom_shift = 32 - lg;
-      for (uint32_t q = r0 + lane; q < r1; q += AMLM_WAVE) {
-        uint32_t m = g.in_nbr[q];
-        uint32_t h1 = bloom_h1(m) >> bloom_shift, h2 = bloom_h2(m) >> bloom_shift;
-        atomicOr(&L.bloom[h1 >> 5], 1u << (h1 & 31));
-        atomicOr(&L.bloom[h2 >> 5], 1u << (h2 & 31));
+  if (lane < take) {
+    uint32_t idx = cq_top - take + lane;
+    uint32_t a = L.cq_pair[idx], pos = L.cq_pos[idx];
+    uint32_t it = L.pr_item[a];
+    int32_t lo = L.i_lo[it], t = L.i_t[it];
+    if (g.out_prv[pos] < lo) {
+      int32_t at = g.out_t[pos];
+      uint32_t m = g.out_nbr[pos];
+      uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+      if (q > vrs) {
+        uint64_t kk = g.inn_key[q - 1];
+        if ((uint32_t)(kk >> 32) == m && (int32_t)(uint32_t)kk > at) atomicAdd(&L.pr_cnt[a], 1u);
       }
-      work += kBytesGatherEntry * nin;
     }
-    if (is_s) L.sid[__popcll(bs & lt)] = nb;
-    uint32_t sbv = 0, n_i = 0;
-    if (lane < ns) {
-      uint32_t s = L.sid[lane];
-      uint32_t rs = g.out_ptr[s], re = g.out_ptr[s + 1];
-      sbv = lower_bound_i32(g.out_t, rs, re, lo);
-      n_i = lower_bound_i32(g.out_t, sbv, re, t) - sbv;
-    }
-    uint32_t incl = wave_incl_scan(n_i);
-    uint32_t T = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
-    if (lane < ns) {
-      L.sb[lane] = sbv;
-      L.soff[lane] = incl - n_i;
-      L.scnt[lane] = 1;  // u is an intermediate of every sender
-    }
-    work += kBytesJoinEntry * T;
-    const uint64_t act = ns == AMLM_WAVE ? ~0ull : ((1ull << ns) - 1ull);
-    for (uint32_t f0 = 0; f0 < T; f0 += AMLM_WAVE) {
-      uint32_t f = f0 + lane;
-      if (f < T) {
-        uint32_t a = 0, b = ns - 1;
-        while (a < b) {
-          uint32_t mid = (a + b + 1) >> 1;
-          if (L.soff[mid] <= f) a = mid; else b = mid - 1;
-        }
-        if (L.scnt[a] < k) {
-          uint32_t pos = L.sb[a] + (f - L.soff[a]);
-          uint32_t m = g.out_nbr[pos];
-          if (m != u) {
-            uint32_t h1 = bloom_h1(m) >> bloom_shift, h2 = bloom_h2(m) >> bloom_shift;
-            bool maybe = ((L.bloom[h1 >> 5] >> (h1 & 31)) & (L.bloom[h2 >> 5] >> (h2 & 31)) & 1u) != 0;
-            if (maybe && g.out_prv[pos] < lo) {  // first (s, m) edge inside the window
-              int32_t at = g.out_t[pos];
-              uint32_t q = lower_bound_u64(g.inn_key, vrs, vre, nbr_key(m, t) + 1ull);
-              if (q > vrs) {
-                uint64_t kk = g.inn_key[q - 1];
-                if ((uint32_t)(kk >> 32) == m && (int32_t)(uint32_t)kk > at) atomicAdd(&L.scnt[a], 1u);
-              }
-            }
-          }
-        }
-      }
-      uint64_t done = __ballot(lane < ns && L.scnt[lane] >= k);
-      if (done == act) break;
-    }
-    sg += __popcll(__ballot(lane < ns && L.scnt[lane] >= k));
-  }
-  if (k == 1) sg = nS;
-  uint32_t gs = 0;
-  if (mp.col_gs >= 0 && nS >= k && nS > 0) {
-    if (k == 1) {
-      gs = nS;
-    } else {
-      uint32_t rs = rfl(g.out_ptr[u]), re = rfl(g.out_ptr[u + 1]);
-      uint32_t d0 = rfl(upper_bound_i32(g.out_t, rs, re, tau));
-      uint32_t d1 = rfl(upper_bound_i32(g.out_t, d0, re, t));
-      uint32_t nd = 0;
-      for (uint32_t c = d0; c < d1; c += AMLM_WAVE) {
-        uint32_t j = c + lane;
-        bool first = j < d1 && g.out_prv[j] <= tau;  // first (u, d) edge after tau
-        nd += __popcll(__ballot(first));
-        work += kBytesScatterEntry * min((uint32_t)AMLM_WAVE, d1 - c);
-        if (nd >= k) break;
-      }
-      gs = nd >= k ? nS : 0;
-    }
-  }
-  if (lane == 0) {
-    if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = sg;
-    if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = gs;
-    if (mp.work) atomicAdd(&mp.work[eid], work + kBytesAnchorSg);
   }
 }
 
-__global__ __launch_bounds__(kSgThreads) void k_sg(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
-                                                   uint32_t *ctr, uint32_t chunk) {
-  __shared__ SgLds lds[kSgThreads / AMLM_WAVE];
-  SgLds &L = lds[threadIdx.x / AMLM_WAVE];
+// Queue the Bloom-positive entries of one 64-entry step and verify a full
+// batch of 64 when the queue holds at least that many.
+__device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t &cq, bool cand, uint32_t a,
+                                        uint32_t pos, uint32_t vrs, uint32_t vre) {
+  uint64_t bc = __ballot(cand);
+  if (cand) {
+    uint32_t slot = cq + __popcll(bc & lanemask_lt());
+    L.cq_pair[slot] = a;
+    L.cq_pos[slot] = pos;
+  }
+  cq += __popcll(bc);
+  if (cq >= AMLM_WAVE) {
+    sg_verify(mp, L, cq, AMLM_WAVE, vrs, vre);
+    cq -= AMLM_WAVE;
+  }
+}
+
+// Join one batch of np (anchor, sender) pairs: pair `slot` (= lane) holds
+// its slice [pr_b, pr_b + pr_n) of the sender's out-row.  Long slices are
+// scanned one pair at a time by the whole wave with the pair's fields in
+// scalar registers; short ones are flattened over the lanes.
+__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre) {
+  const GraphView &g = mp.g;
+  const uint32_t lane = lane_id();
+  const uint32_t need = mp.k - 1;  // intermediates needed besides u
+  uint32_t cq = 0;
+  constexpr int U = kJoinUnroll;  // independent 256-byte loads in flight per wave
+  const uint32_t my_n = lane < np ? L.pr_n[lane] : 0u;
+  uint64_t longs = __ballot(my_n >= kLongPair);
+  while (longs) {
+    uint32_t a = __ffsll((long long)longs) - 1;
+    longs &= longs - 1;
+    const uint32_t b = rfl(L.pr_b[a]), n = rfl(L.pr_n[a]);
+    const uint32_t u = rfl(L.i_u[rfl(L.pr_item[a])]);
+    for (uint32_t f0 = 0; f0 < n; f0 += U * AMLM_WAVE) {
+      if (rfl(L.pr_cnt[a]) >= need) break;
+      uint32_t m[U];
+#pragma unroll
+      for (int r = 0; r < U; r++) {
+        uint32_t f = f0 + r * AMLM_WAVE + lane;
+        m[r] = f < n ? g.out_nbr[b + f] : u;  // u is never a candidate
+      }
+#pragma unroll
+      for (int r = 0; r < U; r++) {
+        bool cand = m[r] != u && bloom_test(L.bloom, shift, m[r]);
+        sg_push(mp, L, cq, cand, a, b + f0 + r * AMLM_WAVE + lane, vrs, vre);
+      }
+    }
+  }
+  // short pairs, flattened
+  const uint32_t ns = my_n < kLongPair ? my_n : 0u;
+  const uint32_t incl = wave_incl_scan(ns);
+  const uint32_t T = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
+  L.pr_off[lane] = incl - ns;
+  for (uint32_t f0 = 0; f0 < T; f0 += AMLM_WAVE) {
+    uint32_t f = f0 + lane;
+    bool cand = false;
+    uint32_t a = 0, pos = 0;
+    if (f < T) {
+      a = owner_of(L.pr_off, np, f);
+      pos = L.pr_b[a] + (f - L.pr_off[a]);
+      if (L.pr_cnt[a] < need) {
+        uint32_t m = g.out_nbr[pos];
+        cand = m != L.i_u[L.pr_item[a]] && bloom_test(L.bloom, shift, m);
+      }
+    }
+    sg_push(mp, L, cq, cand, a, pos, vrs, vre);
+  }
+  while (cq > 0) {
+    uint32_t take = min(cq, (uint32_t)AMLM_WAVE);
+    sg_verify(mp, L, cq, take, vrs, vre);
+    cq -= take;
+  }
+}
+
+// Anchors [s0, s1) of the chunk, all into vertex v.
+__device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t v) {
+  const GraphView &g = mp.g;
+  const uint32_t lane = lane_id();
+  const uint64_t lt = lanemask_lt();
+  const uint32_t nit = s1 - s0;
+  const bool need_join = mp.col_sg >= 0 && mp.k >= 2;
+  int shift = 0;
+  uint32_t vrs = rfl(g.in_ptr[v]), vre = rfl(g.in_ptr[v + 1]);
+  if (need_join) {
+    // gather side of the whole segment: v's in-neighbours in [lo_first, t_last]
+    // (the anchors are time-sorted inside the segment)
+    uint32_t r0 = rfl(L.i_r0[s0]), r1 = rfl(L.i_r1[s1 - 1]);
+    uint32_t nin = r1 - r0;
+    int lg = 9;
+    while (lg < kBloomLog2Max && (1u << lg) < nin * kBloomBitsPerEntry) lg++;
+    uint32_t words = (1u << lg) >> 5;
+    for (uint32_t q = lane; q < words; q += AMLM_WAVE) L.bloom[q] = 0;
+    shift = 32 - (lg - 5);  // word index = top (lg - 5) bits
+    for (uint32_t q0 = r0; q0 < r1; q0 += 4 * AMLM_WAVE) {
+      uint32_t mm[4];
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        uint32_t q = q0 + r * AMLM_WAVE + lane;
+        mm[r] = q < r1 ? g.in_nbr[q] : 0xffffffffu;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        if (mm[r] != 0xffffffffu) bloom_insert(L.bloom, shift, mm[r]);
+      }
+    }
+    if (mp.work && lane < nit) {
+      uint32_t share = kBytesGatherEntry * nin;
+      L.i_work[s0 + lane] += share / nit + (lane == 0 ? share % nit : 0);
+    }
+  }
+  // senders: flatten the anchors' windows [p0, p1) over the lanes
+  uint32_t w = lane < nit ? L.i_wlen[s0 + lane] : 0u;
+  uint32_t incl = wave_incl_scan(w);
+  uint32_t W = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
+  L.seg_off[lane] = incl - w;
+  for (uint32_t f0 = 0; f0 < W; f0 += AMLM_WAVE) {
+    uint32_t f = f0 + lane;
+    bool is_s = false;
+    uint32_t it = 0, nb = 0, apos = 0;
+    if (f < W) {
+      uint32_t a = owner_of(L.seg_off, nit, f);
+      it = s0 + a;
+      uint32_t j = L.i_p0[it] + (f - L.seg_off[a]);
+      nb = g.in_nbr[j];
+      if (nb != v) {
+        atomicMin(&L.i_tau[it], g.in_t[j]);
+        is_s = g.in_nxt[j] >= L.i_t[it];  // last sender edge before t: one per distinct s
+        if (is_s) {
+          atomicAdd(&L.i_ns[it], 1u);
+          apos = g.pos_out[g.in_eid[j]];  // this s -> u edge inside s's out-row
+        }
+      }
+      if (mp.work) atomicAdd(&L.i_work[it], kBytesSenderEntry);
+    }
+    if (!need_join) continue;
+    uint64_t bs = __ballot(is_s);
+    if (!bs) continue;
+    // this lane's pair: slice of s's out-row inside [lo, t)
+    uint32_t b = 0, n = 0;
+    if (is_s) {
+      // s's out-window [lo, t) contains apos: gallop outwards from it
+      uint32_t rs = g.out_ptr[nb], re = g.out_ptr[nb + 1];
+      b = gallop_lower_left(g.out_t, rs, apos, L.i_lo[it]);
+      n = gallop_lower_right(g.out_t, apos + 1, re, L.i_t[it]) - b;
+      if (mp.work) atomicAdd(&L.i_work[it], kBytesJoinEntry * n);
+    }
+    uint32_t np = __popcll(bs);
+    if (is_s) {
+      uint32_t slot = __popcll(bs & lt);
+      L.pr_item[slot] = it;
+      L.pr_b[slot] = b;
+      L.pr_n[slot] = n;
+      L.pr_cnt[slot] = 0;
+    }
+    sg_join(mp, L, np, shift, vrs, vre);
+    if (lane < np && L.pr_cnt[lane] >= mp.k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
+  }
+}
+
+// Gather-scatter for one anchor when the lane-serial scan hit its cap.
+__device__ uint32_t gs_wave(const MineParams &mp, uint32_t u, int32_t tau, int32_t t, uint32_t *work) {
+  const GraphView &g = mp.g;
+  const uint32_t lane = lane_id();
+  uint32_t rs = rfl(g.out_ptr[u]), re = rfl(g.out_ptr[u + 1]);
+  uint32_t d0 = rfl(upper_bound_i32(g.out_t, rs, re, tau));
+  uint32_t d1 = rfl(upper_bound_i32(g.out_t, d0, re, t));
+  uint32_t nd = 0;
+  for (uint32_t c = d0; c < d1; c += AMLM_WAVE) {
+    uint32_t j = c + lane;
+    bool first = j < d1 && g.out_prv[j] <= tau;  // first (u, d) edge after tau
+    nd += __popcll(__ballot(first));
+    *work += kBytesScatterEntry * min((uint32_t)AMLM_WAVE, d1 - c);
+    if (nd >= mp.k) break;
+  }
+  return nd;
+}
+
+constexpr uint32_t kGsLaneCap = 32;
+
+__global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
+                                                 uint32_t *ctr, uint32_t chunk, const uint4 *sg_win,
+                                                 const uint32_t *chunk_tab) {
+  __shared__ SgLds L;
+  const GraphView &g = mp.g;
+  const uint32_t lane = lane_id();
   const uint32_t n_items = *n_items_p;
+  const uint32_t k = mp.k;
+  const int32_t seg_span = (int32_t)max((int64_t)1, min(mp.delta / 4, (int64_t)0x40000000));
+  chunk = min(chunk, (uint32_t)AMLM_WAVE);
+  const uint32_t n_chunks = (n_items + chunk - 1) / chunk;
   for (;;) {
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(ctr, chunk);
-    base = rfl((uint32_t)__shfl(base, 0, AMLM_WAVE));
-    if (base >= n_items) break;
-    uint32_t end = min(base + chunk, n_items);
-    for (uint32_t i = base; i < end; i++) sg_item(mp, items[i], L);
+    // static: consecutive chunks of the CSC-ordered list; learned: the chunk
+    // table orders chunks by predicted cost, heaviest first
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(ctr, 1u);
+    c = rfl((uint32_t)__shfl(c, 0, AMLM_WAVE));
+    if (c >= n_chunks) break;
+    const uint32_t base = (chunk_tab ? chunk_tab[c] : c) * chunk;
+    const uint32_t nr = min(chunk, n_items - base);
+    uint32_t v = 0xffffffffu;
+    if (lane < nr) {
+      uint32_t q = items[base + lane];
+      uint32_t eid = g.in_eid[q];
+      int32_t t = g.in_t[q];
+      uint4 pw = sg_win[q];
+      v = g.in_dst[q];
+      L.i_r0[lane] = pw.z;
+      L.i_r1[lane] = pw.w;
+      L.i_eid[lane] = eid;
+      L.i_u[lane] = g.in_nbr[q];
+      L.i_t[lane] = t;
+      L.i_lo[lane] = window_lo(t, mp.delta);
+      L.i_p0[lane] = pw.x;
+      L.i_wlen[lane] = pw.y - pw.x;
+      L.i_ns[lane] = 0;
+      L.i_sg[lane] = 0;
+      L.i_tau[lane] = AMLM_INT_MAX;
+      L.i_work[lane] = kBytesAnchorSg;
+    }
+    // segments: runs of anchors into the same v inside one time bucket of
+    // width delta / 4, so that a segment's gather window stays short
+    int32_t tb = lane < nr ? L.i_t[lane] / seg_span : 0;
+    uint32_t vprev = __shfl_up(v, 1, AMLM_WAVE);
+    int32_t tbprev = __shfl_up(tb, 1, AMLM_WAVE);
+    uint64_t heads = __ballot(lane < nr && (lane == 0 || v != vprev || tb != tbprev));
+    while (heads) {
+      uint32_t s0 = __ffsll((long long)heads) - 1;
+      heads &= heads - 1;
+      uint32_t s1 = heads ? (uint32_t)(__ffsll((long long)heads) - 1) : nr;
+      uint32_t vs = rfl((uint32_t)__shfl(v, s0, AMLM_WAVE));
+      sg_segment(mp, L, s0, s1, vs);
+    }
+    // gather-scatter and the outputs, one lane per anchor
+    uint32_t sg = 0, gs = 0;
+    bool gs_wide = false;
+    uint32_t ns = 0, u = 0, work = 0;
+    int32_t tau = 0, t = 0;
+    if (lane < nr) {
+      ns = L.i_ns[lane];
+      sg = k == 1 ? ns : L.i_sg[lane];
+      u = L.i_u[lane];
+      tau = L.i_tau[lane];
+      t = L.i_t[lane];
+      work = L.i_work[lane];
+      if (mp.col_gs >= 0 && ns >= k && ns > 0) {
+        if (k == 1) {
+          gs = ns;  // v follows tau, so D is never empty
+        } else {
+          uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
+          uint32_t d0 = upper_bound_i32(g.out_t, rs, re, tau);
+          uint32_t d1 = upper_bound_i32(g.out_t, d0, re, t);
+          uint32_t nd = 0, j = d0;
+          for (; j < d1 && j < d0 + kGsLaneCap && nd < k; j++) nd += g.out_prv[j] <= tau;
+          work += kBytesScatterEntry * (j - d0);
+          if (nd >= k) gs = ns;
+          else if (j < d1) gs_wide = true;
+        }
+      }
+    }
+    uint64_t wide = __ballot(gs_wide);
+    while (wide) {
+      uint32_t a = __ffsll((long long)wide) - 1;
+      wide &= wide - 1;
+      uint32_t ua = rfl((uint32_t)__shfl(u, a, AMLM_WAVE));
+      int32_t ta = rfl(__shfl(tau, a, AMLM_WAVE)), tt = rfl(__shfl(t, a, AMLM_WAVE));
+      uint32_t wk = 0;
+      uint32_t nd = gs_wave(mp, ua, ta, tt, &wk);
+      if (lane == a) {
+        work += wk;
+        if (nd >= k) gs = ns;
+      }
+    }
+    if (lane < nr) {
+      uint32_t eid = L.i_eid[lane];
+      if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = sg;
+      if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = gs;
+      if (mp.work) atomicAdd(&mp.work[eid], work);
+    }
   }
 }
 
@@ -338,7 +572,7 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
     if (base >= n_in) break;
     uint32_t nr = min((uint32_t)AMLM_WAVE, n_in - base);
     if (lane < nr) {
-      uint32_t eid = g.anc[roots[base + lane]];
+      uint32_t eid = g.anc[roots[base + lane]];  // time-order position of the anchor
       uint32_t v = g.dst[eid];
       int32_t t = g.t[eid];
       S.r_eid[lane] = eid;
@@ -404,16 +638,36 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
   }
 }
 
-__global__ void k_flag_count(const uint8_t *flags, uint32_t n, uint32_t *c_sg, uint32_t *c_cy) {
+// Sort keys of the learned schedule: predicted cost of each chunk of `chunk`
+// consecutive list items (sum of expm1 of the predicted log-work), quantised
+// so that an ascending sort puts the heaviest chunk first; chunks past the
+// end of the list sort last.
+__global__ void k_chunk_keys(const float *pred, const uint32_t *n_items_p, uint32_t chunk, uint32_t max_chunks,
+                             uint32_t *keys, uint32_t *vals) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= max_chunks) return;
+  const uint32_t n = *n_items_p;
+  uint32_t key = kChunkKeyInvalid;
+  if (c * chunk < n) {
+    float cost = 0.f;
+    uint32_t e = min(n, (c + 1) * chunk);
+    for (uint32_t i = c * chunk; i < e; i++) cost += expm1f(fminf(fmaxf(pred[i], 0.f), 40.f));
+    float q = log2f(cost + 1.f) * 1024.f;
+    key = 0xffffu - (uint32_t)fminf(q, 65535.f);
+  }
+  keys[c] = key;
+  vals[c] = c;
+}
+
+__global__ void k_flag_count(const uint8_t *fsg, const uint8_t *fcy, uint32_t n, uint32_t *c_sg, uint32_t *c_cy) {
   __shared__ uint32_t ws[2][kFlagThreads / AMLM_WAVE];
   uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
   uint32_t base = blockIdx.x * kFlagTile + tid * kFlagItems;
   uint32_t a = 0, b = 0;
   for (uint32_t j = 0; j < kFlagItems; j++) {
     uint32_t idx = base + j;
-    uint8_t f = idx < n ? flags[idx] : 0;
-    a += (f & kFlagSG) != 0;
-    b += (f & kFlagCYC) != 0;
+    a += idx < n && fsg[idx] != 0;
+    b += idx < n && fcy[idx] != 0;
   }
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_xor(a, o, AMLM_WAVE);
@@ -436,18 +690,19 @@ __global__ void k_flag_count(const uint8_t *flags, uint32_t n, uint32_t *c_sg, u
 }
 
 // order-preserving scatter of flagged anchor positions
-__global__ void k_flag_scatter(const uint8_t *flags, uint32_t n, const uint32_t *o_sg, const uint32_t *o_cy,
-                               uint32_t *l_sg, uint32_t *l_cy) {
+__global__ void k_flag_scatter(const uint8_t *fsg, const uint8_t *fcy, uint32_t n, const uint32_t *o_sg,
+                               const uint32_t *o_cy, uint32_t *l_sg, uint32_t *l_cy) {
   __shared__ uint32_t ws[2][kFlagThreads / AMLM_WAVE];
   uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
   uint32_t base = blockIdx.x * kFlagTile + tid * kFlagItems;
-  uint8_t f[kFlagItems];
+  bool fa[kFlagItems], fb[kFlagItems];
   uint32_t a = 0, b = 0;
   for (uint32_t j = 0; j < kFlagItems; j++) {
     uint32_t idx = base + j;
-    f[j] = idx < n ? flags[idx] : 0;
-    a += (f[j] & kFlagSG) != 0;
-    b += (f[j] & kFlagCYC) != 0;
+    fa[j] = idx < n && fsg[idx] != 0;
+    fb[j] = idx < n && fcy[idx] != 0;
+    a += fa[j];
+    b += fb[j];
   }
   uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
   if (lane_id() == AMLM_WAVE - 1) {
@@ -461,8 +716,8 @@ __global__ void k_flag_scatter(const uint8_t *flags, uint32_t n, const uint32_t 
     pb += ws[1][q];
   }
   for (uint32_t j = 0; j < kFlagItems; j++) {
-    if (f[j] & kFlagSG) l_sg[pa++] = base + j;
-    if (f[j] & kFlagCYC) l_cy[pb++] = base + j;
+    if (fa[j]) l_sg[pa++] = base + j;
+    if (fb[j]) l_cy[pb++] = base + j;
   }
 }
 
@@ -485,7 +740,11 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   CK(launch_fill_u32(ms.ctr, 0, kCtrWords, s));
   if (Ev == 0) return hipSuccess;
   CK(tm->begin(kStAnchor, s));
-  hipLaunchKernelGGL(k_anchor, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, ms.flags);
+  CK(launch_fill_u32((uint32_t *)ms.flags, 0, 2 * ((Ev + 3) / 4), s));
+  uint8_t *flags_sg = ms.flags, *flags_cy = ms.flags + 4 * ((Ev + 3) / 4);
+  const bool learned = cfg.learned && mp.col_sg >= 0 && mp.k >= 2;
+  hipLaunchKernelGGL(k_anchor, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, flags_cy, ms.sg_win,
+                     learned ? ms.feat : (uint32_t *)nullptr);
   CK(hipGetLastError());
   CK(tm->end(kStAnchor, s));
   const bool want_sg = mp.col_sg >= 0 || mp.col_gs >= 0;
@@ -493,19 +752,37 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   if (!want_sg && !want_cyc) return hipSuccess;
   uint32_t nb = (Ev + kFlagTile - 1) / kFlagTile;
   CK(tm->begin(kStLists, s));
-  hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, ms.flags, Ev, ms.bcnt_sg, ms.bcnt_cy);
+  hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, flags_cy, Ev, ms.bcnt_sg,
+                     ms.bcnt_cy);
   CK(hipGetLastError());
   uint32_t *n_sg = ms.ctr + kCtrNSg, *n_cy = ms.ctr + kCtrNCy;
   CK(scan_exclusive_u32(ms.bcnt_sg, ms.boff_sg, nb, n_sg, ms.scan_tmp, s));
   CK(scan_exclusive_u32(ms.bcnt_cy, ms.boff_cy, nb, n_cy, ms.scan_tmp, s));
-  hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, ms.flags, Ev, ms.boff_sg, ms.boff_cy,
-                     ms.list_sg, ms.list_cy);
+  hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, flags_cy, Ev, ms.boff_sg,
+                     ms.boff_cy, ms.list_sg, ms.list_cy);
   CK(hipGetLastError());
   CK(tm->end(kStLists, s));
+  const uint32_t *chunk_tab = nullptr;
+  uint32_t chunk = cfg.sg_chunk;
+  if (want_sg && learned) {
+    // cost model: predicted work per list item, then chunks heavy-first
+    CK(tm->begin(kStModel, s));
+    chunk = cfg.learned_chunk;
+    CK(mlp_infer(global_model(), ms.feat, ms.list_sg, 0, n_sg, cfg.delta_hours, (float)mp.L, ms.pred, s));
+    uint32_t max_chunks = (Ev + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_chunk_keys, dim3((max_chunks + 255) / 256), dim3(256), 0, s, ms.pred, n_sg, chunk,
+                       max_chunks, cfg.bb->ka, cfg.bb->va);
+    CK(hipGetLastError());
+    uint32_t *ks, *vs;
+    CK(radix_sort_pairs(cfg.bb->ka, cfg.bb->va, cfg.bb->kb, cfg.bb->vb, max_chunks, kChunkKeyBits, cfg.bb->hist,
+                        cfg.bb->hist2, cfg.bb->scan_tmp, s, &ks, &vs));
+    chunk_tab = vs;
+    CK(tm->end(kStModel, s));
+  }
   if (want_sg) {
     CK(tm->begin(kStSg, s));
     hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, n_sg,
-                       ms.ctr + kCtrSgWork, cfg.sg_chunk);
+                       ms.ctr + kCtrSgWork, chunk, (const uint4 *)ms.sg_win, chunk_tab);
     CK(hipGetLastError());
     CK(tm->end(kStSg, s));
   }

@@ -10,12 +10,6 @@ extern "C" amlm_status amlm_mine_batch(amlm_graph *const *, const amlm_params *,
                                        void *) {
   return not_built("amlm_mine_batch");
 }
-extern "C" amlm_status amlm_costmodel_train(amlm_graph *const *, const amlm_params *, uint32_t, uint32_t, uint32_t,
-                                            uint64_t, const char *, void *) {
-  return not_built("amlm_costmodel_train");
-}
-extern "C" amlm_status amlm_costmodel_load(const char *) { return not_built("amlm_costmodel_load"); }
-extern "C" amlm_status amlm_costmodel_save(const char *) { return not_built("amlm_costmodel_save"); }
 extern "C" amlm_status amlm_server_create(amlm_graph *, const amlm_params *, uint64_t, uint32_t, amlm_server **) {
   return not_built("amlm_server_create");
 }

@@ -1,0 +1,96 @@
+"""GPU checks of the learned cost model and the learned schedule."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_12241_amd as A
+from oracle import mlp
+from paper_2604_12241_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _weights(seed):
+    rng = np.random.default_rng(seed)
+    w = rng.normal(0, 0.3, mlp.N_PARAMS).astype(np.float32)
+    return mlp.bf16_round(w)
+
+
+def test_forward_and_gradient_match_fp64_reference():
+    rng = np.random.default_rng(7)
+    w = _weights(1)
+    for n in (1, 63, 64, 65, 1000, 4096):
+        X = mlp.bf16_round(rng.normal(0, 1, (n, mlp.F)).astype(np.float32))
+        Y = rng.normal(0, 2, n).astype(np.float32)
+        y_gpu = A.amlm_mlp_forward(w, X)
+        y_ref = mlp.forward(w.astype(np.float64), X.astype(np.float64))
+        np.testing.assert_allclose(y_gpu, y_ref, rtol=1e-4, atol=1e-4)
+        g_gpu, loss = A.amlm_mlp_grad(w, X, Y)
+        g_ref = mlp.grad(w.astype(np.float64), X.astype(np.float64), Y.astype(np.float64))
+        tol = 1e-3 * np.maximum(1.0, np.abs(g_ref))
+        bad = np.abs(g_gpu - g_ref) > tol
+        assert not bad.any(), (n, np.nonzero(bad)[0][:5], g_gpu[bad][:5], g_ref[bad][:5])
+        assert abs(loss - mlp.loss(w, X, Y)) <= 1e-4 * max(1.0, loss)
+
+
+def test_gradient_is_deterministic():
+    rng = np.random.default_rng(9)
+    w = _weights(2)
+    X = rng.normal(0, 1, (3000, mlp.F)).astype(np.float32)
+    Y = rng.normal(0, 1, 3000).astype(np.float32)
+    g1, _ = A.amlm_mlp_grad(w, X, Y)
+    g2, _ = A.amlm_mlp_grad(w, X, Y)
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+@pytest.fixture(scope="module")
+def trained():
+    gs = [W.mid(202 + i, scale=0.02) for i in range(2)]
+    Gs = [A.Graph(g.src, g.dst, g.ts, g.n_vertices) for g in gs]
+    ps = [A.params(A.AMLM_ALL, 86400, 6, 2)] * len(Gs)
+    A.amlm_costmodel_train(Gs, ps, epochs=3, batch=1024, seed=5)
+    w, mean, inv_std = A.amlm_costmodel_get()
+    for G in Gs:
+        G.close()
+    return w, mean, inv_std
+
+
+def test_training_is_deterministic_and_predicts_work(trained):
+    w, mean, inv_std = trained
+    assert np.isfinite(w).all() and np.isfinite(mean).all()
+    # retrain with the same seed: identical weights
+    gs = [W.mid(202 + i, scale=0.02) for i in range(2)]
+    Gs = [A.Graph(g.src, g.dst, g.ts, g.n_vertices) for g in gs]
+    A.amlm_costmodel_train(Gs, [A.params(A.AMLM_ALL, 86400, 6, 2)] * 2, epochs=3, batch=1024, seed=5)
+    w2, _, _ = A.amlm_costmodel_get()
+    assert np.array_equal(w.view(np.uint32), w2.view(np.uint32))
+    for G in Gs:
+        G.close()
+
+
+def test_learned_schedule_counts_equal_static_and_oracle(trained):
+    g = W.mid(210, scale=0.03)
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    ps = A.params(A.AMLM_ALL, 86400, 6, 2, A.AMLM_SCHED_STATIC)
+    pl = A.params(A.AMLM_ALL, 86400, 6, 2, A.AMLM_SCHED_LEARNED)
+    a = A.to_u32(A.amlm_mine(G, ps))
+    b = A.to_u32(A.amlm_mine(G, pl))
+    A.amlm_graph_sync(G)
+    np.testing.assert_array_equal(a, b)
+    ref = oracle.mine(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL, 86400, 6, 2)
+    np.testing.assert_array_equal(b, ref)
+    G.close()
+
+
+def test_save_load_roundtrip(trained):
+    w, mean, inv_std = trained
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        A.amlm_costmodel_save(path)
+        A.amlm_costmodel_load(path)
+        w2, m2, s2 = A.amlm_costmodel_get()
+    assert np.array_equal(w, w2) and np.array_equal(mean, m2) and np.array_equal(inv_std, s2)
