@@ -160,14 +160,52 @@ amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream);
 amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
                            uint32_t *work_dev, void *hip_stream);
 
+/* ---- batching: many independent graphs in one launch ---- */
+
 /*
- * Mine n_graphs independent graphs in one launch sequence (captured once
- * into a hipGraph per distinct batch shape and replayed).  gs[i], ps[i],
- * counts_dev[i] are as for amlm_mine; each graph keeps its own delta, L and
- * k, but all must request the same pattern set and schedule.
+ * Batched store: n_graphs independent graphs (for example one partition per
+ * institution) held in one graph store with disjoint vertex ranges, so that
+ * one launch sequence mines all of them.  src / dst hold each graph's LOCAL
+ * vertex ids (graph i: 0 <= id < n_vertices[i]); graph i owns edges
+ * [edge_offsets[i], edge_offsets[i + 1]) of the concatenated arrays
+ * (edge_offsets[0] = 0, n_graphs + 1 entries).  The timestamps of all graphs
+ * together must span < 2^31 - 1.  Pointers as for amlm_graph_create; the
+ * call synchronises hip_stream.  Destroy with amlm_graph_destroy.
  */
-amlm_status amlm_mine_batch(amlm_graph *const *gs, const amlm_params *ps, uint32_t *const *counts_dev,
-                            uint32_t n_graphs, void *hip_stream);
+amlm_status amlm_batch_create(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                              const uint64_t *edge_offsets, const uint32_t *n_vertices, uint32_t n_graphs,
+                              int inputs_on_device, void *hip_stream, amlm_graph **out);
+
+/*
+ * Mine every graph of a batched store with its own parameters ps[i]: the
+ * same pattern set and schedule for all, delta, L and k per graph.
+ * counts_dev[i]: device memory of amlm_num_columns(&ps[i]) * n_edges_i
+ * uint32, layout [col][edge] of graph i (edge ids local to graph i).  The
+ * launch sequence (anchor pass, work lists, scatter-gather and cycle
+ * kernels, split into the per-graph outputs) is captured once into a
+ * hipGraph per launch signature and replayed on hip_stream; parameters and
+ * output pointers are read from device memory at replay, so they may change
+ * between calls.  Asynchronous like amlm_mine.
+ */
+amlm_status amlm_mine_batch(amlm_graph *batch, const amlm_params *ps, uint32_t *const *counts_dev,
+                            void *hip_stream);
+
+/* Number of sub-graphs of a batched store and how many hipGraph captures
+ * amlm_mine_batch has made so far. */
+amlm_status amlm_batch_info(const amlm_graph *g, uint32_t *n_graphs, uint32_t *captures);
+
+/*
+ * Autotune the mining launch shape of g (work-stealing chunk size and grid
+ * sizes of the persistent kernels) by timed runs with HIP events, keep the
+ * best on the handle, and cache it in the JSON file cache_path (keyed by
+ * device, graph size and parameters; NULL = no cache).  A cached entry is
+ * used without timing.  For a batched store pass one parameter set per graph
+ * and counts_dev as for amlm_mine_batch; otherwise n_params = 1 and
+ * counts_dev[0].  chosen (may be NULL) receives {chunk, sg_blocks,
+ * cyc_blocks}.  Counts written during tuning are the mining results.
+ */
+amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint32_t n_params, uint32_t *const *counts_dev,
+                          const char *cache_path, void *hip_stream, uint32_t *chosen);
 
 /* ---- learned cost model (scheduling only; never changes a count) ---- */
 

@@ -29,6 +29,7 @@ EXPORTS = [
     "amlm_server_create", "amlm_server_submit", "amlm_server_wait", "amlm_server_ticket_times",
     "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
+    "amlm_batch_create", "amlm_batch_info", "amlm_autotune",
 ]
 
 
@@ -66,7 +67,10 @@ def lib():
             "amlm_mine": (st, [p, pp, p, p]),
             "amlm_graph_sync": (st, [p, p]),
             "amlm_mine_work": (st, [p, pp, p, p, p]),
-            "amlm_mine_batch": (st, [p, pp, p, u32, p]),
+            "amlm_mine_batch": (st, [p, pp, p, p]),
+            "amlm_batch_create": (st, [p, p, p, p, p, u32, ctypes.c_int, p, ctypes.POINTER(p)]),
+            "amlm_batch_info": (st, [p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+            "amlm_autotune": (st, [p, pp, u32, p, ctypes.c_char_p, p, p]),
             "amlm_costmodel_train": (st, [p, pp, u32, u32, u32, u64, ctypes.c_char_p, p]),
             "amlm_costmodel_load": (st, [ctypes.c_char_p]),
             "amlm_costmodel_save": (st, [ctypes.c_char_p]),
@@ -214,6 +218,54 @@ def amlm_stage_times(g: Graph) -> dict:
 
 def amlm_graph_sync(g: Graph, stream=None):
     _check(lib().amlm_graph_sync(g.handle, _stream_handle(stream)))
+
+
+class Batch(Graph):
+    """A batched store: many independent graphs mined in one launch."""
+
+    def __init__(self, graphs, stream=None):
+        srcs = [np.ascontiguousarray(g[0], np.uint32) for g in graphs]
+        dsts = [np.ascontiguousarray(g[1], np.uint32) for g in graphs]
+        tss = [np.ascontiguousarray(g[2], np.int64) for g in graphs]
+        nvs = np.array([int(g[3]) for g in graphs], np.uint32)
+        sizes = np.array([s.shape[0] for s in srcs], np.uint64)
+        self.eoff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+        src = np.concatenate(srcs) if srcs else np.zeros(0, np.uint32)
+        dst = np.concatenate(dsts) if dsts else np.zeros(0, np.uint32)
+        ts = np.concatenate(tss) if tss else np.zeros(0, np.int64)
+        self.handle = ctypes.c_void_p()
+        _check(lib().amlm_batch_create(_ptr(src), _ptr(dst), _ptr(ts), _ptr(self.eoff), _ptr(nvs),
+                                       len(graphs), 0, _stream_handle(stream), ctypes.byref(self.handle)))
+        self.n_graphs = len(graphs)
+        self.n_edges = int(self.eoff[-1])
+        self.sizes = sizes
+
+    def info_batch(self):
+        n, c = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().amlm_batch_info(self.handle, ctypes.byref(n), ctypes.byref(c)))
+        return n.value, c.value
+
+
+def amlm_mine_batch(b: Batch, ps, outs=None, stream=None):
+    """Mine a batched store; ps: one amlm_params per graph.  Returns the list
+    of per-graph int32 tensors [ncols_i, n_edges_i]."""
+    import torch
+    if outs is None:
+        outs = [torch.empty((amlm_num_columns(p), int(b.sizes[i])), dtype=torch.int32, device="cuda")
+                for i, p in enumerate(ps)]
+    pa = (amlm_params * len(ps))(*ps)
+    ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+    _check(lib().amlm_mine_batch(b.handle, pa, ptrs, _stream_handle(stream)))
+    return outs
+
+
+def amlm_autotune(g: Graph, ps, outs, cache_path=None, stream=None):
+    pa = (amlm_params * len(ps))(*ps)
+    ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+    chosen = (ctypes.c_uint32 * 3)()
+    _check(lib().amlm_autotune(g.handle, pa, len(ps), ptrs, cache_path.encode() if cache_path else None,
+                               _stream_handle(stream), chosen))
+    return list(chosen)
 
 
 MLP_PARAMS = 5057

@@ -247,6 +247,7 @@ extern "C" amlm_status amlm_graph_rebuild(amlm_graph *g, const uint32_t *src, co
 extern "C" void amlm_graph_destroy(amlm_graph *g) {
   if (!g) return;
   (void)hipDeviceSynchronize();
+  batch_free(g);
   free_all(g);
   if (g->timer.ev[0])
     for (hipEvent_t &e : g->timer.ev) (void)hipEventDestroy(e);
@@ -313,6 +314,8 @@ MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *coun
   mp.delta = p->delta;
   mp.L = (p->patterns & AMLM_CYCLES) ? p->max_cycle_len : 2;
   mp.k = p->k ? p->k : 1;
+  mp.vgraph = nullptr;
+  mp.sub = nullptr;
   int c = 0;
   mp.col_fo = (p->patterns & AMLM_FAN_OUT) ? c++ : -1;
   mp.col_fi = (p->patterns & AMLM_FAN_IN) ? c++ : -1;

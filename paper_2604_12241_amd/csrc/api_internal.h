@@ -1,6 +1,7 @@
 // Host-side graph handle and helpers shared by the C ABI translation units.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "mine.h"
@@ -17,6 +18,26 @@ struct TuneParams {
   uint32_t sg_chunk = 0, sg_blocks = 0, cyc_blocks = 0;  // 0 = default
 };
 
+// Batched store state (batch.hip): sub-graph layout, device parameter
+// tables and the captured launch sequence.
+struct BatchState {
+  uint32_t n = 0;                      // number of sub-graphs (0: ordinary graph)
+  std::vector<uint64_t> eoff;          // edge offsets [n + 1]
+  std::vector<uint32_t> voff;          // vertex offsets [n + 1]
+  uint64_t *d_eoff = nullptr;
+  uint32_t *d_voff = nullptr, *vgraph = nullptr, *d_ncols = nullptr;
+  SubParams *d_sub = nullptr;
+  uint32_t **d_outs = nullptr;
+  uint32_t *comb = nullptr;            // combined counts [ncols][E]
+  uint32_t comb_cols = 0;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::string sig;
+  uint32_t captures = 0;
+  std::vector<void *> allocs;
+};
+void batch_free(amlm_graph *g);
+
 struct amlm_graph {
   int device = 0;
   uint64_t E = 0;
@@ -32,6 +53,7 @@ struct amlm_graph {
   MineScratch ms{};
   TuneParams tune{};
   StageTimer timer{};
+  BatchState batch{};
   amlm_status sticky = AMLM_OK;
   std::vector<void *> allocs;
   uint64_t device_bytes = 0;

@@ -1,0 +1,429 @@
+// Batched mining: many independent graphs in one graph store (disjoint vertex
+// ranges), mined by one launch sequence that is captured once into a
+// hipGraph and replayed; plus the autotuner for the launch shape.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+#include "costmodel.h"
+
+namespace {
+
+// local ids -> global ids; flags endpoints outside their graph's range
+__global__ void k_batch_offsets(const uint32_t *src, const uint32_t *dst, uint64_t E, const uint64_t *eoff,
+                                const uint32_t *voff, const uint32_t *nv, uint32_t n, uint32_t *gsrc, uint32_t *gdst,
+                                uint32_t *bad) {
+  uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= E) return;
+  uint32_t a = 0, b = n - 1;  // graph i with eoff[i] <= j < eoff[i+1]
+  while (a < b) {
+    uint32_t mid = (a + b + 1) >> 1;
+    if (eoff[mid] <= j) a = mid; else b = mid - 1;
+  }
+  uint32_t s = src[j], d = dst[j];
+  if (s >= nv[a] || d >= nv[a]) atomicOr(bad, 1u);
+  gsrc[j] = s + voff[a];
+  gdst[j] = d + voff[a];
+}
+
+__global__ void k_fill_vgraph(const uint32_t *voff, uint32_t n, uint32_t *vgraph) {
+  uint32_t i = blockIdx.x;
+  if (i >= n) return;
+  for (uint32_t x = voff[i] + threadIdx.x; x < voff[i + 1]; x += blockDim.x) vgraph[x] = i;
+}
+
+// combined [ncols][E] -> per-graph [ncols_i][E_i]
+__global__ void k_batch_split(const uint32_t *comb, uint64_t E, uint32_t ncols, const uint64_t *eoff, uint32_t n,
+                              uint32_t *const *outs, const uint32_t *ncols_i) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; idx < (uint64_t)ncols * E; idx += stride) {
+    uint32_t c = (uint32_t)(idx / E);
+    uint64_t e = idx - (uint64_t)c * E;
+    uint32_t a = 0, b = n - 1;
+    while (a < b) {
+      uint32_t mid = (a + b + 1) >> 1;
+      if (eoff[mid] <= e) a = mid; else b = mid - 1;
+    }
+    if (c < ncols_i[a]) {
+      uint64_t Ei = eoff[a + 1] - eoff[a];
+      outs[a][(uint64_t)c * Ei + (e - eoff[a])] = comb[idx];
+    }
+  }
+}
+
+uint32_t ncols_of(uint32_t patterns, uint32_t L) {
+  uint32_t c = 0;
+  if (patterns & AMLM_FAN_OUT) c++;
+  if (patterns & AMLM_FAN_IN) c++;
+  if (patterns & AMLM_SG) c++;
+  if (patterns & AMLM_GS) c++;
+  if (patterns & AMLM_CYCLES) c += L - 1;
+  return c;
+}
+
+}  // namespace
+
+#define A_TRY(x)                    \
+  do {                              \
+    amlm_status st_ = (x);          \
+    if (st_ != AMLM_OK) return st_; \
+  } while (0)
+
+static amlm_status balloc(amlm_graph *g, void **p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 256) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc failed in batch set-up");
+    return AMLM_E_NOMEM;
+  }
+  g->batch.allocs.push_back(*p);
+  return AMLM_OK;
+}
+
+void batch_free(amlm_graph *g) {
+  BatchState &B = g->batch;
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.cap_stream) (void)hipStreamDestroy(B.cap_stream);
+  for (void *p : B.allocs) (void)hipFree(p);
+  B = BatchState();
+}
+
+extern "C" amlm_status amlm_batch_create(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                                         const uint64_t *edge_offsets, const uint32_t *n_vertices,
+                                         uint32_t n_graphs, int inputs_on_device, void *hip_stream,
+                                         amlm_graph **out) {
+  if (!out || !edge_offsets || !n_vertices || n_graphs == 0) {
+    set_error("invalid batch description");
+    return AMLM_E_INVALID;
+  }
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (edge_offsets[0] != 0) {
+    set_error("edge_offsets[0] must be 0");
+    return AMLM_E_INVALID;
+  }
+  uint64_t vtot = 0;
+  for (uint32_t i = 0; i < n_graphs; i++) {
+    if (edge_offsets[i + 1] < edge_offsets[i]) {
+      set_error("edge_offsets must be non-decreasing");
+      return AMLM_E_INVALID;
+    }
+    vtot += n_vertices[i];
+  }
+  if (vtot >= 0xffffffffull) {
+    set_error("too many vertices in the batch");
+    return AMLM_E_INVALID;
+  }
+  const uint64_t E = edge_offsets[n_graphs];
+  // stage the inputs with global vertex ids, then build one store
+  amlm_graph tmp;  // owner of the staging buffers
+  uint32_t *d_src, *d_dst, *gsrc, *gdst, *d_nv, *d_voff, *bad;
+  uint64_t *d_eoff;
+  int64_t *d_ts;
+  std::vector<uint32_t> voff(n_graphs + 1, 0);
+  for (uint32_t i = 0; i < n_graphs; i++) voff[i + 1] = voff[i] + n_vertices[i];
+  A_TRY(balloc(&tmp, (void **)&gsrc, 4 * E));
+  A_TRY(balloc(&tmp, (void **)&gdst, 4 * E));
+  A_TRY(balloc(&tmp, (void **)&d_nv, 4 * n_graphs));
+  A_TRY(balloc(&tmp, (void **)&d_voff, 4 * (n_graphs + 1)));
+  A_TRY(balloc(&tmp, (void **)&d_eoff, 8 * (n_graphs + 1)));
+  A_TRY(balloc(&tmp, (void **)&bad, 4));
+  if (inputs_on_device) {
+    d_src = (uint32_t *)src;
+    d_dst = (uint32_t *)dst;
+    d_ts = (int64_t *)ts;
+  } else {
+    A_TRY(balloc(&tmp, (void **)&d_src, 4 * E));
+    A_TRY(balloc(&tmp, (void **)&d_dst, 4 * E));
+    A_TRY(balloc(&tmp, (void **)&d_ts, 8 * E));
+    if (E) {
+      HIP_TRY(hipMemcpyAsync(d_src, src, 4 * E, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(d_dst, dst, 4 * E, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(d_ts, ts, 8 * E, hipMemcpyHostToDevice, s));
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(d_nv, n_vertices, 4 * n_graphs, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_voff, voff.data(), 4 * (n_graphs + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_eoff, edge_offsets, 8 * (n_graphs + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_fill_u32(bad, 0, 1, s));
+  if (E) {
+    hipLaunchKernelGGL(k_batch_offsets, dim3((uint32_t)((E + 255) / 256)), dim3(256), 0, s, d_src, d_dst, E, d_eoff,
+                       d_voff, d_nv, n_graphs, gsrc, gdst, bad);
+    HIP_TRY(hipGetLastError());
+  }
+  uint32_t hbad = 0;
+  HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hbad) {
+    batch_free(&tmp);
+    set_error("an edge endpoint is outside its graph's vertex range");
+    return AMLM_E_INVALID;
+  }
+  amlm_graph *g = nullptr;
+  amlm_status st = amlm_graph_create(gsrc, gdst, d_ts, nullptr, E, (uint32_t)vtot, 1, hip_stream, &g);
+  batch_free(&tmp);
+  if (st != AMLM_OK) return st;
+  BatchState &B = g->batch;
+  B.n = n_graphs;
+  B.eoff.assign(edge_offsets, edge_offsets + n_graphs + 1);
+  B.voff = voff;
+  if ((st = balloc(g, (void **)&B.d_eoff, 8 * (n_graphs + 1))) != AMLM_OK ||
+      (st = balloc(g, (void **)&B.d_voff, 4 * (n_graphs + 1))) != AMLM_OK ||
+      (st = balloc(g, (void **)&B.vgraph, 4 * std::max<uint64_t>(vtot, 1))) != AMLM_OK ||
+      (st = balloc(g, (void **)&B.d_sub, sizeof(SubParams) * n_graphs)) != AMLM_OK ||
+      (st = balloc(g, (void **)&B.d_outs, sizeof(uint32_t *) * n_graphs)) != AMLM_OK ||
+      (st = balloc(g, (void **)&B.d_ncols, 4 * n_graphs)) != AMLM_OK) {
+    amlm_graph_destroy(g);
+    return st;
+  }
+  HIP_TRY(hipMemcpyAsync(B.d_eoff, edge_offsets, 8 * (n_graphs + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(B.d_voff, voff.data(), 4 * (n_graphs + 1), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_fill_vgraph, dim3(n_graphs), dim3(256), 0, s, B.d_voff, n_graphs, B.vgraph);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = g;
+  return AMLM_OK;
+}
+
+// Signature of a capture: everything that is baked into the launches.
+static std::string batch_signature(const amlm_graph *g, uint32_t patterns, uint32_t schedule, uint32_t Lmax,
+                                   const MineLaunch &cfg) {
+  std::ostringstream o;
+  o << patterns << "/" << schedule << "/" << Lmax << "/" << cfg.sg_blocks << "/" << cfg.sg_chunk << "/"
+    << cfg.cyc_blocks << "/" << cfg.learned_chunk << "/" << g->E << "/" << g->ms.cap_ev;
+  return o.str();
+}
+
+extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uint32_t *const *counts_dev,
+                                       void *hip_stream) {
+  if (!g || !ps || !counts_dev) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  BatchState &B = g->batch;
+  if (B.n == 0) {
+    set_error("not a batched graph store (use amlm_batch_create)");
+    return AMLM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  uint32_t Lmax = 2, kmin = ~0u;
+  std::vector<SubParams> sub(B.n);
+  std::vector<uint32_t> ncols(B.n);
+  for (uint32_t i = 0; i < B.n; i++) {
+    A_TRY(check_params(&ps[i]));
+    if (ps[i].patterns != ps[0].patterns || ps[i].schedule != ps[0].schedule) {
+      set_error("every graph of a batch must use the same patterns and schedule");
+      return AMLM_E_INVALID;
+    }
+    uint32_t L = (ps[i].patterns & AMLM_CYCLES) ? ps[i].max_cycle_len : 2;
+    sub[i].delta = ps[i].delta;
+    sub[i].L = L;
+    sub[i].k = ps[i].k ? ps[i].k : 1;
+    Lmax = std::max(Lmax, L);
+    kmin = std::min(kmin, sub[i].k);
+    ncols[i] = ncols_of(ps[i].patterns, L);
+    if (B.eoff[i + 1] > B.eoff[i] && !counts_dev[i]) {
+      set_error("null counts for a non-empty graph");
+      return AMLM_E_INVALID;
+    }
+  }
+  amlm_params pm = ps[0];
+  pm.max_cycle_len = Lmax;
+  pm.k = kmin;
+  const uint32_t nc_max = ncols_of(pm.patterns, Lmax);
+  A_TRY(alloc_mine_scratch(g));
+  if (!B.comb || B.comb_cols < nc_max) {
+    A_TRY(balloc(g, (void **)&B.comb, 4ull * nc_max * std::max<uint64_t>(g->E, 1)));
+    B.comb_cols = nc_max;
+  }
+  if (pm.schedule == AMLM_SCHED_LEARNED && !global_model().loaded) {
+    set_error("the learned schedule needs a cost model (amlm_costmodel_train or _load)");
+    return AMLM_E_INVALID;
+  }
+  // parameters and output pointers live in device memory read by the graph
+  HIP_TRY(hipMemcpyAsync(B.d_sub, sub.data(), sizeof(SubParams) * B.n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(B.d_outs, counts_dev, sizeof(uint32_t *) * B.n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(B.d_ncols, ncols.data(), 4 * B.n, hipMemcpyHostToDevice, s));
+  MineParams mp = make_params(g, &pm, B.comb, nullptr);
+  mp.vgraph = B.vgraph;
+  mp.sub = B.d_sub;
+  MineLaunch cfg = default_launch(g);
+  if (pm.schedule == AMLM_SCHED_LEARNED) {
+    cfg.learned = true;
+    cfg.delta_hours = (float)pm.delta / 3600.f;
+    cfg.bb = &g->bb;
+  }
+  std::string sig = batch_signature(g, pm.patterns, pm.schedule, Lmax, cfg);
+  if (!B.exec || sig != B.sig) {
+    if (B.exec) {
+      (void)hipGraphExecDestroy(B.exec);
+      B.exec = nullptr;
+    }
+    if (!B.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = B.cap_stream;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_fill_u32(B.comb, 0, (uint64_t)nc_max * g->E, cs);
+    if (e == hipSuccess) e = mine_launch(mp, g->ms, cfg, cs, nullptr);
+    if (e == hipSuccess && g->E) {
+      hipLaunchKernelGGL(k_batch_split, dim3(4 * device_info().num_cu), dim3(256), 0, cs, B.comb, g->E, nc_max,
+                         B.d_eoff, B.n, B.d_outs, B.d_ncols);
+      e = hipGetLastError();
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      set_error(std::string("batch capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+      return AMLM_E_DEVICE;
+    }
+    e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      B.exec = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      return AMLM_E_DEVICE;
+    }
+    B.sig = sig;
+    B.captures++;
+  }
+  HIP_TRY(hipGraphLaunch(B.exec, s));
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_batch_info(const amlm_graph *g, uint32_t *n_graphs, uint32_t *captures) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  if (n_graphs) *n_graphs = g->batch.n;
+  if (captures) *captures = g->batch.captures;
+  return AMLM_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+static std::string tune_key(const amlm_graph *g, const amlm_params *ps, uint32_t n) {
+  std::ostringstream o;
+  o << device_info().name << ":" << device_info().num_cu << ":E" << g->E << ":V" << g->V << ":G"
+    << std::max(1u, g->batch.n) << ":P" << ps[0].patterns << ":S" << ps[0].schedule;
+  uint32_t Lmax = 0;
+  for (uint32_t i = 0; i < n; i++) Lmax = std::max(Lmax, ps[i].max_cycle_len);
+  o << ":L" << Lmax;
+  return o.str();
+}
+
+static bool cache_lookup(const char *path, const std::string &key, TuneParams *t) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    // one entry per line:  "key": [sg_chunk, sg_blocks, cyc_blocks, ms],
+    size_t q = line.find('"');
+    if (q == std::string::npos) continue;
+    size_t q2 = line.find('"', q + 1);
+    if (q2 == std::string::npos || line.substr(q + 1, q2 - q - 1) != key) continue;
+    unsigned a, b, c;
+    size_t br = line.find('[', q2);
+    if (br != std::string::npos && sscanf(line.c_str() + br, "[%u, %u, %u", &a, &b, &c) == 3) {
+      t->sg_chunk = a;
+      t->sg_blocks = b;
+      t->cyc_blocks = c;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void cache_store(const char *path, const std::string &key, const TuneParams &t, double ms) {
+  if (!path) return;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+      size_t q = line.find('"');
+      if (q == std::string::npos) continue;
+      size_t q2 = line.find('"', q + 1);
+      if (q2 != std::string::npos && line.substr(q + 1, q2 - q - 1) == key) continue;
+      std::string l = line;
+      while (!l.empty() && (l.back() == ',' || l.back() == ' ')) l.pop_back();
+      lines.push_back(l);
+    }
+  }
+  char buf[512];
+  snprintf(buf, sizeof(buf), "  \"%s\": [%u, %u, %u, %.4f]", key.c_str(), t.sg_chunk, t.sg_blocks, t.cyc_blocks, ms);
+  lines.push_back(buf);
+  std::ofstream o(path);
+  o << "{\n";
+  for (size_t i = 0; i < lines.size(); i++) o << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+  o << "}\n";
+}
+
+extern "C" amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint32_t n_params,
+                                     uint32_t *const *counts_dev, const char *cache_path, void *hip_stream,
+                                     uint32_t *chosen) {
+  if (!g || !ps || !counts_dev || n_params == 0) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  const bool batched = g->batch.n > 0;
+  if (batched && n_params != g->batch.n) {
+    set_error("a batched store needs one parameter set per graph");
+    return AMLM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::string key = tune_key(g, ps, n_params);
+  TuneParams best;
+  if (cache_lookup(cache_path, key, &best)) {
+    g->tune = best;
+  } else {
+    DeviceInfo &di = device_info();
+    const uint32_t chunks[] = {16, 32, 64};
+    const uint32_t sg_full = (uint32_t)(di.num_cu * di.sg_occ), cyc_full = (uint32_t)(di.num_cu * di.cyc_occ);
+    const uint32_t grids[][2] = {{sg_full, cyc_full}, {sg_full / 2, cyc_full / 2}};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best_ms = 1e30;
+    for (uint32_t ch : chunks) {
+      for (auto &gr : grids) {
+        g->tune.sg_chunk = ch;
+        g->tune.sg_blocks = std::max(1u, gr[0]);
+        g->tune.cyc_blocks = std::max(1u, gr[1]);
+        std::vector<float> ts;
+        for (int rep = 0; rep < 4; rep++) {
+          HIP_TRY(hipEventRecord(e0, s));
+          amlm_status st = batched ? amlm_mine_batch(g, ps, counts_dev, s) : amlm_mine(g, ps, counts_dev[0], s);
+          if (st != AMLM_OK) return st;
+          HIP_TRY(hipEventRecord(e1, s));
+          HIP_TRY(hipEventSynchronize(e1));
+          float ms = 0;
+          HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) ts.push_back(ms);  // the first run pays the capture
+        }
+        std::sort(ts.begin(), ts.end());
+        double med = ts[ts.size() / 2];
+        if (med < best_ms) {
+          best_ms = med;
+          best = g->tune;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->tune = best;
+    cache_store(cache_path, key, best, best_ms);
+  }
+  if (chosen) {
+    chosen[0] = g->tune.sg_chunk;
+    chosen[1] = g->tune.sg_blocks;
+    chosen[2] = g->tune.cyc_blocks;
+  }
+  return AMLM_OK;
+}

@@ -25,10 +25,18 @@ constexpr uint32_t kCtrCycWork = 1;
 constexpr uint32_t kCtrNSg = 32, kCtrNCy = 33;
 constexpr uint32_t kCtrWords = 64;
 
+// Per-sub-graph parameters of a batched store (see batch.hip).
+struct SubParams {
+  int64_t delta;
+  uint32_t L, k;
+};
+
 struct MineParams {
   GraphView g;
   int64_t delta;
-  uint32_t L, k;
+  uint32_t L, k;          // L: the largest cycle length over all sub-graphs
+  const uint32_t *vgraph; // batched store: sub-graph of each vertex (else NULL)
+  const SubParams *sub;   // batched store: parameters per sub-graph
   int col_fo, col_fi, col_sg, col_gs, col_cyc;  // -1 when not requested
   uint32_t *counts;
   uint64_t stride;   // row stride of counts (= number of edges)
@@ -92,3 +100,14 @@ constexpr uint32_t kBytesScatterEntry = 4;   // out-window of u after tau: previ
 constexpr uint32_t kBytesPathNode = 16;      // a partial path (head, time, edge, parent)
 constexpr uint32_t kBytesPathEntry = 12;     // out-slice entry of a path head: neighbour, time, edge id
 constexpr uint32_t kBytesClosureSearch = 16; // closing-edge binary search result
+
+// Window, cycle length and threshold of the (sub-)graph that vertex x belongs to.
+__device__ __forceinline__ int64_t delta_of(const MineParams &mp, uint32_t x) {
+  return mp.vgraph ? mp.sub[mp.vgraph[x]].delta : mp.delta;
+}
+__device__ __forceinline__ uint32_t L_of(const MineParams &mp, uint32_t x) {
+  return mp.vgraph ? mp.sub[mp.vgraph[x]].L : mp.L;
+}
+__device__ __forceinline__ uint32_t k_of(const MineParams &mp, uint32_t x) {
+  return mp.vgraph ? mp.sub[mp.vgraph[x]].k : mp.k;
+}

@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags_sg
   uint32_t eid = g.anc[p];
   uint32_t u = g.src[eid], v = g.dst[eid];
   int32_t t = g.t[eid];
-  int32_t lo = window_lo(t, mp.delta);
+  int32_t lo = window_lo(t, delta_of(mp, u));
+  const uint32_t k = k_of(mp, u);
   uint8_t f = 0;
   uint32_t fan_out = 0;
   if (mp.col_fo >= 0 || feat) {
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags_sg
         uint32_t ns = 0;
         for (uint32_t j = p0; j < p1; j++) ns += (g.in_nbr[j] != v) & (g.in_nxt[j] >= t);
         if (ns > 0) {
-          if (mp.k == 1) {
+          if (k == 1) {
             // every sender has u as its first intermediate and v is always a
             // scatter destination after the first gather: SG_1 = GS_1 = |S|
             if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = ns;
@@ -124,6 +125,7 @@ struct SgLds {
   uint32_t seg_off[AMLM_WAVE];  // exclusive offsets of the segment's sender windows
   int32_t i_t[AMLM_WAVE], i_lo[AMLM_WAVE], i_tau[AMLM_WAVE];
   uint32_t i_r0[AMLM_WAVE], i_r1[AMLM_WAVE];  // v's in-window [lo, t] of each anchor
+  uint32_t i_k[AMLM_WAVE];                    // threshold k of each anchor
   // (anchor, sender) pairs of one batch
   uint32_t pr_item[AMLM_WAVE], pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
   // Bloom-positive candidates awaiting the exact check
@@ -210,10 +212,11 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
 // its slice [pr_b, pr_b + pr_n) of the sender's out-row.  Long slices are
 // scanned one pair at a time by the whole wave with the pair's fields in
 // scalar registers; short ones are flattened over the lanes.
-__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre) {
+__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre,
+                        uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
-  const uint32_t need = mp.k - 1;  // intermediates needed besides u
+  const uint32_t need = k - 1;  // intermediates needed besides u
   uint32_t cq = 0;
   constexpr int U = kJoinUnroll;  // independent 256-byte loads in flight per wave
   const uint32_t my_n = lane < np ? L.pr_n[lane] : 0u;
@@ -270,7 +273,8 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
   const uint32_t nit = s1 - s0;
-  const bool need_join = mp.col_sg >= 0 && mp.k >= 2;
+  const uint32_t k = rfl(L.i_k[s0]);  // the anchors of a segment share v, hence the (sub-)graph
+  const bool need_join = mp.col_sg >= 0 && k >= 2;
   int shift = 0;
   uint32_t vrs = rfl(g.in_ptr[v]), vre = rfl(g.in_ptr[v + 1]);
   if (need_join) {
@@ -344,13 +348,13 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
       L.pr_n[slot] = n;
       L.pr_cnt[slot] = 0;
     }
-    sg_join(mp, L, np, shift, vrs, vre);
-    if (lane < np && L.pr_cnt[lane] >= mp.k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
+    sg_join(mp, L, np, shift, vrs, vre, k);
+    if (lane < np && L.pr_cnt[lane] >= k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
   }
 }
 
 // Gather-scatter for one anchor when the lane-serial scan hit its cap.
-__device__ uint32_t gs_wave(const MineParams &mp, uint32_t u, int32_t tau, int32_t t, uint32_t *work) {
+__device__ uint32_t gs_wave(const MineParams &mp, uint32_t u, int32_t tau, int32_t t, uint32_t k, uint32_t *work) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   uint32_t rs = rfl(g.out_ptr[u]), re = rfl(g.out_ptr[u + 1]);
@@ -362,7 +366,7 @@ __device__ uint32_t gs_wave(const MineParams &mp, uint32_t u, int32_t tau, int32
     bool first = j < d1 && g.out_prv[j] <= tau;  // first (u, d) edge after tau
     nd += __popcll(__ballot(first));
     *work += kBytesScatterEntry * min((uint32_t)AMLM_WAVE, d1 - c);
-    if (nd >= mp.k) break;
+    if (nd >= k) break;
   }
   return nd;
 }
@@ -376,8 +380,6 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint32_t n_items = *n_items_p;
-  const uint32_t k = mp.k;
-  const int32_t seg_span = (int32_t)max((int64_t)1, min(mp.delta / 4, (int64_t)0x40000000));
   chunk = min(chunk, (uint32_t)AMLM_WAVE);
   const uint32_t n_chunks = (n_items + chunk - 1) / chunk;
   for (;;) {
@@ -390,6 +392,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
     const uint32_t base = (chunk_tab ? chunk_tab[c] : c) * chunk;
     const uint32_t nr = min(chunk, n_items - base);
     uint32_t v = 0xffffffffu;
+    int64_t dl = 1;
     if (lane < nr) {
       uint32_t q = items[base + lane];
       uint32_t eid = g.in_eid[q];
@@ -401,7 +404,9 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       L.i_eid[lane] = eid;
       L.i_u[lane] = g.in_nbr[q];
       L.i_t[lane] = t;
-      L.i_lo[lane] = window_lo(t, mp.delta);
+      dl = delta_of(mp, v);
+      L.i_lo[lane] = window_lo(t, dl);
+      L.i_k[lane] = k_of(mp, v);
       L.i_p0[lane] = pw.x;
       L.i_wlen[lane] = pw.y - pw.x;
       L.i_ns[lane] = 0;
@@ -411,6 +416,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
     }
     // segments: runs of anchors into the same v inside one time bucket of
     // width delta / 4, so that a segment's gather window stays short
+    const int32_t seg_span = (int32_t)max((int64_t)1, min(dl / 4, (int64_t)0x40000000));
     int32_t tb = lane < nr ? L.i_t[lane] / seg_span : 0;
     uint32_t vprev = __shfl_up(v, 1, AMLM_WAVE);
     int32_t tbprev = __shfl_up(tb, 1, AMLM_WAVE);
@@ -425,9 +431,10 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
     // gather-scatter and the outputs, one lane per anchor
     uint32_t sg = 0, gs = 0;
     bool gs_wide = false;
-    uint32_t ns = 0, u = 0, work = 0;
+    uint32_t ns = 0, u = 0, work = 0, k = 1;
     int32_t tau = 0, t = 0;
     if (lane < nr) {
+      k = L.i_k[lane];
       ns = L.i_ns[lane];
       sg = k == 1 ? ns : L.i_sg[lane];
       u = L.i_u[lane];
@@ -455,11 +462,12 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       wide &= wide - 1;
       uint32_t ua = rfl((uint32_t)__shfl(u, a, AMLM_WAVE));
       int32_t ta = rfl(__shfl(tau, a, AMLM_WAVE)), tt = rfl(__shfl(t, a, AMLM_WAVE));
+      uint32_t ka = rfl((uint32_t)__shfl(k, a, AMLM_WAVE));
       uint32_t wk = 0;
-      uint32_t nd = gs_wave(mp, ua, ta, tt, &wk);
+      uint32_t nd = gs_wave(mp, ua, ta, tt, ka, &wk);
       if (lane == a) {
         work += wk;
-        if (nd >= k) gs = ns;
+        if (nd >= ka) gs = ns;
       }
     }
     if (lane < nr) {
@@ -490,7 +498,7 @@ struct CycFrame {
 };
 
 struct CycLds {
-  uint32_t r_eid[AMLM_WAVE], r_u[AMLM_WAVE];
+  uint32_t r_eid[AMLM_WAVE], r_u[AMLM_WAVE], r_L[AMLM_WAVE];
   int32_t r_t[AMLM_WAVE];
   CycFrame fr[kMaxDepth + 1];
 };
@@ -528,14 +536,15 @@ __device__ void cyc_prepare(const MineParams &mp, CycLds &S, uint32_t i) {
     int32_t t = S.r_t[r];
     uint32_t h = F.vert[lane];
     int32_t tau = F.tau[lane];
-    if (i + 2 == mp.L) {
+    const uint32_t Lr = S.r_L[r];
+    if (i + 2 == Lr) {
       uint32_t urs = g.in_ptr[u], ure = g.in_ptr[u + 1];
       int32_t tl = tau + 1 < 0 ? 0 : tau + 1;
       uint32_t qa = lower_bound_u64(g.inn_key, urs, ure, nbr_key(h, tl));
       uint32_t qb = lower_bound_u64(g.inn_key, qa, ure, nbr_key(h, t));
       if (qb > qa) {
-        cyc_credit_path(mp, S, i, lane, mp.L, qb - qa);
-        uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)mp.L - 2) * mp.stride;
+        cyc_credit_path(mp, S, i, lane, Lr, qb - qa);
+        uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)Lr - 2) * mp.stride;
         for (uint32_t q = qa; q < qb; q++) credit(col + g.inn_eid[q], 1u, mp.err);
       }
       if (mp.work) atomicAdd(&mp.work[mp.stride + S.r_eid[r]], kBytesClosureSearch);
@@ -563,7 +572,6 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
-  const uint32_t Lmax = mp.L;
   const uint32_t n_in = *n_in_p;
   for (;;) {
     uint32_t base = 0;
@@ -575,15 +583,17 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
       uint32_t eid = g.anc[roots[base + lane]];  // time-order position of the anchor
       uint32_t v = g.dst[eid];
       int32_t t = g.t[eid];
+      uint32_t u = g.src[eid];
       S.r_eid[lane] = eid;
-      S.r_u[lane] = g.src[eid];
+      S.r_u[lane] = u;
       S.r_t[lane] = t;
+      S.r_L[lane] = L_of(mp, u);
       CycFrame &F0 = S.fr[0];
       F0.par[lane] = lane;
       F0.root[lane] = lane;
       F0.eid[lane] = 0xffffffffu;
       F0.vert[lane] = v;
-      F0.tau[lane] = window_lo(t, mp.delta) - 1;  // first hop at time >= lo
+      F0.tau[lane] = window_lo(t, delta_of(mp, u)) - 1;  // first hop at time >= lo
     }
     if (lane == 0) S.fr[0].n = nr;
     cyc_prepare(mp, S, 0);
@@ -612,7 +622,7 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
           // closing hop: a cycle of sp + 2 edges
           cyc_credit_path(mp, S, sp, a, sp + 2, 1u);
           credit(mp.counts + (uint64_t)(mp.col_cyc + sp) * mp.stride + g.out_eid[pos], 1u, mp.err);
-        } else if ((uint32_t)sp + 3 <= Lmax && !cyc_on_path(S, sp, a, w)) {
+        } else if ((uint32_t)sp + 3 <= S.r_L[F.root[a]] && !cyc_on_path(S, sp, a, w)) {
           child = true;
           ceid = g.out_eid[pos];
           ctau = g.out_t[pos];

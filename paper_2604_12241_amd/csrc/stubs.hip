@@ -6,10 +6,6 @@ static amlm_status not_built(const char *what) {
   return AMLM_E_INVALID;
 }
 
-extern "C" amlm_status amlm_mine_batch(amlm_graph *const *, const amlm_params *, uint32_t *const *, uint32_t,
-                                       void *) {
-  return not_built("amlm_mine_batch");
-}
 extern "C" amlm_status amlm_server_create(amlm_graph *, const amlm_params *, uint64_t, uint32_t, amlm_server **) {
   return not_built("amlm_server_create");
 }
