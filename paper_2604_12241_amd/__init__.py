@@ -268,6 +268,57 @@ def amlm_autotune(g: Graph, ps, outs, cache_path=None, stream=None):
     return list(chosen)
 
 
+class Server:
+    """Continuous-batching server over a resident graph (amlm_server_*)."""
+
+    def __init__(self, resident: Graph, p: amlm_params, hbm_budget: int = 0, max_slots: int = 4):
+        self.handle = ctypes.c_void_p()
+        self.p = p
+        self.ncols = amlm_num_columns(p)
+        _check(lib().amlm_server_create(resident.handle, ctypes.byref(p), int(hbm_budget), int(max_slots),
+                                        ctypes.byref(self.handle)))
+        self.sizes = {}
+
+    def submit(self, src, dst, ts, wait: bool = False) -> int:
+        src = np.ascontiguousarray(src, np.uint32)
+        dst = np.ascontiguousarray(dst, np.uint32)
+        ts = np.ascontiguousarray(ts, np.int64)
+        t = ctypes.c_uint64()
+        _check(lib().amlm_server_submit(self.handle, _ptr(src), _ptr(dst), _ptr(ts), src.shape[0],
+                                        1 if wait else 0, ctypes.byref(t)))
+        self.sizes[t.value] = src.shape[0]
+        return t.value
+
+    def wait(self, ticket: int, cap: int = 1 << 22):
+        n = self.sizes[ticket]
+        counts = np.zeros((self.ncols, n), np.uint32)
+        nd = ctypes.c_uint64()
+        de = np.zeros(cap, np.uint64)
+        dc = np.zeros(cap, np.uint32)
+        dv = np.zeros(cap, np.uint32)
+        _check(lib().amlm_server_wait(self.handle, ticket, _ptr(counts), ctypes.byref(nd), _ptr(de), _ptr(dc),
+                                      _ptr(dv), cap))
+        m = min(nd.value, cap)
+        return counts, (de[:m], dc[:m], dv[:m]), nd.value
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().amlm_server_ticket_times(self.handle, ticket, ctypes.byref(a), ctypes.byref(b),
+                                              ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def close(self):
+        if self.handle:
+            lib().amlm_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 MLP_PARAMS = 5057
 MLP_F = 12
 

@@ -316,6 +316,7 @@ MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *coun
   mp.k = p->k ? p->k : 1;
   mp.vgraph = nullptr;
   mp.sub = nullptr;
+  mp.anchor_lo = 0;
   int c = 0;
   mp.col_fo = (p->patterns & AMLM_FAN_OUT) ? c++ : -1;
   mp.col_fi = (p->patterns & AMLM_FAN_IN) ? c++ : -1;
@@ -342,7 +343,7 @@ MineLaunch default_launch(const amlm_graph *g) {
 }
 
 amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t anchor_lo) {
   if (!g) {
     set_error("null graph");
     return AMLM_E_INVALID;
@@ -361,6 +362,7 @@ amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_de
   if (work_dev) HIP_TRY(launch_fill_u32(work_dev, 0, 2 * g->E, s));
   A_TRY(alloc_mine_scratch(g));
   MineParams mp = make_params(g, p, counts_dev, work_dev);
+  mp.anchor_lo = anchor_lo;
   MineLaunch cfg = default_launch(g);
   if (p->schedule == AMLM_SCHED_LEARNED) {
     if (!global_model().loaded) {

@@ -1,6 +1,7 @@
 // Host-side graph handle and helpers shared by the C ABI translation units.
 #pragma once
 
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -64,5 +65,6 @@ GraphView graph_view(const amlm_graph *g);
 MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, uint32_t *work);
 MineLaunch default_launch(const amlm_graph *g);
 amlm_status alloc_mine_scratch(amlm_graph *g);
+// Mining with the edges of id >= anchor_lo as the only anchors (0 = all).
 amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t anchor_lo = 0);

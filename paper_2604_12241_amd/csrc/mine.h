@@ -37,6 +37,7 @@ struct MineParams {
   uint32_t L, k;          // L: the largest cycle length over all sub-graphs
   const uint32_t *vgraph; // batched store: sub-graph of each vertex (else NULL)
   const SubParams *sub;   // batched store: parameters per sub-graph
+  uint32_t anchor_lo;     // only edges with id >= anchor_lo are anchors (0 = all)
   int col_fo, col_fi, col_sg, col_gs, col_cyc;  // -1 when not requested
   uint32_t *counts;
   uint64_t stride;   // row stride of counts (= number of edges)

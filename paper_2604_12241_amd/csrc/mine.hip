@@ -41,6 +41,7 @@ __global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags_sg
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.Ev) return;
   uint32_t eid = g.anc[p];
+  if (eid < mp.anchor_lo) return;  // context edge (incremental mining)
   uint32_t u = g.src[eid], v = g.dst[eid];
   int32_t t = g.t[eid];
   int32_t lo = window_lo(t, delta_of(mp, u));
