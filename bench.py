@@ -29,6 +29,22 @@ WORKLOADS = {
 }
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    summary, or None if the mining source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_large32M.json")
+    src = os.path.join(ROOT, "paper_2604_12241_amd", "csrc", "mine.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    except (OSError, ValueError):
+        return None
+    if rec.get("mine_hip_sha1") != sha:
+        return None
+    return rec.get("traffic_bytes_per_dispatch", {}).get(kernel)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -42,11 +58,15 @@ def make_workload(name):
     return g, delta, L, k
 
 
-def train_cost_model(delta, L, k, n_graphs=4):
+def train_cost_model(delta, L, k, n_graphs=4, cache=None):
     """Cost model trained (untimed) on graphs of the 5M-edge generator
     (seeds 202..), labels from the plain miner's work counters."""
     import paper_2604_12241_amd as A
     from paper_2604_12241_amd import workloads as W
+    if cache and os.path.exists(cache):
+        A.amlm_costmodel_load(cache)
+        log(f"[bench] cost model loaded from {cache}")
+        return
     t0 = time.time()
     Gs = []
     for i in range(n_graphs):
@@ -56,6 +76,88 @@ def train_cost_model(delta, L, k, n_graphs=4):
     for G in Gs:
         G.close()
     log(f"[bench] cost model trained on {n_graphs} graphs of 5M edges in {time.time() - t0:.1f}s")
+    if cache:
+        A.amlm_costmodel_save(cache)
+
+
+def bench_serving(A, G, g, p, n_batches=40, slots=4):
+    """Config-5 style serving: the graph resident, stream batches of 1k-100k
+    edges (log-uniform) strictly after its end; a saturation run gives the
+    sustained rate, then Poisson arrivals at 50 % and 80 % of it give the
+    p50 / p99 batch latency (submit -> results ready)."""
+    from paper_2604_12241_amd import workloads as W
+    t0 = time.time()
+    batches = W.stream_batches(g, seed=505, n_batches=3 * n_batches + 4)
+    log(f"[bench] generated {len(batches)} stream batches in {time.time() - t0:.1f}s")
+    S = A.Server(G, p, hbm_budget=0, max_slots=slots)
+    it = iter(batches)
+    for _ in range(4):                       # warm the slots
+        b = next(it)
+        S.wait(S.submit(b.src, b.dst, b.ts))
+    # saturation: everything submitted at once
+    sat = [next(it) for _ in range(n_batches)]
+    t_a = time.perf_counter()
+    tk = [S.submit(b.src, b.dst, b.ts) for b in sat]
+    for t in tk:
+        S.wait(t)
+    t_b = time.perf_counter()
+    sustained = sum(b.n_edges for b in sat) / (t_b - t_a)
+    mean_edges = float(np.mean([b.n_edges for b in batches]))
+    rng = np.random.default_rng(7)
+    res = {"sustained_edges_per_s": sustained, "slots": slots, "batches_per_load": n_batches,
+           "batch_edges": "log-uniform 1e3..1e5"}
+    for frac in (0.5, 0.8):
+        rate = frac * sustained / mean_edges          # batches per second
+        bs = [next(it) for _ in range(n_batches)]
+        gaps = rng.exponential(1.0 / rate, len(bs))
+        tk = []
+        start = time.perf_counter()
+        due = start
+        for b, gap in zip(bs, gaps):
+            due += gap
+            while time.perf_counter() < due:
+                time.sleep(min(0.0005, max(0.0, due - time.perf_counter())))
+            tk.append(S.submit(b.src, b.dst, b.ts))
+        lat = []
+        for t in tk:
+            S.wait(t)
+            a, _, c = S.times(t)
+            lat.append((c - a) * 1e3)
+        res[f"load_{int(frac * 100)}"] = {"p50_ms": float(np.percentile(lat, 50)),
+                                          "p99_ms": float(np.percentile(lat, 99)),
+                                          "offered_edges_per_s": frac * sustained}
+    S.close()
+    return res
+
+
+def bench_batching(A, n_graphs=256, steps=5):
+    """Config-3 style batching: 256 independent graphs of 1k-200k edges
+    (log-uniform), windows of 6 h / 24 h / 72 h, in one batched store mined by
+    one captured launch; chunk / grid autotuned (cached per device)."""
+    import torch
+    from paper_2604_12241_amd import workloads as W
+    t0 = time.time()
+    subs = W.batch_subgraphs(n_graphs)
+    log(f"[bench] generated {n_graphs} sub-graphs ({sum(g.n_edges for g, _ in subs)} edges) in "
+        f"{time.time() - t0:.1f}s")
+    B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices) for g, _ in subs])
+    ps = [A.params(A.AMLM_ALL, d, 6, 2) for _, d in subs]
+    outs = [torch.empty((A.amlm_num_columns(q), int(B.sizes[i])), dtype=torch.int32, device="cuda")
+            for i, q in enumerate(ps)]
+    chosen = A.amlm_autotune(B, ps, outs, os.path.join(os.environ.get("TMPDIR", "/tmp"), "amlm_autotune.json"))
+    A.amlm_mine_batch(B, ps, outs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        A.amlm_mine_batch(B, ps, outs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / steps
+    E = B.n_edges
+    n, captures = B.info_batch()
+    B.close()
+    return {"edges_per_s": E / dt, "ms_per_launch": dt * 1e3, "graphs": n, "edges": E,
+            "autotuned": {"chunk": chosen[0], "sg_blocks": chosen[1], "cyc_blocks": chosen[2]},
+            "hipgraph_captures": captures}
 
 
 def cpu_baseline(g, delta, L, k, target_s=12.0):
@@ -82,6 +184,11 @@ def main():
     ap.add_argument("--schedule", default="learned", choices=["static", "learned"])
     ap.add_argument("--train-graphs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--model-cache", default=None, help="load / save the trained cost model here")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: no comparisons, plus a 1 GiB copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -99,8 +206,10 @@ def main():
     ts = torch.from_numpy(g.ts).to(dev)
     stream = torch.cuda.current_stream()
     sched = A.AMLM_SCHED_LEARNED if args.schedule == "learned" else A.AMLM_SCHED_STATIC
+    if args.profile:
+        args.no_serve = args.no_batch = args.no_cpu_baseline = True
     if sched == A.AMLM_SCHED_LEARNED:
-        train_cost_model(delta, L, k, args.train_graphs)
+        train_cost_model(delta, L, k, args.train_graphs, args.model_cache)
     p = A.params(A.AMLM_ALL, delta, L, k, sched)
     p_static = A.params(A.AMLM_ALL, delta, L, k, A.AMLM_SCHED_STATIC)
     G = A.Graph(src, dst, ts, g.n_vertices)
@@ -138,7 +247,13 @@ def main():
     dt, avg = timed(p, args.steps)
     mine_ms = sum(avg.get(s, 0.0) for s in ("anchor", "lists", "sg", "cyc", "model"))
     static = None
-    if sched == A.AMLM_SCHED_LEARNED:
+    if args.profile:
+        # copy probe: 1 GiB read + 1 GiB written by the library's copy kernel
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        A.amlm_copy(b, a)
+        torch.cuda.synchronize()
+    elif sched == A.AMLM_SCHED_LEARNED:
         # the static schedule on the same graph and clock, for the comparison
         check = counts.clone()
         step(p_static)
@@ -154,7 +269,9 @@ def main():
     achieved = cand[dom] / (avg[dom] * 1e-3) / 1e9
     roof = {"kernel": {"sg": "k_sg", "cyc": "k_cyc"}[dom], "bound": "hbm", "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "algorithmic_bytes": cand[dom], "avg_ms": avg[dom], "traffic": None}
+            "algorithmic_bytes": cand[dom], "avg_ms": avg[dom],
+            "traffic": recorded_traffic({"sg": "k_sg", "cyc": "k_cyc"}[dom]),
+            "traffic_source": "profiles/mining_large32M.md (FETCH_SIZE x2.0 + WRITE_SIZE, copy-kernel calibrated)"}
 
     out = {
         "metric": METRIC, "value": E / dt, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
@@ -170,6 +287,11 @@ def main():
     if static is not None:
         out["static_schedule"] = static
         out["learned_over_static"] = (E / dt) / static["value"]
+    if not args.no_serve:
+        out["stream"] = bench_serving(A, G, g, p)
+        out["p99_stream_latency_ms"] = out["stream"]["load_80"]["p99_ms"]
+    if not args.no_batch:
+        out["batching"] = bench_batching(A)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, delta, L, k)

@@ -280,6 +280,11 @@ amlm_status amlm_server_ticket_times(amlm_server *s, uint64_t ticket, double *t_
 
 void amlm_server_destroy(amlm_server *s);
 
+/* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
+ * pointers) by the library's own streaming kernel: the achievable-bandwidth
+ * probe and the calibration of the hardware byte counters.  Asynchronous. */
+amlm_status amlm_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
+
 /* Thread-local message describing the last error on this thread. */
 const char *amlm_last_error(void);
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "amlm_server_create", "amlm_server_submit", "amlm_server_wait", "amlm_server_ticket_times",
     "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
-    "amlm_batch_create", "amlm_batch_info", "amlm_autotune",
+    "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy",
 ]
 
 
@@ -71,6 +71,7 @@ def lib():
             "amlm_batch_create": (st, [p, p, p, p, p, u32, ctypes.c_int, p, ctypes.POINTER(p)]),
             "amlm_batch_info": (st, [p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
             "amlm_autotune": (st, [p, pp, u32, p, ctypes.c_char_p, p, p]),
+            "amlm_copy": (st, [p, p, u64, p]),
             "amlm_costmodel_train": (st, [p, pp, u32, u32, u32, u64, ctypes.c_char_p, p]),
             "amlm_costmodel_load": (st, [ctypes.c_char_p]),
             "amlm_costmodel_save": (st, [ctypes.c_char_p]),
@@ -363,6 +364,10 @@ def amlm_mlp_grad(w, x, y):
     loss = ctypes.c_float()
     _check(lib().amlm_mlp_grad(_ptr(w), _ptr(x), _ptr(y), x.shape[0], _ptr(g), ctypes.byref(loss)))
     return g, loss.value
+
+
+def amlm_copy(dst, src, stream=None):
+    _check(lib().amlm_copy(_ptr(dst), _ptr(src), src.numel() * src.element_size(), _stream_handle(stream)))
 
 
 def to_u32(t) -> np.ndarray:

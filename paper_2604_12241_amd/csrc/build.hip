@@ -396,3 +396,29 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
 #undef CK
   return hipSuccess;
 }
+
+// ---------------------------------------------------------------- copy probe
+namespace {
+// Plain streaming copy (16-byte vector loads and stores, grid-stride): the
+// achievable-bandwidth probe and the byte-count calibration for the
+// hardware traffic counters.
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, uint64_t n16) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+}  // namespace
+
+extern "C" amlm_status amlm_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream) {
+  if (bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) {
+    set_error("amlm_copy needs 16-byte aligned pointers and sizes");
+    return AMLM_E_INVALID;
+  }
+  uint64_t n16 = bytes / 16;
+  if (!n16) return AMLM_OK;
+  uint32_t blocks = (uint32_t)std::min<uint64_t>((n16 + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream, (const uint4 *)src, (uint4 *)dst,
+                     n16);
+  HIP_TRY(hipGetLastError());
+  return AMLM_OK;
+}
