@@ -84,6 +84,7 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&a.out_eid, 4 * e));
   A_TRY(dalloc(g, (void **)&a.out_t, 4 * e));
   A_TRY(dalloc(g, (void **)&a.out_prv, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.out_src, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_ptr, 4 * v1));
   A_TRY(dalloc(g, (void **)&a.in_nbr, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_eid, 4 * e));
@@ -113,17 +114,17 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
 amlm_status alloc_mine_scratch(amlm_graph *g) {
   MineScratch &ms = g->ms;
   uint64_t ev = std::max<uint64_t>(g->Ev, 1);
-  if (ms.flags && ms.cap_ev >= ev) return AMLM_OK;
+  if (ms.flags && ms.cap_ev >= ev && ms.cap_e >= g->E) return AMLM_OK;
   if (ms.flags) {
     // grow: the old buffers stay owned by the graph until it is freed
   }
-  uint32_t nb = (uint32_t)((ev + kFlagTile - 1) / kFlagTile);
-  A_TRY(dalloc(g, (void **)&ms.flags, 2 * ((ev + 3) & ~3ull)));
+  uint32_t nb = (uint32_t)((std::max<uint64_t>(ev, g->E) + kFlagTile - 1) / kFlagTile);
+  A_TRY(dalloc(g, (void **)&ms.flags, ((ev + 3) & ~3ull) + ((std::max<uint64_t>(g->E, 1) + 3) & ~3ull)));
   A_TRY(dalloc(g, (void **)&ms.sg_win, 16 * ev));
   A_TRY(dalloc(g, (void **)&ms.feat, 4 * kMlpRaw * ev));
   A_TRY(dalloc(g, (void **)&ms.pred, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.list_sg, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * ev));
+  A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * std::max<uint64_t>(g->E, 1)));
   A_TRY(dalloc(g, (void **)&ms.bcnt_sg, 4 * (size_t)nb));
   A_TRY(dalloc(g, (void **)&ms.bcnt_cy, 4 * (size_t)nb));
   A_TRY(dalloc(g, (void **)&ms.boff_sg, 4 * (size_t)nb));
@@ -131,6 +132,7 @@ amlm_status alloc_mine_scratch(amlm_graph *g) {
   A_TRY(dalloc(g, (void **)&ms.scan_tmp, 4 * scan_tmp_words(nb)));
   A_TRY(dalloc(g, (void **)&ms.ctr, 4 * kCtrWords));
   ms.cap_ev = ev;
+  ms.cap_e = std::max<uint64_t>(g->E, 1);
   return AMLM_OK;
 }
 
@@ -151,6 +153,7 @@ GraphView graph_view(const amlm_graph *g) {
   v.out_eid = a.out_eid;
   v.out_t = a.out_t;
   v.out_prv = a.out_prv;
+  v.out_src = a.out_src;
   v.in_ptr = a.in_ptr;
   v.in_nbr = a.in_nbr;
   v.in_eid = a.in_eid;

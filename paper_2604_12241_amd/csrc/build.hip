@@ -369,7 +369,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(hipGetLastError());
     CK(hipMemcpyAsync(a.out_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.out_eid, a.dst, a.t, Ev, a.out_nbr,
-                       a.out_t, a.pos_out, (const uint32_t *)nullptr, (uint32_t *)nullptr);
+                       a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src);
     CK(hipGetLastError());
     // 3. CSC: stable sort of the anchor order by destination
     hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.anc, bb.ka, bb.va, Ev);

@@ -30,7 +30,7 @@ struct GraphView {
   const int32_t *t;  // time relative to the minimum timestamp
   const uint32_t *anc;
   const uint32_t *pos_out, *pos_in;  // edge id -> CSR / CSC position
-  const uint32_t *out_ptr, *out_nbr, *out_eid;
+  const uint32_t *out_ptr, *out_nbr, *out_eid, *out_src;  // out_src: row (source) of each entry
   const int32_t *out_t, *out_prv;
   const uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;  // in_dst: row (destination) of each entry
   const int32_t *in_t, *in_nxt;
@@ -131,6 +131,11 @@ __device__ __forceinline__ uint32_t upper_bound_u64_interp(const uint64_t *a, ui
     if (i < hi - 1 && a[i] > key) ans = i;
   }
   return ans;
+}
+
+// first index in [p, e) with a[i] > x, given that every a[i] before p is <= x
+__device__ __forceinline__ uint32_t gallop_upper_right(const int32_t *a, uint32_t p, uint32_t e, int32_t x) {
+  return gallop_lower_right(a, p, e, x + 1);  // integer times: > x is >= x + 1 (x < INT_MAX)
 }
 
 __device__ __forceinline__ uint64_t nbr_key(uint32_t nbr, int32_t t) {

@@ -48,7 +48,7 @@ struct MineParams {
 
 struct MineScratch {
   uint8_t *flags = nullptr;   // [0, Ev): scatter-gather flag per CSC position;
-                              // then the cycle flag per time-order position
+                              // then the cycle-root flag per edge id [0, E)
   uint4 *sg_win = nullptr;    // per CSC position: senders window [p0, p1) in u's
                               // in-row and v's in-window [r0, r1)
   uint32_t *feat = nullptr;   // per CSC position: raw cost-model features [8]
@@ -57,7 +57,7 @@ struct MineScratch {
   uint32_t *bcnt_sg = nullptr, *bcnt_cy = nullptr, *boff_sg = nullptr, *boff_cy = nullptr;
   uint32_t *scan_tmp = nullptr;
   uint32_t *ctr = nullptr;
-  uint64_t cap_ev = 0;
+  uint64_t cap_ev = 0, cap_e = 0;
 };
 
 struct MineLaunch {

@@ -1,10 +1,12 @@
 // Mining kernels.
 //
-//  k_anchor  one lane per anchor (time order): window bounds by binary search
-//            (Find_Starting_Edge, Algorithm 1), FAN_OUT / FAN_IN, the size of
-//            the sender set S(e) when its window slice is short, and the
-//            classification of the anchor into the scatter-gather and cycle
-//            work lists (kept in CSC order: grouped by v, time-sorted).
+//  k_anchor_out / k_anchor_in
+//            one lane per anchor, in CSR then CSC order: window bounds by
+//            galloping and binary search (Find_Starting_Edge, Algorithm 1),
+//            FAN_OUT / FAN_IN, the size of the sender set S(e) when its
+//            window slice is short, and the classification of the anchor into
+//            the scatter-gather list (CSC order: grouped by v, time-sorted) and
+//            the cycle list (edge-id order).
 //  k_sg      scatter-gather / gather-scatter (Section 5 scatter-gather
 //            decomposition, Section 6 compiled example).  A wave takes up to
 //            64 anchors; each run of anchors into the same v is a segment
@@ -34,41 +36,35 @@ __device__ __forceinline__ int32_t window_lo(int32_t t, int64_t delta) {
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ int32_t rfl(int32_t x) { return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x); }
 
-// ------------------------------------------------------------------ k_anchor
-__global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags_sg, uint8_t *flags_cy,
-                                                 uint4 *sg_win, uint32_t *feat) {
+// ------------------------------------------------------------------ anchor passes
+// Pass 1 runs over the CSR (one lane per out-entry: anchor e = (u -> v, t) in
+// u's row), so neighbouring lanes search the same rows: FAN_OUT inside u's
+// own row by galloping from the anchor's position, and u's sender window
+// [lo, t) in u's in-row.  Pass 2 runs over the CSC: FAN_IN inside v's row,
+// and v's out-window [lo, t) (the first hop of a cycle).
+__global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flags_sg, uint4 *sg_win, uint32_t *feat) {
   const GraphView &g = mp.g;
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.Ev) return;
-  uint32_t eid = g.anc[p];
+  uint32_t eid = g.out_eid[p];
   if (eid < mp.anchor_lo) return;  // context edge (incremental mining)
-  uint32_t u = g.src[eid], v = g.dst[eid];
-  int32_t t = g.t[eid];
+  uint32_t u = g.out_src[p], v = g.out_nbr[p];
+  int32_t t = g.out_t[p];
   int32_t lo = window_lo(t, delta_of(mp, u));
   const uint32_t k = k_of(mp, u);
-  uint8_t f = 0;
+  uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
   uint32_t fan_out = 0;
   if (mp.col_fo >= 0 || feat) {
-    uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1], pu = g.pos_out[eid];
-    uint32_t hi = upper_bound_i32(g.out_t, pu + 1, re, t);
-    uint32_t lb = lower_bound_i32(g.out_t, rs, pu, lo);
+    uint32_t hi = gallop_upper_right(g.out_t, p + 1, re, t);
+    uint32_t lb = gallop_lower_left(g.out_t, rs, p, lo);
     fan_out = hi - lb;
     if (mp.col_fo >= 0) mp.counts[(uint64_t)mp.col_fo * mp.stride + eid] = fan_out;
   }
-  // v's in-window [lo, t] (FAN_IN, and the gather side of scatter-gather)
-  const uint32_t pv = g.pos_in[eid];
-  uint32_t vr0 = 0, vr1 = 0;
-  if (mp.col_fi >= 0 || mp.col_sg >= 0 || feat) {
-    uint32_t rs = g.in_ptr[v], re = g.in_ptr[v + 1];
-    vr1 = upper_bound_i32(g.in_t, pv + 1, re, t);
-    vr0 = lower_bound_i32(g.in_t, rs, pv, lo);
-    if (mp.col_fi >= 0) mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = vr1 - vr0;
-  }
-  uint32_t p0 = 0, p1 = 0;
   if (mp.col_sg >= 0 || mp.col_gs >= 0) {
     uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
-    p0 = lower_bound_i32(g.in_t, cs, ce, lo);
-    p1 = lower_bound_i32(g.in_t, p0, ce, t);
+    uint32_t p1 = lower_bound_i32(g.in_t, cs, ce, t);
+    uint32_t p0 = gallop_lower_left(g.in_t, cs, p1, lo);
+    bool item = false;
     if (p1 > p0) {
       if (p1 - p0 <= kAnchorScanCap) {
         uint32_t ns = 0;
@@ -80,37 +76,63 @@ __global__ __launch_bounds__(256) void k_anchor(MineParams mp, uint8_t *flags_sg
             if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = ns;
             if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = ns;
           } else {
-            f |= kFlagSG;
+            item = true;
           }
         }
       } else {
-        f |= kFlagSG;
+        item = true;
+      }
+    }
+    if (item) {
+      // scatter-gather anchors are listed in CSC order: grouped by v, time-sorted
+      uint32_t q = g.pos_in[eid];
+      flags_sg[q] = kFlagSG;
+      sg_win[q].x = p0;
+      sg_win[q].y = p1;
+      if (feat) {
+        uint32_t *o = feat + (uint64_t)q * kMlpRaw;
+        o[0] = fan_out;
+        o[2] = p1 - p0;
+        o[4] = re - rs;
+        o[5] = ce - cs;
       }
     }
   }
-  if (mp.col_cyc >= 0) {
-    uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
-    uint32_t q0 = lower_bound_i32(g.out_t, vs, ve, lo);
-    if (q0 < ve && g.out_t[q0] < t) flags_cy[p] = kFlagCYC;  // cycle roots stay in time order
+}
+
+__global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, const uint8_t *flags_sg, uint8_t *flags_cy,
+                                                   uint4 *sg_win, uint32_t *feat) {
+  const GraphView &g = mp.g;
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.Ev) return;
+  uint32_t eid = g.in_eid[q];
+  if (eid < mp.anchor_lo) return;
+  uint32_t v = g.in_dst[q], u = g.in_nbr[q];
+  int32_t t = g.in_t[q];
+  int32_t lo = window_lo(t, delta_of(mp, u));
+  const bool is_sg = (mp.col_sg >= 0 || mp.col_gs >= 0) && flags_sg[q];
+  if (mp.col_fi >= 0 || is_sg) {
+    uint32_t rs = g.in_ptr[v], re = g.in_ptr[v + 1];
+    uint32_t hi = gallop_upper_right(g.in_t, q + 1, re, t);
+    uint32_t lb = gallop_lower_left(g.in_t, rs, q, lo);
+    if (mp.col_fi >= 0) mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = hi - lb;
+    if (is_sg) {
+      sg_win[q].z = lb;
+      sg_win[q].w = hi;
+      if (feat) {
+        feat[(uint64_t)q * kMlpRaw + 1] = hi - lb;
+        feat[(uint64_t)q * kMlpRaw + 7] = re - rs;
+      }
+    }
   }
-  if (f & kFlagSG) {
-    // scatter-gather anchors are listed in CSC order: grouped by v, time-sorted
-    flags_sg[pv] = kFlagSG;
-    sg_win[pv] = make_uint4(p0, p1, vr0, vr1);
-    if (feat) {
-      // raw cost-model features of this anchor (see costmodel.h)
-      uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
-      uint32_t q0 = lower_bound_i32(g.out_t, vs, ve, lo);
-      uint32_t q1 = lower_bound_i32(g.out_t, q0, ve, t);
-      uint32_t *o = feat + (uint64_t)pv * kMlpRaw;
-      o[0] = fan_out;
-      o[1] = vr1 - vr0;
-      o[2] = p1 - p0;
-      o[3] = q1 - q0;
-      o[4] = g.out_ptr[u + 1] - g.out_ptr[u];
-      o[5] = g.in_ptr[u + 1] - g.in_ptr[u];
-      o[6] = ve - vs;
-      o[7] = g.in_ptr[v + 1] - g.in_ptr[v];
+  if (mp.col_cyc >= 0 || (is_sg && feat)) {
+    uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
+    uint32_t q1 = lower_bound_i32(g.out_t, vs, ve, t);
+    if (mp.col_cyc >= 0 && q1 > vs && g.out_t[q1 - 1] >= lo) flags_cy[eid] = kFlagCYC;
+    if (is_sg && feat) {
+      uint32_t q0 = gallop_lower_left(g.out_t, vs, q1, lo);
+      feat[(uint64_t)q * kMlpRaw + 3] = q1 - q0;
+      feat[(uint64_t)q * kMlpRaw + 6] = ve - vs;
     }
   }
 }
@@ -581,7 +603,7 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
     if (base >= n_in) break;
     uint32_t nr = min((uint32_t)AMLM_WAVE, n_in - base);
     if (lane < nr) {
-      uint32_t eid = g.anc[roots[base + lane]];  // time-order position of the anchor
+      uint32_t eid = roots[base + lane];  // edge id of the anchor
       uint32_t v = g.dst[eid];
       int32_t t = g.t[eid];
       uint32_t u = g.src[eid];
@@ -670,66 +692,41 @@ __global__ void k_chunk_keys(const float *pred, const uint32_t *n_items_p, uint3
   vals[c] = c;
 }
 
-__global__ void k_flag_count(const uint8_t *fsg, const uint8_t *fcy, uint32_t n, uint32_t *c_sg, uint32_t *c_cy) {
-  __shared__ uint32_t ws[2][kFlagThreads / AMLM_WAVE];
+// Order-preserving compaction of the indices i with flags[i] != 0 (block
+// counts, exclusive scan, scatter).
+__global__ void k_flag_count(const uint8_t *flags, uint32_t n, uint32_t *cnt) {
+  __shared__ uint32_t ws[kFlagThreads / AMLM_WAVE];
   uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
   uint32_t base = blockIdx.x * kFlagTile + tid * kFlagItems;
-  uint32_t a = 0, b = 0;
-  for (uint32_t j = 0; j < kFlagItems; j++) {
-    uint32_t idx = base + j;
-    a += idx < n && fsg[idx] != 0;
-    b += idx < n && fcy[idx] != 0;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o, AMLM_WAVE);
-    b += __shfl_xor(b, o, AMLM_WAVE);
-  }
-  if (lane_id() == 0) {
-    ws[0][w] = a;
-    ws[1][w] = b;
-  }
+  uint32_t a = 0;
+  for (uint32_t j = 0; j < kFlagItems; j++) a += base + j < n && flags[base + j] != 0;
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, AMLM_WAVE);
+  if (lane_id() == 0) ws[w] = a;
   __syncthreads();
   if (tid == 0) {
-    uint32_t sa = 0, sb = 0;
-    for (int q = 0; q < kFlagThreads / AMLM_WAVE; q++) {
-      sa += ws[0][q];
-      sb += ws[1][q];
-    }
-    c_sg[blockIdx.x] = sa;
-    c_cy[blockIdx.x] = sb;
+    uint32_t sa = 0;
+    for (int q = 0; q < kFlagThreads / AMLM_WAVE; q++) sa += ws[q];
+    cnt[blockIdx.x] = sa;
   }
 }
 
-// order-preserving scatter of flagged anchor positions
-__global__ void k_flag_scatter(const uint8_t *fsg, const uint8_t *fcy, uint32_t n, const uint32_t *o_sg,
-                               const uint32_t *o_cy, uint32_t *l_sg, uint32_t *l_cy) {
-  __shared__ uint32_t ws[2][kFlagThreads / AMLM_WAVE];
+__global__ void k_flag_scatter(const uint8_t *flags, uint32_t n, const uint32_t *off, uint32_t *list) {
+  __shared__ uint32_t ws[kFlagThreads / AMLM_WAVE];
   uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
   uint32_t base = blockIdx.x * kFlagTile + tid * kFlagItems;
-  bool fa[kFlagItems], fb[kFlagItems];
-  uint32_t a = 0, b = 0;
+  bool fa[kFlagItems];
+  uint32_t a = 0;
   for (uint32_t j = 0; j < kFlagItems; j++) {
-    uint32_t idx = base + j;
-    fa[j] = idx < n && fsg[idx] != 0;
-    fb[j] = idx < n && fcy[idx] != 0;
+    fa[j] = base + j < n && flags[base + j] != 0;
     a += fa[j];
-    b += fb[j];
   }
-  uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
-  if (lane_id() == AMLM_WAVE - 1) {
-    ws[0][w] = ia;
-    ws[1][w] = ib;
-  }
+  uint32_t ia = wave_incl_scan(a);
+  if (lane_id() == AMLM_WAVE - 1) ws[w] = ia;
   __syncthreads();
-  uint32_t pa = o_sg[blockIdx.x] + ia - a, pb = o_cy[blockIdx.x] + ib - b;
-  for (uint32_t q = 0; q < w; q++) {
-    pa += ws[0][q];
-    pb += ws[1][q];
-  }
-  for (uint32_t j = 0; j < kFlagItems; j++) {
-    if (fa[j]) l_sg[pa++] = base + j;
-    if (fb[j]) l_cy[pb++] = base + j;
-  }
+  uint32_t pa = off[blockIdx.x] + ia - a;
+  for (uint32_t q = 0; q < w; q++) pa += ws[q];
+  for (uint32_t j = 0; j < kFlagItems; j++)
+    if (fa[j]) list[pa++] = base + j;
 }
 
 }  // namespace
@@ -751,27 +748,37 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   CK(launch_fill_u32(ms.ctr, 0, kCtrWords, s));
   if (Ev == 0) return hipSuccess;
   CK(tm->begin(kStAnchor, s));
-  CK(launch_fill_u32((uint32_t *)ms.flags, 0, 2 * ((Ev + 3) / 4), s));
+  const uint32_t E = mp.g.E;
+  CK(launch_fill_u32((uint32_t *)ms.flags, 0, (Ev + 3) / 4 + (E + 3) / 4, s));
   uint8_t *flags_sg = ms.flags, *flags_cy = ms.flags + 4 * ((Ev + 3) / 4);
   const bool learned = cfg.learned && mp.col_sg >= 0 && mp.k >= 2;
-  hipLaunchKernelGGL(k_anchor, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, flags_cy, ms.sg_win,
-                     learned ? ms.feat : (uint32_t *)nullptr);
+  uint32_t *feat = learned ? ms.feat : (uint32_t *)nullptr;
+  hipLaunchKernelGGL(k_anchor_out, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, ms.sg_win, feat);
+  CK(hipGetLastError());
+  hipLaunchKernelGGL(k_anchor_in, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, flags_cy, ms.sg_win, feat);
   CK(hipGetLastError());
   CK(tm->end(kStAnchor, s));
   const bool want_sg = mp.col_sg >= 0 || mp.col_gs >= 0;
   const bool want_cyc = mp.col_cyc >= 0;
   if (!want_sg && !want_cyc) return hipSuccess;
-  uint32_t nb = (Ev + kFlagTile - 1) / kFlagTile;
   CK(tm->begin(kStLists, s));
-  hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, flags_cy, Ev, ms.bcnt_sg,
-                     ms.bcnt_cy);
-  CK(hipGetLastError());
   uint32_t *n_sg = ms.ctr + kCtrNSg, *n_cy = ms.ctr + kCtrNCy;
-  CK(scan_exclusive_u32(ms.bcnt_sg, ms.boff_sg, nb, n_sg, ms.scan_tmp, s));
-  CK(scan_exclusive_u32(ms.bcnt_cy, ms.boff_cy, nb, n_cy, ms.scan_tmp, s));
-  hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, flags_cy, Ev, ms.boff_sg,
-                     ms.boff_cy, ms.list_sg, ms.list_cy);
-  CK(hipGetLastError());
+  if (want_sg) {
+    uint32_t nb = (Ev + kFlagTile - 1) / kFlagTile;
+    hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, Ev, ms.bcnt_sg);
+    CK(hipGetLastError());
+    CK(scan_exclusive_u32(ms.bcnt_sg, ms.boff_sg, nb, n_sg, ms.scan_tmp, s));
+    hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, Ev, ms.boff_sg, ms.list_sg);
+    CK(hipGetLastError());
+  }
+  if (want_cyc) {
+    uint32_t nb = (E + kFlagTile - 1) / kFlagTile;
+    hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_cy, E, ms.bcnt_cy);
+    CK(hipGetLastError());
+    CK(scan_exclusive_u32(ms.bcnt_cy, ms.boff_cy, nb, n_cy, ms.scan_tmp, s));
+    hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_cy, E, ms.boff_cy, ms.list_cy);
+    CK(hipGetLastError());
+  }
   CK(tm->end(kStLists, s));
   const uint32_t *chunk_tab = nullptr;
   uint32_t chunk = cfg.sg_chunk;
