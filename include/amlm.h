@@ -235,6 +235,10 @@ amlm_status amlm_costmodel_get(float *weights, float *mean, float *inv_std);
  * 5057 parameters, accumulated over samples in a fixed order (deterministic);
  * *loss (may be NULL) receives the mean squared error. */
 amlm_status amlm_mlp_forward(const float *weights, const float *x, uint32_t n, float *y);
+/* The scheduler's inference path: the same network on the matrix cores
+ * (16x16x16 BF16 MFMA tiles of 16 anchors), BF16 inputs and activations,
+ * FP32 accumulation. */
+amlm_status amlm_mlp_predict(const float *weights, const float *x, uint32_t n, float *y);
 amlm_status amlm_mlp_grad(const float *weights, const float *x, const float *y, uint32_t n, float *grad,
                           float *loss);
 

@@ -69,3 +69,13 @@ def grad(w, X, Y):
     g[OFF_W1:OFF_B1] = (da1.T @ X).ravel()
     g[OFF_B1:OFF_W2] = da1.sum(axis=0)
     return g
+
+
+def forward_bf16_act(w, X):
+    """Forward pass with the inputs and both hidden activations rounded to
+    BF16 after the ReLU, as the matrix-core inference path computes them."""
+    W1, b1, W2, b2, w3, b3 = unpack(w)
+    X = bf16_round(np.asarray(X, dtype=np.float32)).astype(np.float64)
+    h1 = bf16_round(np.maximum(X @ W1.T + b1, 0.0).astype(np.float32)).astype(np.float64)
+    h2 = bf16_round(np.maximum(h1 @ W2.T + b2, 0.0).astype(np.float32)).astype(np.float64)
+    return h2 @ w3 + b3

@@ -29,7 +29,7 @@ EXPORTS = [
     "amlm_server_create", "amlm_server_submit", "amlm_server_wait", "amlm_server_ticket_times",
     "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
-    "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy",
+    "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy", "amlm_mlp_predict",
 ]
 
 
@@ -86,6 +86,7 @@ def lib():
             "amlm_set_timing": (st, [p, ctypes.c_int]),
             "amlm_costmodel_get": (st, [p, p, p]),
             "amlm_mlp_forward": (st, [p, p, u32, p]),
+            "amlm_mlp_predict": (st, [p, p, u32, p]),
             "amlm_mlp_grad": (st, [p, p, p, u32, p, p]),
             "amlm_stage_times": (st, [p, ctypes.POINTER(ctypes.c_float)]),
         }
@@ -353,6 +354,14 @@ def amlm_mlp_forward(w, x):
     x = np.ascontiguousarray(x, np.float32)
     y = np.zeros(x.shape[0], np.float32)
     _check(lib().amlm_mlp_forward(_ptr(w), _ptr(x), x.shape[0], _ptr(y)))
+    return y
+
+
+def amlm_mlp_predict(w, x):
+    w = np.ascontiguousarray(w, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.zeros(x.shape[0], np.float32)
+    _check(lib().amlm_mlp_predict(_ptr(w), _ptr(x), x.shape[0], _ptr(y)))
     return y
 
 

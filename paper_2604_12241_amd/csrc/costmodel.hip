@@ -91,6 +91,136 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *w16, const fl
   }
 }
 
+// ---- MFMA inference: 16 anchors per v_mfma_f32_16x16x16_bf16 tile ----
+// Operand layout of the 16x16x16 BF16 MFMA (64 lanes, l = lane):
+//   A (16 x 16, M x K): lane l holds row l % 16, k = 4 (l / 16) + 0..3
+//   B (16 x 16, K x N): lane l holds col l % 16, k = 4 (l / 16) + 0..3
+//   C (16 x 16):        lane l holds col l % 16, rows 4 (l / 16) + 0..3
+// The three layers are dense products [16 x K] x [K x 64] (K = 16 with the
+// 12 inputs zero-padded, then 64, then 64 x 16 with w3 in column 0); every
+// weight operand stays in registers, and the activations go through a
+// 16 x 64 BF16 tile in LDS to move from the C layout to the A layout.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) { return (short)d_f32_to_bf16(f); }
+
+constexpr int kTileRows = 16;
+constexpr int kActPad = kMlpH + 8;  // bf16 per LDS row (pad against bank conflicts)
+
+template <bool kFromRaw>
+__global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const float *norm, const uint32_t *feat,
+                                                  const uint32_t *idx, const float *X, const uint32_t *n_p,
+                                                  uint32_t n_host, float dh, float L, float *pred) {
+  __shared__ short act[256 / AMLM_WAVE][kTileRows][kActPad];
+  const uint32_t lane = lane_id(), w = threadIdx.x / AMLM_WAVE;
+  const uint32_t col = lane % 16, kq = (lane / 16) * 4;
+  // weights as B operands, in registers
+  bf16x4_t B1[4], B2[4][4], B3[4];
+  float bias1[4], bias2[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++) {
+    uint32_t n = nt * 16 + col;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      uint32_t k = kq + i;
+      B1[nt][i] = k < kMlpF ? (short)w16[kOffW1 + n * kMlpF + k] : (short)0;
+    }
+    bias1[nt] = dbf16(w16[kOffB1 + n]);
+    bias2[nt] = dbf16(w16[kOffB2 + n]);
+#pragma unroll
+    for (int kt = 0; kt < 4; kt++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) B2[kt][nt][i] = (short)w16[kOffW2 + n * kMlpH + kt * 16 + kq + i];
+  }
+#pragma unroll
+  for (int kt = 0; kt < 4; kt++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) B3[kt][i] = col == 0 ? (short)w16[kOffW3 + kt * 16 + kq + i] : (short)0;
+  const float b3 = dbf16(w16[kOffB3]);
+  float nrm[2 * kMlpF];
+#pragma unroll
+  for (int i = 0; i < 2 * kMlpF; i++) nrm[i] = kFromRaw ? norm[i] : 0.f;
+  const uint32_t n = n_p ? *n_p : n_host;
+  const uint32_t n_tiles = (n + kTileRows - 1) / kTileRows;
+  const uint32_t wave_id = blockIdx.x * (256 / AMLM_WAVE) + w, n_waves = gridDim.x * (256 / AMLM_WAVE);
+  for (uint32_t tile = wave_id; tile < n_tiles; tile += n_waves) {
+    const uint32_t row = lane % 16;
+    const uint32_t item = tile * kTileRows + row;
+    const bool valid = item < n;
+    // A operand of layer 1: this lane's four inputs of its row
+    float x[4] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+      if (kFromRaw) {
+        uint32_t r[kMlpRaw];
+        uint64_t rr = idx ? idx[item] : item;
+#pragma unroll
+        for (int q = 0; q < kMlpRaw; q++) r[q] = feat[rr * kMlpRaw + q];
+        float xf[kMlpF];
+        mlp_input(r, dh, L, nrm, xf);
+#pragma unroll
+        for (int i = 0; i < 4; i++) x[i] = kq + i < kMlpF ? xf[kq + i] : 0.f;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++) x[i] = kq + i < kMlpF ? X[(uint64_t)item * kMlpF + kq + i] : 0.f;
+      }
+    }
+    bf16x4_t a1;
+#pragma unroll
+    for (int i = 0; i < 4; i++) a1[i] = bf16_bits(x[i]);
+    // layer 1 -> act (bf16, relu)
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+      floatx4_t c = {0.f, 0.f, 0.f, 0.f};
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, B1[nt], c, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        float h = c[i] + bias1[nt];
+        act[w][kq + i][nt * 16 + col] = bf16_bits(h > 0.f ? h : 0.f);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    // layer 2
+    bf16x4_t a2[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; kt++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) a2[kt][i] = act[w][row][kt * 16 + kq + i];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+      floatx4_t c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < 4; kt++) c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[kt], B2[kt][nt], c, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        float h = c[i] + bias2[nt];
+        act[w][kq + i][nt * 16 + col] = bf16_bits(h > 0.f ? h : 0.f);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    // layer 3 (w3 in column 0)
+    bf16x4_t a3[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; kt++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) a3[kt][i] = act[w][row][kt * 16 + kq + i];
+    __builtin_amdgcn_wave_barrier();
+    floatx4_t c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; kt++) c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[kt], B3[kt], c, 0, 0, 0);
+    if (col == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        uint32_t it = tile * kTileRows + kq + i;
+        if (it < n) pred[it] = c[i] + b3;
+      }
+    }
+  }
+}
+
 // Forward pass on standardised inputs X[n][12].
 __global__ __launch_bounds__(256) void k_mlp_fwd_x(const uint16_t *w16, const float *X, uint32_t n, float *y) {
   __shared__ float W[kMlpParams];
@@ -356,9 +486,9 @@ hipError_t model_upload(MlpModel &m) {
 
 hipError_t mlp_infer(const MlpModel &m, const uint32_t *feat, const uint32_t *idx, uint32_t n_host,
                      const uint32_t *n_dev, float delta_hours, float L, float *pred, hipStream_t s) {
-  uint32_t blocks = 4 * device_info().num_cu;
-  hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, s, m.d_w16, m.d_norm, feat, idx, n_dev, n_host,
-                     delta_hours, L, pred);
+  uint32_t blocks = 2 * device_info().num_cu;
+  hipLaunchKernelGGL(k_mlp_mfma<true>, dim3(blocks), dim3(256), 0, s, m.d_w16, m.d_norm, feat, idx,
+                     (const float *)nullptr, n_dev, n_host, delta_hours, L, pred);
   return hipGetLastError();
 }
 
@@ -462,6 +592,30 @@ extern "C" amlm_status amlm_mlp_forward(const float *w_host, const float *x_host
   HIP_TRY(hipMemcpy(w16, w.data(), 2 * kMlpParams, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(X, x_host, 4ull * n * kMlpF, hipMemcpyHostToDevice));
   hipLaunchKernelGGL(k_mlp_fwd_x, dim3((n + 255) / 256), dim3(256), 0, 0, w16, X, n, Y);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpy(y_host, Y, 4ull * n, hipMemcpyDeviceToHost));
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_mlp_predict(const float *w_host, const float *x_host, uint32_t n, float *y_host) {
+  if (!w_host || (n && (!x_host || !y_host))) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  if (n == 0) return AMLM_OK;
+  DevBuf b;
+  uint16_t *w16;
+  float *X, *Y;
+  A_TRY(b.get(&w16, kMlpParams));
+  A_TRY(b.get(&X, (size_t)n * kMlpF));
+  A_TRY(b.get(&Y, n));
+  std::vector<uint16_t> w(kMlpParams);
+  for (int p = 0; p < kMlpParams; p++) w[p] = f32_to_bf16(w_host[p]);
+  HIP_TRY(hipMemcpy(w16, w.data(), 2 * kMlpParams, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(X, x_host, 4ull * n * kMlpF, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_mlp_mfma<false>, dim3(std::max(1u, std::min(1024u, (n + 63) / 64))), dim3(256), 0, 0, w16,
+                     (const float *)nullptr, (const uint32_t *)nullptr, (const uint32_t *)nullptr, X,
+                     (const uint32_t *)nullptr, n, 0.f, 0.f, Y);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpy(y_host, Y, 4ull * n, hipMemcpyDeviceToHost));
   return AMLM_OK;

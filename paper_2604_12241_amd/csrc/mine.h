@@ -8,10 +8,19 @@ constexpr uint8_t kFlagSG = 1, kFlagCYC = 2;
 constexpr uint32_t kAnchorScanCap = 16;
 
 constexpr int kSgThreads = 64;   // one wave per block
-constexpr int kBloomLog2Max = 16;                       // 64 Kbit filter
+#ifndef AMLM_BLOOM_LOG2_MAX
+#define AMLM_BLOOM_LOG2_MAX 16
+#endif
+#ifndef AMLM_BLOOM_BITS_PER_ENTRY
+#define AMLM_BLOOM_BITS_PER_ENTRY 16
+#endif
+#ifndef AMLM_JOIN_UNROLL
+#define AMLM_JOIN_UNROLL 8
+#endif
+constexpr int kBloomLog2Max = AMLM_BLOOM_LOG2_MAX;      // 64 Kbit filter by default
 constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
-constexpr uint32_t kBloomBitsPerEntry = 16;             // blocked, 3 bits per key: ~1% false positives
-constexpr int kJoinUnroll = 8;
+constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;  // blocked, 3 bits per key: ~1% false positives at 16
+constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each

@@ -37,6 +37,21 @@ def test_forward_and_gradient_match_fp64_reference():
         assert abs(loss - mlp.loss(w, X, Y)) <= 1e-4 * max(1.0, loss)
 
 
+def test_matrix_core_inference_matches_reference():
+    """The MFMA path (16x16x16 BF16 tiles) against the FP64 reference with the
+    same BF16 rounding of inputs and activations; sizes cover partial tiles."""
+    rng = np.random.default_rng(11)
+    w = _weights(3)
+    for n in (1, 15, 16, 17, 100, 4097):
+        X = rng.normal(0, 1, (n, mlp.F)).astype(np.float32)
+        y = A.amlm_mlp_predict(w, X)
+        ref = mlp.forward_bf16_act(w.astype(np.float64), X)
+        np.testing.assert_allclose(y, ref, rtol=2e-2, atol=2e-2 * max(1.0, np.abs(ref).max()))
+        # and it tracks the FP32-activation forward closely
+        full = mlp.forward(w.astype(np.float64), mlp.bf16_round(X).astype(np.float64))
+        assert np.corrcoef(y, full)[0, 1] > 0.999 if n > 16 else True
+
+
 def test_gradient_is_deterministic():
     rng = np.random.default_rng(9)
     w = _weights(2)
