@@ -338,7 +338,7 @@ MineLaunch default_launch(const amlm_graph *g) {
   MineLaunch cfg;
   cfg.sg_blocks = (uint32_t)(di.num_cu * di.sg_occ);
   cfg.cyc_blocks = (uint32_t)(di.num_cu * di.cyc_occ);
-  cfg.sg_chunk = AMLM_WAVE;  // anchors per work-stealing grab (<= 64)
+  cfg.sg_chunk = kSgChunkMax;  // anchors per work-stealing grab
   if (g->tune.sg_chunk) cfg.sg_chunk = g->tune.sg_chunk;
   if (g->tune.sg_blocks) cfg.sg_blocks = g->tune.sg_blocks;
   if (g->tune.cyc_blocks) cfg.cyc_blocks = g->tune.cyc_blocks;

@@ -9,18 +9,22 @@ constexpr uint32_t kAnchorScanCap = 16;
 
 constexpr int kSgThreads = 64;   // one wave per block
 #ifndef AMLM_BLOOM_LOG2_MAX
-#define AMLM_BLOOM_LOG2_MAX 16
+#define AMLM_BLOOM_LOG2_MAX 15
 #endif
 #ifndef AMLM_BLOOM_BITS_PER_ENTRY
-#define AMLM_BLOOM_BITS_PER_ENTRY 16
+#define AMLM_BLOOM_BITS_PER_ENTRY 32
+#endif
+#ifndef AMLM_SG_CHUNK_MAX
+#define AMLM_SG_CHUNK_MAX 8
 #endif
 #ifndef AMLM_JOIN_UNROLL
 #define AMLM_JOIN_UNROLL 8
 #endif
-constexpr int kBloomLog2Max = AMLM_BLOOM_LOG2_MAX;      // 64 Kbit filter by default
+constexpr int kBloomLog2Max = AMLM_BLOOM_LOG2_MAX;      // 32 Kbit (4 KB) filter: occupancy beats a lower false-positive rate
 constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
-constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;  // blocked, 3 bits per key: ~1% false positives at 16
+constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;  // blocked, 3 bits per key
 constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
+constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
 constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
@@ -72,7 +76,7 @@ struct MineScratch {
 struct MineLaunch {
   uint32_t sg_blocks, sg_chunk, cyc_blocks;
   bool learned = false;         // schedule scatter-gather chunks by the cost model
-  uint32_t learned_chunk = 16;  // anchors per chunk in the learned schedule
+  uint32_t learned_chunk = kSgChunkMax;  // anchors per chunk in the learned schedule
   float delta_hours = 24.f;
   BuildBuffers *bb = nullptr;   // sort buffers reused by the learned schedule
 };

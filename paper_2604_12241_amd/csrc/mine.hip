@@ -143,12 +143,12 @@ constexpr uint32_t kCandCap = 2 * AMLM_WAVE;
 struct SgLds {
   uint32_t bloom[kBloomWordsMax];
   // anchors of the current chunk
-  uint32_t i_eid[AMLM_WAVE], i_u[AMLM_WAVE], i_p0[AMLM_WAVE], i_ns[AMLM_WAVE], i_sg[AMLM_WAVE];
-  uint32_t i_work[AMLM_WAVE], i_wlen[AMLM_WAVE];
+  uint32_t i_eid[kSgChunkMax], i_u[kSgChunkMax], i_p0[kSgChunkMax], i_ns[kSgChunkMax], i_sg[kSgChunkMax];
+  uint32_t i_work[kSgChunkMax], i_wlen[kSgChunkMax];
   uint32_t seg_off[AMLM_WAVE];  // exclusive offsets of the segment's sender windows
-  int32_t i_t[AMLM_WAVE], i_lo[AMLM_WAVE], i_tau[AMLM_WAVE];
-  uint32_t i_r0[AMLM_WAVE], i_r1[AMLM_WAVE];  // v's in-window [lo, t] of each anchor
-  uint32_t i_k[AMLM_WAVE];                    // threshold k of each anchor
+  int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax], i_tau[kSgChunkMax];
+  uint32_t i_q[kSgChunkMax];    // CSC position of each anchor (its v-window is in sg_win)
+  uint32_t i_k[kSgChunkMax];    // threshold k of each anchor
   // (anchor, sender) pairs of one batch
   uint32_t pr_item[AMLM_WAVE], pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
   // Bloom-positive candidates awaiting the exact check
@@ -291,7 +291,8 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, 
 }
 
 // Anchors [s0, s1) of the chunk, all into vertex v.
-__device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t v) {
+__device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t v,
+                           const uint4 *sg_win) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
@@ -303,7 +304,7 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   if (need_join) {
     // gather side of the whole segment: v's in-neighbours in [lo_first, t_last]
     // (the anchors are time-sorted inside the segment)
-    uint32_t r0 = rfl(L.i_r0[s0]), r1 = rfl(L.i_r1[s1 - 1]);
+    uint32_t r0 = rfl(sg_win[L.i_q[s0]].z), r1 = rfl(sg_win[L.i_q[s1 - 1]].w);
     uint32_t nin = r1 - r0;
     int lg = 9;
     while (lg < kBloomLog2Max && (1u << lg) < nin * kBloomBitsPerEntry) lg++;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint32_t n_items = *n_items_p;
-  chunk = min(chunk, (uint32_t)AMLM_WAVE);
+  chunk = min(chunk, kSgChunkMax);
   const uint32_t n_chunks = (n_items + chunk - 1) / chunk;
   for (;;) {
     // static: consecutive chunks of the CSC-ordered list; learned: the chunk
@@ -422,8 +423,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       int32_t t = g.in_t[q];
       uint4 pw = sg_win[q];
       v = g.in_dst[q];
-      L.i_r0[lane] = pw.z;
-      L.i_r1[lane] = pw.w;
+      L.i_q[lane] = q;
       L.i_eid[lane] = eid;
       L.i_u[lane] = g.in_nbr[q];
       L.i_t[lane] = t;
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       heads &= heads - 1;
       uint32_t s1 = heads ? (uint32_t)(__ffsll((long long)heads) - 1) : nr;
       uint32_t vs = rfl((uint32_t)__shfl(v, s0, AMLM_WAVE));
-      sg_segment(mp, L, s0, s1, vs);
+      sg_segment(mp, L, s0, s1, vs, sg_win);
     }
     // gather-scatter and the outputs, one lane per anchor
     uint32_t sg = 0, gs = 0;
