@@ -166,3 +166,25 @@ def test_mid_full_size_sampled(mid_full):
     cf = oracle.count_cycles_first(g.src, g.dst, g.ts, g.n_vertices, 86400, 6)
     for l in range(2, 7):
         assert int(c[4 + l - 2].astype(np.uint64).sum()) == l * int(cf[l])
+
+
+@pytest.fixture(scope="module")
+def large_full():
+    return W.large(404)
+
+
+def test_large_full_size_sampled_learned_schedule(large_full):
+    """The 32M-edge benchmark workload in the benchmark's launch
+    configuration (learned schedule, cost model trained on graphs of the
+    5M-edge generator): sampled edges against the oracle, and the learned
+    counts equal the static ones on every edge."""
+    g = large_full
+    mids = [W.mid(202 + i, scale=0.05) for i in range(2)]
+    Gs = [A.Graph(m.src, m.dst, m.ts, m.n_vertices) for m in mids]
+    A.amlm_costmodel_train(Gs, [A.params(A.AMLM_ALL, 86400, 6, 2)] * 2, epochs=2, batch=4096, seed=1)
+    for G in Gs:
+        G.close()
+    learned = gpu_mine(g, 86400, 6, 2, schedule=A.AMLM_SCHED_LEARNED, on_device=True)
+    static = gpu_mine(g, 86400, 6, 2, schedule=A.AMLM_SCHED_STATIC, on_device=True)
+    np.testing.assert_array_equal(learned, static)
+    _sampled(g, learned, 86400, 6, 2, n_sample=300, seed=3)
