@@ -200,11 +200,14 @@ __global__ void k_row_ptr(const uint32_t *keys, uint32_t n, uint32_t V, uint32_t
 }
 
 __global__ void k_fill_rows(const uint32_t *eids, const uint32_t *other, const int32_t *t, uint32_t n,
-                            uint32_t *nbr, int32_t *tt, uint32_t *pos, const uint32_t *rowkey, uint32_t *row) {
+                            uint32_t *nbr, int32_t *tt, uint32_t *pos, const uint32_t *rowkey, uint32_t *row,
+                            uint32_t *hnbr) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   uint32_t e = eids[p];
-  nbr[p] = other[e];
+  uint32_t o = other[e];
+  nbr[p] = o;
+  if (hnbr) hnbr[p] = vhash(o);
   tt[p] = t[e];
   pos[e] = p;
   if (row) row[p] = rowkey[p];
@@ -369,7 +372,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(hipGetLastError());
     CK(hipMemcpyAsync(a.out_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.out_eid, a.dst, a.t, Ev, a.out_nbr,
-                       a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src);
+                       a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src, a.out_h);
     CK(hipGetLastError());
     // 3. CSC: stable sort of the anchor order by destination
     hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.anc, bb.ka, bb.va, Ev);
@@ -379,7 +382,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(hipGetLastError());
     CK(hipMemcpyAsync(a.in_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.in_eid, a.src, a.t, Ev, a.in_nbr,
-                       a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst);
+                       a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst, (uint32_t *)nullptr);
     CK(hipGetLastError());
     // 4. CSC-N: stable sort of the CSR order (source, time, id) by destination
     hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.out_eid, bb.ka, bb.va, Ev);

@@ -16,7 +16,8 @@
 //  * anchors: valid (non-self-loop) edge ids in (time, id) order
 //  * CSR (out): rows by source, each row sorted by (time, id); per entry the
 //    destination, the time, the edge id and the time of the previous edge of
-//    the same (source, destination) pair (AMLM_INT_MIN if none)
+//    the same (source, destination) pair (AMLM_INT_MIN if none), and
+//    vhash(destination) (the scatter-gather join's filter key)
 //  * CSC (in): rows by destination, sorted by (time, id); per entry the
 //    source, time, edge id and the time of the next edge of the same pair
 //    (AMLM_INT_MAX if none)
@@ -31,12 +32,38 @@ struct GraphView {
   const uint32_t *anc;
   const uint32_t *pos_out, *pos_in;  // edge id -> CSR / CSC position
   const uint32_t *out_ptr, *out_nbr, *out_eid, *out_src;  // out_src: row (source) of each entry
+  const uint32_t *out_h;  // vhash(out_nbr[p])
   const int32_t *out_t, *out_prv;
   const uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;  // in_dst: row (destination) of each entry
   const int32_t *in_t, *in_nxt;
   const uint64_t *inn_key;
   const uint32_t *inn_eid;
 };
+
+// MurmurHash3's 32-bit finaliser (fmix32): a bijection on 32-bit words with
+// full avalanche, so two vertices share a hash only if they are equal.
+constexpr uint32_t kFmixC1 = 0x85EBCA6Bu, kFmixC2 = 0xC2B2AE35u;
+constexpr uint32_t inverse_mod_2_32(uint32_t c) {  // c odd; Newton steps double the correct bits
+  uint32_t x = c;
+  for (int i = 0; i < 5; i++) x *= 2u - c * x;
+  return x;
+}
+__host__ __device__ __forceinline__ uint32_t vhash(uint32_t x) {
+  x ^= x >> 16;
+  x *= kFmixC1;
+  x ^= x >> 13;
+  x *= kFmixC2;
+  x ^= x >> 16;
+  return x;
+}
+__host__ __device__ __forceinline__ uint32_t vhash_inv(uint32_t x) {
+  x ^= x >> 16;
+  x *= inverse_mod_2_32(kFmixC2);
+  x ^= (x >> 13) ^ (x >> 26);
+  x *= inverse_mod_2_32(kFmixC1);
+  x ^= x >> 16;
+  return x;
+}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }

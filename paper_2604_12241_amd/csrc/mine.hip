@@ -155,28 +155,25 @@ struct SgLds {
   uint32_t cq_pair[kCandCap], cq_pos[kCandCap];
 };
 
-// Register-blocked Bloom filter: a key selects one 32-bit word and sets
-// three bits inside it, so a test is a single LDS read.
+// Register-blocked Bloom filter over vertex hashes (vhash): a key selects
+// one 32-bit word by its top bits and sets three bits inside it chosen by its
+// low 15 bits, so a test is a single LDS read and a few shifts.  The word
+// index uses at most 10 bits (wshift >= 22), disjoint from the bit choices.
 struct BloomProbe {
   uint32_t word, mask;
 };
-__device__ __forceinline__ BloomProbe bloom_probe(uint32_t m, int wshift) {
-  uint32_t x = m * 0x9E3779B1u;
-  x ^= x >> 16;
-  x *= 0x85EBCA6Bu;
-  x ^= x >> 13;
-  uint32_t y = x * 0xC2B2AE35u;
+__device__ __forceinline__ BloomProbe bloom_probe(uint32_t h, int wshift) {
   BloomProbe p;
-  p.word = x >> wshift;
-  p.mask = (1u << (y >> 27)) | (1u << ((y >> 22) & 31u)) | (1u << ((y >> 17) & 31u));
+  p.word = h >> wshift;
+  p.mask = (1u << (h & 31u)) | (1u << ((h >> 5) & 31u)) | (1u << ((h >> 10) & 31u));
   return p;
 }
-__device__ __forceinline__ bool bloom_test(const uint32_t *bloom, int wshift, uint32_t m) {
-  BloomProbe p = bloom_probe(m, wshift);
+__device__ __forceinline__ bool bloom_test(const uint32_t *bloom, int wshift, uint32_t h) {
+  BloomProbe p = bloom_probe(h, wshift);
   return (bloom[p.word] & p.mask) == p.mask;
 }
-__device__ __forceinline__ void bloom_insert(uint32_t *bloom, int wshift, uint32_t m) {
-  BloomProbe p = bloom_probe(m, wshift);
+__device__ __forceinline__ void bloom_insert(uint32_t *bloom, int wshift, uint32_t h) {
+  BloomProbe p = bloom_probe(h, wshift);
   atomicOr(&bloom[p.word], p.mask);
 }
 
@@ -204,7 +201,7 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
     int32_t lo = L.i_lo[it], t = L.i_t[it];
     if (g.out_prv[pos] < lo) {
       int32_t at = g.out_t[pos];
-      uint32_t m = g.out_nbr[pos];
+      uint32_t m = vhash_inv(g.out_h[pos]);  // the scan has just read this line
       uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
       if (q > vrs) {
         uint64_t kk = g.inn_key[q - 1];
@@ -214,11 +211,13 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
   }
 }
 
-// Queue the Bloom-positive entries of one 64-entry step and verify a full
-// batch of 64 when the queue holds at least that many.
+// Queue the Bloom-positive entries of one 64-entry step (lane l holds
+// position pos0 + l) and verify a full batch of 64 when the queue holds at
+// least that many.  Steps without a candidate cost one scalar test.
 __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t &cq, bool cand, uint32_t a,
                                         uint32_t pos, uint32_t vrs, uint32_t vre) {
-  uint64_t bc = __ballot(cand);
+  uint64_t bc = __builtin_amdgcn_ballot_w64(cand);
+  if (bc == 0) return;
   if (cand) {
     uint32_t slot = cq + __popcll(bc & lanemask_lt());
     L.cq_pair[slot] = a;
@@ -248,19 +247,26 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, 
     uint32_t a = __ffsll((long long)longs) - 1;
     longs &= longs - 1;
     const uint32_t b = rfl(L.pr_b[a]), n = rfl(L.pr_n[a]);
-    const uint32_t u = rfl(L.i_u[rfl(L.pr_item[a])]);
+    const uint32_t hu = vhash(rfl(L.i_u[rfl(L.pr_item[a])]));  // u itself is never a candidate
     for (uint32_t f0 = 0; f0 < n; f0 += U * AMLM_WAVE) {
       if (rfl(L.pr_cnt[a]) >= need) break;
-      uint32_t m[U];
+      const uint32_t *src = g.out_h + b + f0 + lane;
+      uint32_t h[U];
+      auto step = [&]() {
 #pragma unroll
-      for (int r = 0; r < U; r++) {
-        uint32_t f = f0 + r * AMLM_WAVE + lane;
-        m[r] = f < n ? g.out_nbr[b + f] : u;  // u is never a candidate
-      }
+        for (int r = 0; r < U; r++) {
+          bool cand = (h[r] != hu) & bloom_test(L.bloom, shift, h[r]);
+          sg_push(mp, L, cq, cand, a, b + f0 + r * AMLM_WAVE + lane, vrs, vre);
+        }
+      };
+      if (f0 + U * AMLM_WAVE <= n) {
 #pragma unroll
-      for (int r = 0; r < U; r++) {
-        bool cand = m[r] != u && bloom_test(L.bloom, shift, m[r]);
-        sg_push(mp, L, cq, cand, a, b + f0 + r * AMLM_WAVE + lane, vrs, vre);
+        for (int r = 0; r < U; r++) h[r] = src[r * AMLM_WAVE];
+        step();
+      } else {
+#pragma unroll
+        for (int r = 0; r < U; r++) h[r] = f0 + r * AMLM_WAVE + lane < n ? src[r * AMLM_WAVE] : hu;
+        step();
       }
     }
   }
@@ -277,8 +283,8 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, 
       a = owner_of(L.pr_off, np, f);
       pos = L.pr_b[a] + (f - L.pr_off[a]);
       if (L.pr_cnt[a] < need) {
-        uint32_t m = g.out_nbr[pos];
-        cand = m != L.i_u[L.pr_item[a]] && bloom_test(L.bloom, shift, m);
+        uint32_t h = g.out_h[pos];
+        cand = h != vhash(L.i_u[L.pr_item[a]]) && bloom_test(L.bloom, shift, h);
       }
     }
     sg_push(mp, L, cq, cand, a, pos, vrs, vre);
@@ -320,7 +326,7 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
       }
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        if (mm[r] != 0xffffffffu) bloom_insert(L.bloom, shift, mm[r]);
+        if (mm[r] != 0xffffffffu) bloom_insert(L.bloom, shift, vhash(mm[r]));
       }
     }
     if (mp.work && lane < nit) {
