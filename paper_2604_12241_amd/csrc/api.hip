@@ -86,6 +86,7 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&a.out_prv, 4 * e));
   A_TRY(dalloc(g, (void **)&a.out_src, 4 * e));
   A_TRY(dalloc(g, (void **)&a.out_h, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.out_ts, 4 * (e / 32 + 1)));
   A_TRY(dalloc(g, (void **)&a.in_ptr, 4 * v1));
   A_TRY(dalloc(g, (void **)&a.in_nbr, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_eid, 4 * e));
@@ -156,6 +157,7 @@ GraphView graph_view(const amlm_graph *g) {
   v.out_prv = a.out_prv;
   v.out_src = a.out_src;
   v.out_h = a.out_h;
+  v.out_ts = a.out_ts;
   v.in_ptr = a.in_ptr;
   v.in_nbr = a.in_nbr;
   v.in_eid = a.in_eid;

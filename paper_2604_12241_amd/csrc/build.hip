@@ -213,6 +213,11 @@ __global__ void k_fill_rows(const uint32_t *eids, const uint32_t *other, const i
   if (row) row[p] = rowkey[p];
 }
 
+__global__ void k_line_samples(const int32_t *t, uint32_t n, int32_t *smp) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (32ull * i < n) smp[i] = t[32 * i];
+}
+
 __global__ void k_inn_keys(const uint32_t *eids, const uint32_t *src, const int32_t *t, uint32_t n, uint64_t *key) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
@@ -373,6 +378,8 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(hipMemcpyAsync(a.out_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.out_eid, a.dst, a.t, Ev, a.out_nbr,
                        a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src, a.out_h);
+    CK(hipGetLastError());
+    hipLaunchKernelGGL(k_line_samples, dim3(nblk((Ev + 31) / 32, 256)), dim3(256), 0, s, a.out_t, Ev, a.out_ts);
     CK(hipGetLastError());
     // 3. CSC: stable sort of the anchor order by destination
     hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.anc, bb.ka, bb.va, Ev);

@@ -33,6 +33,7 @@ struct GraphView {
   const uint32_t *pos_out, *pos_in;  // edge id -> CSR / CSC position
   const uint32_t *out_ptr, *out_nbr, *out_eid, *out_src;  // out_src: row (source) of each entry
   const uint32_t *out_h;  // vhash(out_nbr[p])
+  const int32_t *out_ts;  // out_t[32 i]: the first time of each 128-byte line of out_t
   const int32_t *out_t, *out_prv;
   const uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;  // in_dst: row (destination) of each entry
   const int32_t *in_t, *in_nxt;
@@ -115,6 +116,29 @@ __device__ __forceinline__ uint32_t gallop_lower_right(const int32_t *a, uint32_
     step <<= 1;
   }
   return e;
+}
+
+// The same two searches over a long sorted run, guided by the line samples
+// smp[i] = a[32 i]: a gallop over the samples (a small array that stays in
+// cache) finds the 32-entry line that holds the answer, and a binary search
+// inside that line finishes.  Only that line of `a` is read.
+__device__ __forceinline__ uint32_t lines_lower_left(const int32_t *a, const int32_t *smp, uint32_t b, uint32_t p,
+                                                     int32_t x) {
+  const uint32_t ilo = (b + 31) >> 5, ihi = p >> 5;  // samples inside [b, p]
+  if (ilo > ihi) return lower_bound_i32(a, b, p, x);
+  if (smp[ihi] < x) return lower_bound_i32(a, 32 * ihi + 1, p, x);
+  const uint32_t j = gallop_lower_left(smp, ilo, ihi, x);  // first sample >= x
+  if (j == ilo) return lower_bound_i32(a, b, 32 * ilo, x);
+  return lower_bound_i32(a, 32 * (j - 1) + 1, 32 * j, x);
+}
+__device__ __forceinline__ uint32_t lines_lower_right(const int32_t *a, const int32_t *smp, uint32_t p, uint32_t e,
+                                                      int32_t x) {
+  if (p >= e) return e;
+  const uint32_t ilo = (p + 31) >> 5, ihi = (e - 1) >> 5;  // samples inside [p, e)
+  if (ilo > ihi) return lower_bound_i32(a, p, e, x);
+  if (smp[ilo] >= x) return lower_bound_i32(a, p, 32 * ilo, x);
+  const uint32_t j = gallop_lower_right(smp, ilo + 1, ihi + 1, x);  // first sample >= x
+  return lower_bound_i32(a, 32 * (j - 1) + 1, min(32 * j, e), x);
 }
 
 // First index in [b, e) with a[i] > key, for sorted 64-bit keys.

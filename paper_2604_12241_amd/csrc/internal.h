@@ -59,7 +59,7 @@ struct GraphArrays {
   int32_t *t;
   uint32_t *anc, *pos_out, *pos_in;
   uint32_t *out_ptr, *out_nbr, *out_eid, *out_src, *out_h;
-  int32_t *out_t, *out_prv;
+  int32_t *out_t, *out_prv, *out_ts;
   uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;
   int32_t *in_t, *in_nxt;
   uint64_t *inn_key;

@@ -14,6 +14,9 @@ constexpr int kSgThreads = 64;   // one wave per block
 #ifndef AMLM_BLOOM_BITS_PER_ENTRY
 #define AMLM_BLOOM_BITS_PER_ENTRY 32
 #endif
+#ifndef AMLM_BLOOM_K
+#define AMLM_BLOOM_K 4
+#endif
 #ifndef AMLM_SG_CHUNK_MAX
 #define AMLM_SG_CHUNK_MAX 8
 #endif
@@ -22,7 +25,8 @@ constexpr int kSgThreads = 64;   // one wave per block
 #endif
 constexpr int kBloomLog2Max = AMLM_BLOOM_LOG2_MAX;      // 32 Kbit (4 KB) filter: occupancy beats a lower false-positive rate
 constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
-constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;  // blocked, 3 bits per key
+constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;  // filter bits per gathered entry
+constexpr int kBloomK = AMLM_BLOOM_K;                   // bits set per key, all in one 32-bit word
 constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
 constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave

@@ -156,16 +156,18 @@ struct SgLds {
 };
 
 // Register-blocked Bloom filter over vertex hashes (vhash): a key selects
-// one 32-bit word by its top bits and sets three bits inside it chosen by its
-// low 15 bits, so a test is a single LDS read and a few shifts.  The word
-// index uses at most 10 bits (wshift >= 22), disjoint from the bit choices.
+// one 32-bit word by its top bits and sets kBloomK bits inside it chosen by
+// consecutive 5-bit fields of its low bits, so a test is a single LDS read and
+// a few shifts.  The word index uses at most 10 bits (wshift >= 22).
 struct BloomProbe {
   uint32_t word, mask;
 };
 __device__ __forceinline__ BloomProbe bloom_probe(uint32_t h, int wshift) {
   BloomProbe p;
   p.word = h >> wshift;
-  p.mask = (1u << (h & 31u)) | (1u << ((h >> 5) & 31u)) | (1u << ((h >> 10) & 31u));
+  p.mask = 0;
+#pragma unroll
+  for (int i = 0; i < kBloomK; i++) p.mask |= 1u << ((h >> (5 * i)) & 31u);
   return p;
 }
 __device__ __forceinline__ bool bloom_test(const uint32_t *bloom, int wshift, uint32_t h) {
@@ -187,9 +189,12 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t *off, uint32_t n, ui
   return a;
 }
 
-// Confirm `take` queued candidates (from the top of the queue): the entry
-// must be the first (s, m) edge inside the window and m must have an edge to
-// v later than it and no later than the anchor.
+// Confirm `take` queued candidates (from the top of the queue): m must have
+// an edge to v later than the (s, m) entry and no later than the anchor, and
+// the entry must be the first (s, m) edge inside the window.  The search in
+// v's CSC-N row comes first: it rejects the filter's false positives from
+// lines that the segment's other candidates keep in cache, before any read
+// of the sender's row.
 __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint32_t take, uint32_t vrs,
                           uint32_t vre) {
   const GraphView &g = mp.g;
@@ -199,14 +204,12 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
     uint32_t a = L.cq_pair[idx], pos = L.cq_pos[idx];
     uint32_t it = L.pr_item[a];
     int32_t lo = L.i_lo[it], t = L.i_t[it];
-    if (g.out_prv[pos] < lo) {
-      int32_t at = g.out_t[pos];
-      uint32_t m = vhash_inv(g.out_h[pos]);  // the scan has just read this line
-      uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
-      if (q > vrs) {
-        uint64_t kk = g.inn_key[q - 1];
-        if ((uint32_t)(kk >> 32) == m && (int32_t)(uint32_t)kk > at) atomicAdd(&L.pr_cnt[a], 1u);
-      }
+    uint32_t m = vhash_inv(g.out_h[pos]);  // the scan has just read this line
+    uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+    if (q > vrs) {
+      uint64_t kk = g.inn_key[q - 1];  // the last m -> v edge at or before t, if any
+      if ((uint32_t)(kk >> 32) == m && g.out_prv[pos] < lo && (int32_t)(uint32_t)kk > g.out_t[pos])
+        atomicAdd(&L.pr_cnt[a], 1u);
     }
   }
 }
@@ -366,8 +369,8 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     if (is_s) {
       // s's out-window [lo, t) contains apos: gallop outwards from it
       uint32_t rs = g.out_ptr[nb], re = g.out_ptr[nb + 1];
-      b = gallop_lower_left(g.out_t, rs, apos, L.i_lo[it]);
-      n = gallop_lower_right(g.out_t, apos + 1, re, L.i_t[it]) - b;
+      b = lines_lower_left(g.out_t, g.out_ts, rs, apos, L.i_lo[it]);
+      n = lines_lower_right(g.out_t, g.out_ts, apos + 1, re, L.i_t[it]) - b;
       if (mp.work) atomicAdd(&L.i_work[it], kBytesJoinEntry * n);
     }
     uint32_t np = __popcll(bs);
@@ -383,13 +386,12 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   }
 }
 
-// Gather-scatter for one anchor when the lane-serial scan hit its cap.
-__device__ uint32_t gs_wave(const MineParams &mp, uint32_t u, int32_t tau, int32_t t, uint32_t k, uint32_t *work) {
+// Gather-scatter for one anchor when the lane-serial scan hit its cap: count
+// the first (u, d) edges after tau among u's out-row positions [d0, d1).
+__device__ uint32_t gs_wave(const MineParams &mp, uint32_t d0, uint32_t d1, int32_t tau, uint32_t k,
+                            uint32_t *work) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
-  uint32_t rs = rfl(g.out_ptr[u]), re = rfl(g.out_ptr[u + 1]);
-  uint32_t d0 = rfl(upper_bound_i32(g.out_t, rs, re, tau));
-  uint32_t d1 = rfl(upper_bound_i32(g.out_t, d0, re, t));
   uint32_t nd = 0;
   for (uint32_t c = d0; c < d1; c += AMLM_WAVE) {
     uint32_t j = c + lane;
@@ -460,23 +462,26 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
     // gather-scatter and the outputs, one lane per anchor
     uint32_t sg = 0, gs = 0;
     bool gs_wide = false;
-    uint32_t ns = 0, u = 0, work = 0, k = 1;
-    int32_t tau = 0, t = 0;
+    uint32_t ns = 0, work = 0, k = 1, d0 = 0, d1 = 0;
+    int32_t tau = 0;
     if (lane < nr) {
       k = L.i_k[lane];
       ns = L.i_ns[lane];
       sg = k == 1 ? ns : L.i_sg[lane];
-      u = L.i_u[lane];
       tau = L.i_tau[lane];
-      t = L.i_t[lane];
       work = L.i_work[lane];
       if (mp.col_gs >= 0 && ns >= k && ns > 0) {
         if (k == 1) {
           gs = ns;  // v follows tau, so D is never empty
         } else {
-          uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
-          uint32_t d0 = upper_bound_i32(g.out_t, rs, re, tau);
-          uint32_t d1 = upper_bound_i32(g.out_t, d0, re, t);
+          // u's out-edges in (tau, t]: gallop outwards from the anchor's own
+          // position in u's out-row
+          const uint32_t u = L.i_u[lane];
+          const int32_t t = L.i_t[lane];
+          const uint32_t ap = g.pos_out[L.i_eid[lane]];
+          const uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
+          d0 = gallop_lower_left(g.out_t, rs, ap, tau + 1);
+          d1 = gallop_upper_right(g.out_t, ap + 1, re, t);
           uint32_t nd = 0, j = d0;
           for (; j < d1 && j < d0 + kGsLaneCap && nd < k; j++) nd += g.out_prv[j] <= tau;
           work += kBytesScatterEntry * (j - d0);
@@ -489,11 +494,11 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
     while (wide) {
       uint32_t a = __ffsll((long long)wide) - 1;
       wide &= wide - 1;
-      uint32_t ua = rfl((uint32_t)__shfl(u, a, AMLM_WAVE));
-      int32_t ta = rfl(__shfl(tau, a, AMLM_WAVE)), tt = rfl(__shfl(t, a, AMLM_WAVE));
+      uint32_t a0 = rfl((uint32_t)__shfl(d0, a, AMLM_WAVE)), a1 = rfl((uint32_t)__shfl(d1, a, AMLM_WAVE));
+      int32_t ta = rfl(__shfl(tau, a, AMLM_WAVE));
       uint32_t ka = rfl((uint32_t)__shfl(k, a, AMLM_WAVE));
       uint32_t wk = 0;
-      uint32_t nd = gs_wave(mp, ua, ta, tt, ka, &wk);
+      uint32_t nd = gs_wave(mp, a0, a1, ta, ka, &wk);
       if (lane == a) {
         work += wk;
         if (nd >= ka) gs = ns;
