@@ -134,25 +134,49 @@ __global__ __launch_bounds__(kThreads) void k_rs_hist(const uint32_t *keys, uint
   hist[tid * nblocks + blockIdx.x] = s;
 }
 
-// Stable scatter: ranks follow the (iteration, wave, lane) order, which is
-// the input order inside the tile.
+// Stable scatter.  Ranks follow the (iteration, wave, lane) order, which is
+// the input order inside the tile; the tile is first sorted by digit in LDS
+// and then written out bucket by bucket, so that consecutive threads store
+// to consecutive addresses of one bucket.
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                                                          uint32_t *vout, uint32_t n, int shift,
                                                          const uint32_t *offs, uint32_t nblocks) {
   constexpr int NW = kThreads / AMLM_WAVE;
-  __shared__ uint32_t run[256];
+  __shared__ uint32_t sk[kTile], sv[kTile];
+  __shared__ uint32_t run[256], start[256], gbase[256];
   __shared__ uint32_t wc[NW][256];
-  uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
-  run[tid] = offs[tid * nblocks + blockIdx.x];
+  __shared__ uint32_t wsum[NW];
+  const uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE, lane = lane_id();
+  const uint32_t base = blockIdx.x * kTile;
+  const uint32_t tn = min(kTile, n - base);
+  // tile histogram, then its exclusive scan: the tile-local start of each bucket
   for (int q = 0; q < NW; q++) wc[q][tid] = 0;
   __syncthreads();
-  uint32_t base = blockIdx.x * kTile;
-  uint64_t lt = lanemask_lt();
   for (int j = 0; j < kItems; j++) {
-    uint32_t idx = base + j * kThreads + tid;
-    bool valid = idx < n;
-    uint32_t key = valid ? kin[idx] : 0u;
-    uint32_t val = valid ? vin[idx] : 0u;
+    uint32_t idx = j * kThreads + tid;
+    if (idx < tn) atomicAdd(&wc[w][(kin[base + idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  uint32_t cnt = 0;
+  for (int q = 0; q < NW; q++) {
+    cnt += wc[q][tid];
+    wc[q][tid] = 0;
+  }
+  const uint32_t incl = wave_incl_scan(cnt);
+  if (lane == AMLM_WAVE - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t q = 0; q < w; q++) before += wsum[q];
+  start[tid] = before + incl - cnt;
+  run[tid] = before + incl - cnt;
+  gbase[tid] = offs[tid * nblocks + blockIdx.x];
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  for (int j = 0; j < kItems; j++) {
+    uint32_t idx = j * kThreads + tid;
+    bool valid = idx < tn;
+    uint32_t key = valid ? kin[base + idx] : 0u;
+    uint32_t val = valid ? vin[base + idx] : 0u;
     uint32_t d = (key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -167,8 +191,8 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *kin, co
     if (valid) {
       uint32_t pos = run[d] + rank;
       for (uint32_t q = 0; q < w; q++) pos += wc[q][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      sk[pos] = key;
+      sv[pos] = val;
     }
     __syncthreads();
     uint32_t tot = 0;
@@ -178,6 +202,13 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *kin, co
     }
     run[tid] += tot;
     __syncthreads();
+  }
+  for (uint32_t i = tid; i < tn; i += kThreads) {
+    uint32_t key = sk[i];
+    uint32_t d = (key >> shift) & 255u;
+    uint32_t pos = gbase[d] + (i - start[d]);
+    kout[pos] = key;
+    vout[pos] = sv[i];
   }
 }
 
@@ -392,8 +423,9 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
                        a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst, (uint32_t *)nullptr);
     CK(hipGetLastError());
     // 4. CSC-N: stable sort of the CSR order (source, time, id) by destination
-    hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.out_eid, bb.ka, bb.va, Ev);
-    CK(hipGetLastError());
+    //    (the destination of CSR entry p is out_nbr[p])
+    CK(hipMemcpyAsync(bb.ka, a.out_nbr, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
+    CK(hipMemcpyAsync(bb.va, a.out_eid, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
     CK(hipMemcpyAsync(a.inn_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_inn_keys, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.inn_eid, a.src, a.t, Ev, a.inn_key);
