@@ -106,6 +106,7 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   size_t tw = std::max(scan_tmp_words(hw), scan_tmp_words(v1));
   A_TRY(dalloc(g, (void **)&b.scan_tmp, 4 * tw));
   A_TRY(dalloc(g, (void **)&b.stats, 8 * 8));
+  A_TRY(dalloc(g, (void **)&b.ep, 16 * e));
   A_TRY(dalloc(g, (void **)&g->err_dev, 64));
   A_TRY(dalloc(g, (void **)&g->ts_stage, 8 * e));
   g->cap_e = E;

@@ -62,12 +62,14 @@ __global__ void k_init_stats(unsigned long long *stats) {
 // relative times, edge copies, and the first sort key:
 // key = self_loop << t_bits | t_rel, value = edge id
 __global__ void k_reltime(const int64_t *ts, int64_t tmin, const uint32_t *src, const uint32_t *dst, uint32_t E,
-                          int t_bits, int32_t *t, uint32_t *key, uint32_t *val, int with_time_key) {
+                          int t_bits, int32_t *t, uint32_t *key, uint32_t *val, int with_time_key, uint4 *ep) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
   int32_t tr = (int32_t)(ts[i] - tmin);
+  uint32_t s = src[i], d = dst[i];
   t[i] = tr;
-  uint32_t loop = src[i] == dst[i];
+  ep[i] = make_uint4(s, d, (uint32_t)tr, 0u);  // one line per random read in the row fills
+  uint32_t loop = s == d;
   key[i] = with_time_key ? ((loop << t_bits) | (uint32_t)tr) : loop;
   val[i] = i;
 }
@@ -230,18 +232,22 @@ __global__ void k_row_ptr(const uint32_t *keys, uint32_t n, uint32_t V, uint32_t
   for (int64_t x = kprev + 1; x <= kp; x++) ptr[x] = p;
 }
 
-__global__ void k_fill_rows(const uint32_t *eids, const uint32_t *other, const int32_t *t, uint32_t n,
+// Row fill after a sort: entry p takes edge eids[p]; `col` picks the other
+// endpoint from the packed edge (0: source, 1: destination).
+__global__ void k_fill_rows(const uint32_t *eids, uint32_t *eids_out, const uint4 *ep, int col, uint32_t n,
                             uint32_t *nbr, int32_t *tt, uint32_t *pos, const uint32_t *rowkey, uint32_t *row,
                             uint32_t *hnbr) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   uint32_t e = eids[p];
-  uint32_t o = other[e];
+  uint4 x = ep[e];
+  uint32_t o = col ? x.y : x.x;
+  eids_out[p] = e;
   nbr[p] = o;
   if (hnbr) hnbr[p] = vhash(o);
-  tt[p] = t[e];
+  tt[p] = (int32_t)x.z;
   pos[e] = p;
-  if (row) row[p] = rowkey[p];
+  row[p] = rowkey[p];
 }
 
 __global__ void k_line_samples(const int32_t *t, uint32_t n, int32_t *smp) {
@@ -249,11 +255,13 @@ __global__ void k_line_samples(const int32_t *t, uint32_t n, int32_t *smp) {
   if (32ull * i < n) smp[i] = t[32 * i];
 }
 
-__global__ void k_inn_keys(const uint32_t *eids, const uint32_t *src, const int32_t *t, uint32_t n, uint64_t *key) {
+__global__ void k_inn_keys(const uint32_t *eids, uint32_t *eids_out, const uint4 *ep, uint32_t n, uint64_t *key) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   uint32_t e = eids[q];
-  key[q] = nbr_key(src[e], t[e]);
+  uint4 x = ep[e];
+  eids_out[q] = e;
+  key[q] = nbr_key(x.x, (int32_t)x.z);
 }
 
 // same-pair time links from the (dst, src, time)-sorted index
@@ -389,7 +397,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
   if (E) {
     int with_time = time_sorted ? 0 : 1;
     hipLaunchKernelGGL(k_reltime, dim3(nblk(E, 256)), dim3(256), 0, s, ts, tmin, a.src, a.dst, E, t_bits, a.t,
-                       bb.ka, bb.va, with_time);
+                       bb.ka, bb.va, with_time, bb.ep);
     CK(hipGetLastError());
     int sort_bits = time_sorted ? (n_self ? 1 : 0) : t_bits + 1;
     uint32_t *ks, *vs;
@@ -406,9 +414,9 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
     hipLaunchKernelGGL(k_row_ptr, dim3(nblk((uint64_t)Ev + 1, 256)), dim3(256), 0, s, ks, Ev, V, a.out_ptr);
     CK(hipGetLastError());
-    CK(hipMemcpyAsync(a.out_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.out_eid, a.dst, a.t, Ev, a.out_nbr,
-                       a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src, a.out_h);
+    hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.out_eid,
+                       (const uint4 *)bb.ep, 1, Ev, a.out_nbr, a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src,
+                       a.out_h);
     CK(hipGetLastError());
     hipLaunchKernelGGL(k_line_samples, dim3(nblk((Ev + 31) / 32, 256)), dim3(256), 0, s, a.out_t, Ev, a.out_ts);
     CK(hipGetLastError());
@@ -418,17 +426,17 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
     hipLaunchKernelGGL(k_row_ptr, dim3(nblk((uint64_t)Ev + 1, 256)), dim3(256), 0, s, ks, Ev, V, a.in_ptr);
     CK(hipGetLastError());
-    CK(hipMemcpyAsync(a.in_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.in_eid, a.src, a.t, Ev, a.in_nbr,
-                       a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.in_eid,
+                       (const uint4 *)bb.ep, 0, Ev, a.in_nbr, a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst,
+                       (uint32_t *)nullptr);
     CK(hipGetLastError());
     // 4. CSC-N: stable sort of the CSR order (source, time, id) by destination
     //    (the destination of CSR entry p is out_nbr[p])
     CK(hipMemcpyAsync(bb.ka, a.out_nbr, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     CK(hipMemcpyAsync(bb.va, a.out_eid, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
-    CK(hipMemcpyAsync(a.inn_eid, vs, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_inn_keys, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.inn_eid, a.src, a.t, Ev, a.inn_key);
+    hipLaunchKernelGGL(k_inn_keys, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.inn_eid,
+                       (const uint4 *)bb.ep, Ev, a.inn_key);
     CK(hipGetLastError());
     // 5. same-pair links (ks still holds the destination of every CSC-N entry)
     hipLaunchKernelGGL(k_links, dim3(nblk(Ev, 256)), dim3(256), 0, s, ks, a.inn_key, a.inn_eid, Ev, a.pos_in,

@@ -33,6 +33,7 @@ struct BuildBuffers {
   uint32_t *ka = nullptr, *kb = nullptr, *va = nullptr, *vb = nullptr;
   uint32_t *hist = nullptr, *hist2 = nullptr, *scan_tmp = nullptr;
   uint64_t *stats = nullptr;  // [8] validation results
+  uint4 *ep = nullptr;        // per edge id: (source, destination, relative time, 0)
   size_t cap_n = 0, cap_hist = 0, cap_tmp = 0;
 };
 
