@@ -4,6 +4,10 @@
 #include "internal.h"
 
 constexpr uint8_t kFlagSG = 1, kFlagCYC = 2;
+// scatter-gather anchor whose v has no in-neighbour other than u inside the
+// anchor's window: no intermediate besides u exists, so SG_k is 0 for k >= 2
+// and the anchor needs no join (only its senders, for GS_k)
+constexpr uint8_t kFlagSgNoJoin = 4;
 // senders-window slices up to this length are classified by the anchor lane
 constexpr uint32_t kAnchorScanCap = 16;
 

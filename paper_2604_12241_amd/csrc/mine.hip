@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
   }
 }
 
-__global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, const uint8_t *flags_sg, uint8_t *flags_cy,
+__global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags_sg, uint8_t *flags_cy,
                                                    uint4 *sg_win, uint32_t *feat) {
   const GraphView &g = mp.g;
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,6 +119,13 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, const uint8_t 
     if (is_sg) {
       sg_win[q].z = lb;
       sg_win[q].w = hi;
+      // short windows: look for an in-neighbour other than u (longer ones
+      // are taken to have one)
+      if (hi - lb <= kAnchorScanCap) {
+        bool other = false;
+        for (uint32_t j = lb; j < hi; j++) other |= g.in_nbr[j] != u;
+        if (!other) flags_sg[q] = kFlagSG | kFlagSgNoJoin;
+      }
       if (feat) {
         feat[(uint64_t)q * kMlpRaw + 1] = hi - lb;
         feat[(uint64_t)q * kMlpRaw + 7] = re - rs;
@@ -149,6 +156,7 @@ struct SgLds {
   int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax], i_tau[kSgChunkMax];
   uint32_t i_q[kSgChunkMax];    // CSC position of each anchor (its v-window is in sg_win)
   uint32_t i_k[kSgChunkMax];    // threshold k of each anchor
+  uint32_t i_join[kSgChunkMax]; // 1 if the anchor's senders need the join
   // (anchor, sender) pairs of one batch
   uint32_t pr_item[AMLM_WAVE], pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
   // Bloom-positive candidates awaiting the exact check
@@ -307,7 +315,8 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   const uint64_t lt = lanemask_lt();
   const uint32_t nit = s1 - s0;
   const uint32_t k = rfl(L.i_k[s0]);  // the anchors of a segment share v, hence the (sub-)graph
-  const bool need_join = mp.col_sg >= 0 && k >= 2;
+  const bool need_join = mp.col_sg >= 0 && k >= 2 &&
+                         __ballot(lane >= s0 && lane < s1 && L.i_join[min(lane, kSgChunkMax - 1)] != 0) != 0;
   int shift = 0;
   uint32_t vrs = rfl(g.in_ptr[v]), vre = rfl(g.in_ptr[v + 1]);
   if (need_join) {
@@ -345,36 +354,35 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   for (uint32_t f0 = 0; f0 < W; f0 += AMLM_WAVE) {
     uint32_t f = f0 + lane;
     bool is_s = false;
-    uint32_t it = 0, nb = 0, apos = 0;
+    uint32_t it = 0, nb = 0, j = 0;
     if (f < W) {
       uint32_t a = owner_of(L.seg_off, nit, f);
       it = s0 + a;
-      uint32_t j = L.i_p0[it] + (f - L.seg_off[a]);
+      j = L.i_p0[it] + (f - L.seg_off[a]);
       nb = g.in_nbr[j];
       if (nb != v) {
         atomicMin(&L.i_tau[it], g.in_t[j]);
         is_s = g.in_nxt[j] >= L.i_t[it];  // last sender edge before t: one per distinct s
-        if (is_s) {
-          atomicAdd(&L.i_ns[it], 1u);
-          apos = g.pos_out[g.in_eid[j]];  // this s -> u edge inside s's out-row
-        }
+        if (is_s) atomicAdd(&L.i_ns[it], 1u);
       }
       if (mp.work) atomicAdd(&L.i_work[it], kBytesSenderEntry);
     }
     if (!need_join) continue;
-    uint64_t bs = __ballot(is_s);
+    const bool pair = is_s && L.i_join[it] != 0;
+    uint64_t bs = __ballot(pair);
     if (!bs) continue;
     // this lane's pair: slice of s's out-row inside [lo, t)
     uint32_t b = 0, n = 0;
-    if (is_s) {
-      // s's out-window [lo, t) contains apos: gallop outwards from it
-      uint32_t rs = g.out_ptr[nb], re = g.out_ptr[nb + 1];
+    if (pair) {
+      // s's out-window [lo, t) contains the s -> u edge: search outwards from it
+      const uint32_t apos = g.pos_out[g.in_eid[j]];
+      const uint32_t rs = g.out_ptr[nb], re = g.out_ptr[nb + 1];
       b = lines_lower_left(g.out_t, g.out_ts, rs, apos, L.i_lo[it]);
       n = lines_lower_right(g.out_t, g.out_ts, apos + 1, re, L.i_t[it]) - b;
       if (mp.work) atomicAdd(&L.i_work[it], kBytesJoinEntry * n);
     }
     uint32_t np = __popcll(bs);
-    if (is_s) {
+    if (pair) {
       uint32_t slot = __popcll(bs & lt);
       L.pr_item[slot] = it;
       L.pr_b[slot] = b;
@@ -407,7 +415,7 @@ constexpr uint32_t kGsLaneCap = 32;
 
 __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
                                                  uint32_t *ctr, uint32_t chunk, const uint4 *sg_win,
-                                                 const uint32_t *chunk_tab) {
+                                                 const uint32_t *chunk_tab, const uint8_t *flags_sg) {
   __shared__ SgLds L;
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
@@ -438,6 +446,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       dl = delta_of(mp, v);
       L.i_lo[lane] = window_lo(t, dl);
       L.i_k[lane] = k_of(mp, v);
+      L.i_join[lane] = (flags_sg[q] & kFlagSgNoJoin) ? 0u : 1u;
       L.i_p0[lane] = pw.x;
       L.i_wlen[lane] = pw.y - pw.x;
       L.i_ns[lane] = 0;
@@ -811,7 +820,8 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   if (want_sg) {
     CK(tm->begin(kStSg, s));
     hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, n_sg,
-                       ms.ctr + kCtrSgWork, chunk, (const uint4 *)ms.sg_win, chunk_tab);
+                       ms.ctr + kCtrSgWork, chunk, (const uint4 *)ms.sg_win, chunk_tab,
+                       (const uint8_t *)flags_sg);
     CK(hipGetLastError());
     CK(tm->end(kStSg, s));
   }
