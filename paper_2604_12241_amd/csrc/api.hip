@@ -93,6 +93,7 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&a.in_t, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_nxt, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_dst, 4 * e));
+  A_TRY(dalloc(g, (void **)&a.in_h, 4 * e));
   A_TRY(dalloc(g, (void **)&a.inn_key, 8 * e));
   A_TRY(dalloc(g, (void **)&a.inn_eid, 4 * e));
   BuildBuffers &b = g->bb;
@@ -165,6 +166,7 @@ GraphView graph_view(const amlm_graph *g) {
   v.in_t = a.in_t;
   v.in_nxt = a.in_nxt;
   v.in_dst = a.in_dst;
+  v.in_h = a.in_h;
   v.inn_key = a.inn_key;
   v.inn_eid = a.inn_eid;
   return v;

@@ -428,7 +428,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(hipGetLastError());
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.in_eid,
                        (const uint4 *)bb.ep, 0, Ev, a.in_nbr, a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst,
-                       (uint32_t *)nullptr);
+                       a.in_h);
     CK(hipGetLastError());
     // 4. CSC-N: stable sort of the CSR order (source, time, id) by destination
     //    (the destination of CSR entry p is out_nbr[p])

@@ -36,6 +36,7 @@ struct GraphView {
   const int32_t *out_ts;  // out_t[32 i]: the first time of each 128-byte line of out_t
   const int32_t *out_t, *out_prv;
   const uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;  // in_dst: row (destination) of each entry
+  const uint32_t *in_h;  // vhash(in_nbr[q])
   const int32_t *in_t, *in_nxt;
   const uint64_t *inn_key;
   const uint32_t *inn_eid;

@@ -61,7 +61,7 @@ struct GraphArrays {
   uint32_t *anc, *pos_out, *pos_in;
   uint32_t *out_ptr, *out_nbr, *out_eid, *out_src, *out_h;
   int32_t *out_t, *out_prv, *out_ts;
-  uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;
+  uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst, *in_h;
   int32_t *in_t, *in_nxt;
   uint64_t *inn_key;
   uint32_t *inn_eid;

@@ -334,11 +334,11 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         uint32_t q = q0 + r * AMLM_WAVE + lane;
-        mm[r] = q < r1 ? g.in_nbr[q] : 0xffffffffu;
+        mm[r] = q < r1 ? g.in_h[q] : 0u;
       }
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        if (mm[r] != 0xffffffffu) bloom_insert(L.bloom, shift, vhash(mm[r]));
+        if (q0 + r * AMLM_WAVE + lane < r1) bloom_insert(L.bloom, shift, mm[r]);
       }
     }
     if (mp.work && lane < nit) {
