@@ -8,6 +8,10 @@ constexpr uint8_t kFlagSG = 1, kFlagCYC = 2;
 // anchor's window: no intermediate besides u exists, so SG_k is 0 for k >= 2
 // and the anchor needs no join (only its senders, for GS_k)
 constexpr uint8_t kFlagSgNoJoin = 4;
+// scatter-gather anchor (k >= 2) whose u has at least k distinct scatter
+// destinations in (tau, t], tau the earliest sender time: decided by the CSR
+// pass, where u's out-row is at hand
+constexpr uint8_t kFlagGsDest = 8;
 // senders-window slices up to this length are classified by the anchor lane
 constexpr uint32_t kAnchorScanCap = 16;
 

@@ -86,7 +86,23 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
     if (item) {
       // scatter-gather anchors are listed in CSC order: grouped by v, time-sorted
       uint32_t q = g.pos_in[eid];
-      flags_sg[q] = kFlagSG;
+      uint8_t fl = kFlagSG;
+      if (mp.col_gs >= 0 && k >= 2) {
+        // gather-scatter's destination side: u's first edges to each d in
+        // (tau, t], tau = the earliest sender edge (senders exclude v)
+        uint32_t j = p0;
+        while (j < p1 && g.in_nbr[j] == v) j++;
+        if (j < p1) {
+          const int32_t tau = g.in_t[j];
+          const uint32_t d0 = gallop_lower_left(g.out_t, rs, p, tau + 1);
+          const uint32_t d1 = gallop_upper_right(g.out_t, p + 1, re, t);
+          uint32_t nd = 0, c = d0;
+          for (; c < d1 && nd < k; c++) nd += g.out_prv[c] <= tau;
+          if (nd >= k) fl |= kFlagGsDest;
+          if (mp.work) atomicAdd(&mp.work[eid], kBytesScatterEntry * (c - d0));
+        }
+      }
+      flags_sg[q] = fl;
       sg_win[q].x = p0;
       sg_win[q].y = p1;
       if (feat) {
@@ -124,7 +140,7 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
       if (hi - lb <= kAnchorScanCap) {
         bool other = false;
         for (uint32_t j = lb; j < hi; j++) other |= g.in_nbr[j] != u;
-        if (!other) flags_sg[q] = kFlagSG | kFlagSgNoJoin;
+        if (!other) flags_sg[q] |= kFlagSgNoJoin;
       }
       if (feat) {
         feat[(uint64_t)q * kMlpRaw + 1] = hi - lb;
@@ -153,10 +169,11 @@ struct SgLds {
   uint32_t i_eid[kSgChunkMax], i_u[kSgChunkMax], i_p0[kSgChunkMax], i_ns[kSgChunkMax], i_sg[kSgChunkMax];
   uint32_t i_work[kSgChunkMax], i_wlen[kSgChunkMax];
   uint32_t seg_off[AMLM_WAVE];  // exclusive offsets of the segment's sender windows
-  int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax], i_tau[kSgChunkMax];
+  int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax];
   uint32_t i_q[kSgChunkMax];    // CSC position of each anchor (its v-window is in sg_win)
   uint32_t i_k[kSgChunkMax];    // threshold k of each anchor
   uint32_t i_join[kSgChunkMax]; // 1 if the anchor's senders need the join
+  uint32_t i_gsd[kSgChunkMax];  // 1 if u has k scatter destinations after tau
   // (anchor, sender) pairs of one batch
   uint32_t pr_item[AMLM_WAVE], pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
   // Bloom-positive candidates awaiting the exact check
@@ -361,7 +378,6 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
       j = L.i_p0[it] + (f - L.seg_off[a]);
       nb = g.in_nbr[j];
       if (nb != v) {
-        atomicMin(&L.i_tau[it], g.in_t[j]);
         is_s = g.in_nxt[j] >= L.i_t[it];  // last sender edge before t: one per distinct s
         if (is_s) atomicAdd(&L.i_ns[it], 1u);
       }
@@ -393,25 +409,6 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     if (lane < np && L.pr_cnt[lane] >= k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
   }
 }
-
-// Gather-scatter for one anchor when the lane-serial scan hit its cap: count
-// the first (u, d) edges after tau among u's out-row positions [d0, d1).
-__device__ uint32_t gs_wave(const MineParams &mp, uint32_t d0, uint32_t d1, int32_t tau, uint32_t k,
-                            uint32_t *work) {
-  const GraphView &g = mp.g;
-  const uint32_t lane = lane_id();
-  uint32_t nd = 0;
-  for (uint32_t c = d0; c < d1; c += AMLM_WAVE) {
-    uint32_t j = c + lane;
-    bool first = j < d1 && g.out_prv[j] <= tau;  // first (u, d) edge after tau
-    nd += __popcll(__ballot(first));
-    *work += kBytesScatterEntry * min((uint32_t)AMLM_WAVE, d1 - c);
-    if (nd >= k) break;
-  }
-  return nd;
-}
-
-constexpr uint32_t kGsLaneCap = 32;
 
 __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
                                                  uint32_t *ctr, uint32_t chunk, const uint4 *sg_win,
@@ -446,12 +443,13 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       dl = delta_of(mp, v);
       L.i_lo[lane] = window_lo(t, dl);
       L.i_k[lane] = k_of(mp, v);
-      L.i_join[lane] = (flags_sg[q] & kFlagSgNoJoin) ? 0u : 1u;
+      const uint8_t fl = flags_sg[q];
+      L.i_join[lane] = (fl & kFlagSgNoJoin) ? 0u : 1u;
+      L.i_gsd[lane] = (fl & kFlagGsDest) ? 1u : 0u;
       L.i_p0[lane] = pw.x;
       L.i_wlen[lane] = pw.y - pw.x;
       L.i_ns[lane] = 0;
       L.i_sg[lane] = 0;
-      L.i_tau[lane] = AMLM_INT_MAX;
       L.i_work[lane] = kBytesAnchorSg;
     }
     // segments: runs of anchors into the same v inside one time bucket of
@@ -469,49 +467,13 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       sg_segment(mp, L, s0, s1, vs, sg_win);
     }
     // gather-scatter and the outputs, one lane per anchor
-    uint32_t sg = 0, gs = 0;
-    bool gs_wide = false;
-    uint32_t ns = 0, work = 0, k = 1, d0 = 0, d1 = 0;
-    int32_t tau = 0;
+    uint32_t sg = 0, gs = 0, work = 0;
     if (lane < nr) {
-      k = L.i_k[lane];
-      ns = L.i_ns[lane];
+      const uint32_t k = L.i_k[lane], ns = L.i_ns[lane];
       sg = k == 1 ? ns : L.i_sg[lane];
-      tau = L.i_tau[lane];
       work = L.i_work[lane];
-      if (mp.col_gs >= 0 && ns >= k && ns > 0) {
-        if (k == 1) {
-          gs = ns;  // v follows tau, so D is never empty
-        } else {
-          // u's out-edges in (tau, t]: gallop outwards from the anchor's own
-          // position in u's out-row
-          const uint32_t u = L.i_u[lane];
-          const int32_t t = L.i_t[lane];
-          const uint32_t ap = g.pos_out[L.i_eid[lane]];
-          const uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
-          d0 = gallop_lower_left(g.out_t, rs, ap, tau + 1);
-          d1 = gallop_upper_right(g.out_t, ap + 1, re, t);
-          uint32_t nd = 0, j = d0;
-          for (; j < d1 && j < d0 + kGsLaneCap && nd < k; j++) nd += g.out_prv[j] <= tau;
-          work += kBytesScatterEntry * (j - d0);
-          if (nd >= k) gs = ns;
-          else if (j < d1) gs_wide = true;
-        }
-      }
-    }
-    uint64_t wide = __ballot(gs_wide);
-    while (wide) {
-      uint32_t a = __ffsll((long long)wide) - 1;
-      wide &= wide - 1;
-      uint32_t a0 = rfl((uint32_t)__shfl(d0, a, AMLM_WAVE)), a1 = rfl((uint32_t)__shfl(d1, a, AMLM_WAVE));
-      int32_t ta = rfl(__shfl(tau, a, AMLM_WAVE));
-      uint32_t ka = rfl((uint32_t)__shfl(k, a, AMLM_WAVE));
-      uint32_t wk = 0;
-      uint32_t nd = gs_wave(mp, a0, a1, ta, ka, &wk);
-      if (lane == a) {
-        work += wk;
-        if (nd >= ka) gs = ns;
-      }
+      // k == 1: v follows tau, so D is never empty
+      if (mp.col_gs >= 0 && ns >= k && ns > 0 && (k == 1 || L.i_gsd[lane])) gs = ns;
     }
     if (lane < nr) {
       uint32_t eid = L.i_eid[lane];
