@@ -86,7 +86,10 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&a.out_prv, 4 * e));
   A_TRY(dalloc(g, (void **)&a.out_src, 4 * e));
   A_TRY(dalloc(g, (void **)&a.out_h, 4 * e));
-  A_TRY(dalloc(g, (void **)&a.out_ts, 4 * (e / 32 + 1)));
+  A_TRY(dalloc(g, (void **)&a.out_tm, 16 * v1));
+  A_TRY(dalloc(g, (void **)&a.out_tix, 4 * (e / kTixPerBucket + 2 * v1 + 2)));
+  A_TRY(dalloc(g, (void **)&a.tix_cnt, 4 * v1));
+  A_TRY(dalloc(g, (void **)&a.tix_off, 4 * v1));
   A_TRY(dalloc(g, (void **)&a.in_ptr, 4 * v1));
   A_TRY(dalloc(g, (void **)&a.in_nbr, 4 * e));
   A_TRY(dalloc(g, (void **)&a.in_eid, 4 * e));
@@ -159,7 +162,8 @@ GraphView graph_view(const amlm_graph *g) {
   v.out_prv = a.out_prv;
   v.out_src = a.out_src;
   v.out_h = a.out_h;
-  v.out_ts = a.out_ts;
+  v.out_tm = a.out_tm;
+  v.out_tix = a.out_tix;
   v.in_ptr = a.in_ptr;
   v.in_nbr = a.in_nbr;
   v.in_eid = a.in_eid;

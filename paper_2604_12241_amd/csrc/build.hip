@@ -250,9 +250,44 @@ __global__ void k_fill_rows(const uint32_t *eids, uint32_t *eids_out, const uint
   row[p] = rowkey[p];
 }
 
-__global__ void k_line_samples(const int32_t *t, uint32_t n, int32_t *smp) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (32ull * i < n) smp[i] = t[32 * i];
+// Row time index (layout next to tix_lower_bound): bucket counts per row ...
+__global__ void k_tix_count(const uint32_t *ptr, const int32_t *t, uint32_t V, uint4 *meta, uint32_t *cnt) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const uint32_t rs = ptr[v], re = ptr[v + 1], len = re - rs;
+  uint4 m = make_uint4(0u, 0u, 0u, 0u);
+  if (len > kTixMinRow) {
+    const int32_t t0 = t[rs], t1 = t[re - 1];
+    const uint32_t span = (uint32_t)(t1 - t0), maxnb = (len + kTixPerBucket - 1) / kTixPerBucket;
+    uint32_t w = 0;
+    while ((span >> w) + 1 > maxnb) w++;
+    m = make_uint4(0u, (span >> w) + 1, (uint32_t)t0, w);
+  }
+  meta[v] = m;
+  cnt[v] = m.y ? m.y + 1 : 0u;
+}
+// ... their offsets ...
+__global__ void k_tix_offsets(const uint32_t *off, uint32_t V, uint4 *meta) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) meta[v].x = off[v];
+}
+// ... and the bucket starts: entry p writes the buckets that begin after its
+// predecessor's time and at or before its own (the row's last entry also
+// writes the ones after it, up to the end sentinel).
+__global__ void k_tix_fill(const uint32_t *ptr, const int32_t *t, const uint32_t *row, uint32_t n, const uint4 *meta,
+                           uint32_t *tix) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t v = row[p];
+  const uint4 m = meta[v];
+  if (m.y == 0) return;
+  const uint32_t rs = ptr[v], re = ptr[v + 1];
+  const int32_t t0 = (int32_t)m.z;
+  const int32_t bp = (int32_t)((uint32_t)(t[p] - t0) >> m.w);
+  const int32_t bq = p == rs ? -1 : (int32_t)((uint32_t)(t[p - 1] - t0) >> m.w);
+  for (int32_t i = bq + 1; i <= bp; i++) tix[m.x + i] = p;
+  if (p == re - 1)
+    for (uint32_t i = (uint32_t)bp + 1; i <= m.y; i++) tix[m.x + i] = re;
 }
 
 __global__ void k_inn_keys(const uint32_t *eids, uint32_t *eids_out, const uint4 *ep, uint32_t n, uint64_t *key) {
@@ -384,6 +419,22 @@ hipError_t validate_edges(const uint32_t *src, const uint32_t *dst, const int64_
   return hipSuccess;
 }
 
+// Time index of the rows (ptr, t); row[p] is the row of entry p.
+static hipError_t build_tix(const uint32_t *ptr, const int32_t *t, const uint32_t *row, uint32_t V, uint32_t n,
+                            uint4 *meta, uint32_t *tix, uint32_t *cnt, uint32_t *off, uint32_t *scan_tmp,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_tix_count, dim3(nblk(V, 256)), dim3(256), 0, s, ptr, t, V, meta, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive_u32(cnt, off, V, nullptr, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tix_offsets, dim3(nblk(V, 256)), dim3(256), 0, s, off, V, meta);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tix_fill, dim3(nblk(n, 256)), dim3(256), 0, s, ptr, t, row, n, (const uint4 *)meta, tix);
+  return hipGetLastError();
+}
+
 hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, uint32_t E, uint32_t Ev, uint32_t V,
                        int t_bits, bool time_sorted, uint64_t n_self, BuildBuffers &bb, hipStream_t s) {
   hipError_t e;
@@ -418,8 +469,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
                        (const uint4 *)bb.ep, 1, Ev, a.out_nbr, a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src,
                        a.out_h);
     CK(hipGetLastError());
-    hipLaunchKernelGGL(k_line_samples, dim3(nblk((Ev + 31) / 32, 256)), dim3(256), 0, s, a.out_t, Ev, a.out_ts);
-    CK(hipGetLastError());
+    CK(build_tix(a.out_ptr, a.out_t, a.out_src, V, Ev, a.out_tm, a.out_tix, a.tix_cnt, a.tix_off, bb.scan_tmp, s));
     // 3. CSC: stable sort of the anchor order by destination
     hipLaunchKernelGGL(k_gather_key, dim3(nblk(Ev, 256)), dim3(256), 0, s, a.dst, a.anc, bb.ka, bb.va, Ev);
     CK(hipGetLastError());

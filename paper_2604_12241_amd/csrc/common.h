@@ -17,7 +17,8 @@
 //  * CSR (out): rows by source, each row sorted by (time, id); per entry the
 //    destination, the time, the edge id and the time of the previous edge of
 //    the same (source, destination) pair (AMLM_INT_MIN if none), and
-//    vhash(destination) (the scatter-gather join's filter key)
+//    vhash(destination) (the scatter-gather join's filter key); a time index
+//    per row
 //  * CSC (in): rows by destination, sorted by (time, id); per entry the
 //    source, time, edge id and the time of the next edge of the same pair
 //    (AMLM_INT_MAX if none)
@@ -33,7 +34,10 @@ struct GraphView {
   const uint32_t *pos_out, *pos_in;  // edge id -> CSR / CSC position
   const uint32_t *out_ptr, *out_nbr, *out_eid, *out_src;  // out_src: row (source) of each entry
   const uint32_t *out_h;  // vhash(out_nbr[p])
-  const int32_t *out_ts;  // out_t[32 i]: the first time of each 128-byte line of out_t
+  // time index of the out-rows (see tix_lower_bound): per vertex (offset,
+  // buckets, first time, bucket shift), and the bucket starts
+  const uint4 *out_tm;
+  const uint32_t *out_tix;
   const int32_t *out_t, *out_prv;
   const uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst;  // in_dst: row (destination) of each entry
   const uint32_t *in_h;  // vhash(in_nbr[q])
@@ -119,27 +123,22 @@ __device__ __forceinline__ uint32_t gallop_lower_right(const int32_t *a, uint32_
   return e;
 }
 
-// The same two searches over a long sorted run, guided by the line samples
-// smp[i] = a[32 i]: a gallop over the samples (a small array that stays in
-// cache) finds the 32-entry line that holds the answer, and a binary search
-// inside that line finishes.  Only that line of `a` is read.
-__device__ __forceinline__ uint32_t lines_lower_left(const int32_t *a, const int32_t *smp, uint32_t b, uint32_t p,
-                                                     int32_t x) {
-  const uint32_t ilo = (b + 31) >> 5, ihi = p >> 5;  // samples inside [b, p]
-  if (ilo > ihi) return lower_bound_i32(a, b, p, x);
-  if (smp[ihi] < x) return lower_bound_i32(a, 32 * ihi + 1, p, x);
-  const uint32_t j = gallop_lower_left(smp, ilo, ihi, x);  // first sample >= x
-  if (j == ilo) return lower_bound_i32(a, b, 32 * ilo, x);
-  return lower_bound_i32(a, 32 * (j - 1) + 1, 32 * j, x);
-}
-__device__ __forceinline__ uint32_t lines_lower_right(const int32_t *a, const int32_t *smp, uint32_t p, uint32_t e,
-                                                      int32_t x) {
-  if (p >= e) return e;
-  const uint32_t ilo = (p + 31) >> 5, ihi = (e - 1) >> 5;  // samples inside [p, e)
-  if (ilo > ihi) return lower_bound_i32(a, p, e, x);
-  if (smp[ilo] >= x) return lower_bound_i32(a, p, 32 * ilo, x);
-  const uint32_t j = gallop_lower_right(smp, ilo + 1, ihi + 1, x);  // first sample >= x
-  return lower_bound_i32(a, 32 * (j - 1) + 1, min(32 * j, e), x);
+// Row time index.  A row longer than kTixMinRow entries is cut into nb
+// buckets of 2^w time units starting at its first time t0, with w the
+// smallest shift that leaves at most ceil(len / kTixPerBucket) buckets;
+// tix[off + i] is the first position whose time is >= t0 + (i << w), and
+// tix[off + nb] is the row end.  m = (off, nb, t0, w); nb = 0 for short rows.
+constexpr uint32_t kTixMinRow = 32, kTixPerBucket = 16;
+
+// first position in the row [rs, re) with time >= x
+__device__ __forceinline__ uint32_t tix_lower_bound(const int32_t *t, const uint32_t *tix, uint4 m, uint32_t rs,
+                                                    uint32_t re, int32_t x) {
+  if (m.y == 0) return lower_bound_i32(t, rs, re, x);
+  const int32_t t0 = (int32_t)m.z;
+  if (x <= t0) return rs;
+  const uint32_t i = (uint32_t)(x - t0) >> m.w;
+  if (i >= m.y) return re;
+  return lower_bound_i32(t, tix[m.x + i], tix[m.x + i + 1], x);
 }
 
 // First index in [b, e) with a[i] > key, for sorted 64-bit keys.

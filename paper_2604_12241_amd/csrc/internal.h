@@ -60,7 +60,10 @@ struct GraphArrays {
   int32_t *t;
   uint32_t *anc, *pos_out, *pos_in;
   uint32_t *out_ptr, *out_nbr, *out_eid, *out_src, *out_h;
-  int32_t *out_t, *out_prv, *out_ts;
+  int32_t *out_t, *out_prv;
+  uint4 *out_tm;        // [V]: out-row time index headers
+  uint32_t *out_tix;    // bucket starts, at most Ev / 16 + 2 V + 2 entries
+  uint32_t *tix_cnt, *tix_off;  // [V + 1] build scratch
   uint32_t *in_ptr, *in_nbr, *in_eid, *in_dst, *in_h;
   int32_t *in_t, *in_nxt;
   uint64_t *inn_key;

@@ -391,10 +391,10 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     uint32_t b = 0, n = 0;
     if (pair) {
       // s's out-window [lo, t) contains the s -> u edge: search outwards from it
-      const uint32_t apos = g.pos_out[g.in_eid[j]];
       const uint32_t rs = g.out_ptr[nb], re = g.out_ptr[nb + 1];
-      b = lines_lower_left(g.out_t, g.out_ts, rs, apos, L.i_lo[it]);
-      n = lines_lower_right(g.out_t, g.out_ts, apos + 1, re, L.i_t[it]) - b;
+      const uint4 m = g.out_tm[nb];
+      b = tix_lower_bound(g.out_t, g.out_tix, m, rs, re, L.i_lo[it]);
+      n = tix_lower_bound(g.out_t, g.out_tix, m, rs, re, L.i_t[it]) - b;
       if (mp.work) atomicAdd(&L.i_work[it], kBytesJoinEntry * n);
     }
     uint32_t np = __popcll(bs);
