@@ -109,7 +109,7 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&b.hist2, 4 * hw));
   size_t tw = std::max(scan_tmp_words(hw), scan_tmp_words(v1));
   A_TRY(dalloc(g, (void **)&b.scan_tmp, 4 * tw));
-  A_TRY(dalloc(g, (void **)&b.stats, 8 * 8));
+  A_TRY(dalloc(g, (void **)&b.stats, 8 * (8 + 5 * kValidateBlocks)));
   A_TRY(dalloc(g, (void **)&b.ep, 16 * e));
   A_TRY(dalloc(g, (void **)&g->err_dev, 64));
   A_TRY(dalloc(g, (void **)&g->ts_stage, 8 * e));

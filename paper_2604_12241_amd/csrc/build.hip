@@ -8,6 +8,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr uint32_t kTile = kThreads * kItems;  // 4096 elements per block
+constexpr int64_t kInt64Max = 0x7fffffffffffffffll;
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -16,23 +17,85 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
 }
 
 // stats[0] = min ts (biased to unsigned order), [1] = max ts (biased),
-// [2] = ids >= V, [3] = self-loops, [4] = i with ts[i] > ts[i+1]
-__global__ void k_validate(const uint32_t *src, const uint32_t *dst, const int64_t *ts, uint64_t E, uint32_t V,
-                           unsigned long long *stats) {
+// [2] = ids >= V, [3] = self-loops, [4] = i with ts[i] > ts[i+1].
+// Each block writes its five partial results; k_validate_final folds them.
+__global__ __launch_bounds__(256) void k_validate(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                                                  uint64_t E, uint32_t V, unsigned long long *part) {
   const unsigned long long bias = 0x8000000000000000ull;
   unsigned long long mn = ~0ull, mx = 0ull, bad = 0, loops = 0, unsorted = 0;
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < E; i += stride) {
-    unsigned long long b = (unsigned long long)ts[i] ^ bias;
-    mn = b < mn ? b : mn;
-    mx = b > mx ? b : mx;
-    uint32_t s = src[i], d = dst[i];
-    bad += (s >= V) | (d >= V);
-    loops += (s == d);
-    if (i + 1 < E) unsorted += ts[i] > ts[i + 1];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  constexpr int U = 4;  // independent loads in flight per thread
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < E; i0 += U * stride) {
+    int64_t tv[U], tn[U];
+    uint32_t sv[U], dv[U];
+#pragma unroll
+    for (int r = 0; r < U; r++) {
+      uint64_t i = i0 + r * stride;
+      bool in = i < E;
+      tv[r] = in ? ts[i] : 0;
+      tn[r] = in && i + 1 < E ? ts[i + 1] : kInt64Max;
+      sv[r] = in ? src[i] : 0u;
+      dv[r] = in ? dst[i] : 1u;
+    }
+#pragma unroll
+    for (int r = 0; r < U; r++) {
+      if (i0 + r * stride >= E) continue;
+      unsigned long long b = (unsigned long long)tv[r] ^ bias;
+      mn = b < mn ? b : mn;
+      mx = b > mx ? b : mx;
+      bad += (sv[r] >= V) | (dv[r] >= V);
+      loops += (sv[r] == dv[r]);
+      unsorted += tv[r] > tn[r];
+    }
   }
-  // wave reduction then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long a = __shfl_xor(mn, o, AMLM_WAVE);
+    mn = a < mn ? a : mn;
+    a = __shfl_xor(mx, o, AMLM_WAVE);
+    mx = a > mx ? a : mx;
+    bad += __shfl_xor(bad, o, AMLM_WAVE);
+    loops += __shfl_xor(loops, o, AMLM_WAVE);
+    unsorted += __shfl_xor(unsorted, o, AMLM_WAVE);
+  }
+  __shared__ unsigned long long ws[4][5];
+  const uint32_t w = threadIdx.x / AMLM_WAVE;
+  if (lane_id() == 0) {
+    ws[w][0] = mn;
+    ws[w][1] = mx;
+    ws[w][2] = bad;
+    ws[w][3] = loops;
+    ws[w][4] = unsorted;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t q = 1; q < blockDim.x / AMLM_WAVE; q++) {
+      mn = ws[q][0] < mn ? ws[q][0] : mn;
+      mx = ws[q][1] > mx ? ws[q][1] : mx;
+      bad += ws[q][2];
+      loops += ws[q][3];
+      unsorted += ws[q][4];
+    }
+    unsigned long long *o = part + 5ull * blockIdx.x;
+    o[0] = mn;
+    o[1] = mx;
+    o[2] = bad;
+    o[3] = loops;
+    o[4] = unsorted;
+  }
+}
+
+// Folds the per-block results; blocks that saw no element report the
+// neutral values, so the fold starts from them too.
+__global__ void k_validate_final(const unsigned long long *part, uint32_t nblocks, unsigned long long *stats) {
+  unsigned long long mn = ~0ull, mx = 0ull, bad = 0, loops = 0, unsorted = 0;
+  for (uint32_t b = lane_id(); b < nblocks; b += AMLM_WAVE) {
+    const unsigned long long *o = part + 5ull * b;
+    mn = o[0] < mn ? o[0] : mn;
+    mx = o[1] > mx ? o[1] : mx;
+    bad += o[2];
+    loops += o[3];
+    unsorted += o[4];
+  }
   for (int o = 32; o > 0; o >>= 1) {
     unsigned long long a = __shfl_xor(mn, o, AMLM_WAVE);
     mn = a < mn ? a : mn;
@@ -43,19 +106,11 @@ __global__ void k_validate(const uint32_t *src, const uint32_t *dst, const int64
     unsorted += __shfl_xor(unsorted, o, AMLM_WAVE);
   }
   if (lane_id() == 0) {
-    atomicMin(&stats[0], mn);
-    atomicMax(&stats[1], mx);
-    if (bad) atomicAdd(&stats[2], bad);
-    if (loops) atomicAdd(&stats[3], loops);
-    if (unsorted) atomicAdd(&stats[4], unsorted);
-  }
-}
-
-__global__ void k_init_stats(unsigned long long *stats) {
-  if (threadIdx.x == 0) {
-    stats[0] = ~0ull;
-    stats[1] = 0;
-    stats[2] = stats[3] = stats[4] = 0;
+    stats[0] = mn;
+    stats[1] = mx;
+    stats[2] = bad;
+    stats[3] = loops;
+    stats[4] = unsorted;
   }
 }
 
@@ -151,12 +206,21 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *kin, co
   const uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE, lane = lane_id();
   const uint32_t base = blockIdx.x * kTile;
   const uint32_t tn = min(kTile, n - base);
+  // the whole tile is loaded up front, so the loads overlap
+  uint32_t kr[kItems], vr[kItems];
+#pragma unroll
+  for (int j = 0; j < kItems; j++) {
+    uint32_t idx = j * kThreads + tid;
+    kr[j] = idx < tn ? kin[base + idx] : 0u;
+    vr[j] = idx < tn ? vin[base + idx] : 0u;
+  }
   // tile histogram, then its exclusive scan: the tile-local start of each bucket
   for (int q = 0; q < NW; q++) wc[q][tid] = 0;
   __syncthreads();
+#pragma unroll
   for (int j = 0; j < kItems; j++) {
     uint32_t idx = j * kThreads + tid;
-    if (idx < tn) atomicAdd(&wc[w][(kin[base + idx] >> shift) & 255u], 1u);
+    if (idx < tn) atomicAdd(&wc[w][(kr[j] >> shift) & 255u], 1u);
   }
   __syncthreads();
   uint32_t cnt = 0;
@@ -174,11 +238,12 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *kin, co
   gbase[tid] = offs[tid * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt = lanemask_lt();
+#pragma unroll
   for (int j = 0; j < kItems; j++) {
     uint32_t idx = j * kThreads + tid;
     bool valid = idx < tn;
-    uint32_t key = valid ? kin[base + idx] : 0u;
-    uint32_t val = valid ? vin[base + idx] : 0u;
+    uint32_t key = kr[j];
+    uint32_t val = vr[j];
     uint32_t d = (key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -398,11 +463,10 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 hipError_t validate_edges(const uint32_t *src, const uint32_t *dst, const int64_t *ts, uint64_t E, uint32_t V,
                           uint64_t *stats_dev, ValidateResult *res, hipStream_t s) {
   unsigned long long *st = (unsigned long long *)stats_dev;
-  hipLaunchKernelGGL(k_init_stats, dim3(1), dim3(64), 0, s, st);
-  if (E) {
-    uint32_t blocks = (uint32_t)std::min<uint64_t>((E + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, src, dst, ts, E, V, st);
-  }
+  const uint32_t blocks = E ? (uint32_t)std::min<uint64_t>((E + 1023) / 1024, kValidateBlocks) : 1u;
+  hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, src, dst, ts, E, V, st + 8);
+  hipLaunchKernelGGL(k_validate_final, dim3(1), dim3(AMLM_WAVE), 0, s, (const unsigned long long *)(st + 8), blocks,
+                     st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   unsigned long long h[5];

@@ -32,7 +32,7 @@ struct DeviceArena {
 struct BuildBuffers {
   uint32_t *ka = nullptr, *kb = nullptr, *va = nullptr, *vb = nullptr;
   uint32_t *hist = nullptr, *hist2 = nullptr, *scan_tmp = nullptr;
-  uint64_t *stats = nullptr;  // [8] validation results
+  uint64_t *stats = nullptr;  // [8] validation results, then 5 per validation block
   uint4 *ep = nullptr;        // per edge id: (source, destination, relative time, 0)
   size_t cap_n = 0, cap_hist = 0, cap_tmp = 0;
 };
@@ -69,6 +69,8 @@ struct GraphArrays {
   uint64_t *inn_key;
   uint32_t *inn_eid;
 };
+
+constexpr uint32_t kValidateBlocks = 2048;  // most blocks of the validation pass
 
 struct ValidateResult {
   int64_t tmin, tmax;
