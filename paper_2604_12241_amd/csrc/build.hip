@@ -117,13 +117,17 @@ __global__ void k_validate_final(const unsigned long long *part, uint32_t nblock
 // relative times, edge copies, and the first sort key:
 // key = self_loop << t_bits | t_rel, value = edge id
 __global__ void k_reltime(const int64_t *ts, int64_t tmin, const uint32_t *src, const uint32_t *dst, uint32_t E,
-                          int t_bits, int32_t *t, uint32_t *key, uint32_t *val, int with_time_key, uint4 *ep) {
+                          int t_bits, int32_t *t, uint32_t *key, uint32_t *val, int with_time_key, uint2 *ep_dt,
+                          uint2 *ep_st) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E) return;
   int32_t tr = (int32_t)(ts[i] - tmin);
   uint32_t s = src[i], d = dst[i];
   t[i] = tr;
-  ep[i] = make_uint4(s, d, (uint32_t)tr, 0u);  // one line per random read in the row fills
+  // (other endpoint, time) per edge id: one line per random read in the row
+  // fills, from an array small enough to stay in the last-level cache
+  ep_dt[i] = make_uint2(d, (uint32_t)tr);
+  ep_st[i] = make_uint2(s, (uint32_t)tr);
   uint32_t loop = s == d;
   key[i] = with_time_key ? ((loop << t_bits) | (uint32_t)tr) : loop;
   val[i] = i;
@@ -297,20 +301,20 @@ __global__ void k_row_ptr(const uint32_t *keys, uint32_t n, uint32_t V, uint32_t
   for (int64_t x = kprev + 1; x <= kp; x++) ptr[x] = p;
 }
 
-// Row fill after a sort: entry p takes edge eids[p]; `col` picks the other
-// endpoint from the packed edge (0: source, 1: destination).
-__global__ void k_fill_rows(const uint32_t *eids, uint32_t *eids_out, const uint4 *ep, int col, uint32_t n,
+// Row fill after a sort: entry p takes edge eids[p], whose other endpoint
+// and time come packed from ep.
+__global__ void k_fill_rows(const uint32_t *eids, uint32_t *eids_out, const uint2 *ep, uint32_t n,
                             uint32_t *nbr, int32_t *tt, uint32_t *pos, const uint32_t *rowkey, uint32_t *row,
                             uint32_t *hnbr) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   uint32_t e = eids[p];
-  uint4 x = ep[e];
-  uint32_t o = col ? x.y : x.x;
+  uint2 x = ep[e];
+  uint32_t o = x.x;
   eids_out[p] = e;
   nbr[p] = o;
   if (hnbr) hnbr[p] = vhash(o);
-  tt[p] = (int32_t)x.z;
+  tt[p] = (int32_t)x.y;
   pos[e] = p;
   row[p] = rowkey[p];
 }
@@ -355,13 +359,13 @@ __global__ void k_tix_fill(const uint32_t *ptr, const int32_t *t, const uint32_t
     for (uint32_t i = (uint32_t)bp + 1; i <= m.y; i++) tix[m.x + i] = re;
 }
 
-__global__ void k_inn_keys(const uint32_t *eids, uint32_t *eids_out, const uint4 *ep, uint32_t n, uint64_t *key) {
+__global__ void k_inn_keys(const uint32_t *eids, uint32_t *eids_out, const uint2 *ep, uint32_t n, uint64_t *key) {
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   uint32_t e = eids[q];
-  uint4 x = ep[e];
+  uint2 x = ep[e];
   eids_out[q] = e;
-  key[q] = nbr_key(x.x, (int32_t)x.z);
+  key[q] = nbr_key(x.x, (int32_t)x.y);
 }
 
 // same-pair time links from the (dst, src, time)-sorted index
@@ -508,11 +512,12 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     if (e != hipSuccess) return e;  \
   } while (0)
   const int vbits = bits_for(V ? V - 1 : 0);
+  uint2 *ep_dt = (uint2 *)bb.ep, *ep_st = (uint2 *)bb.ep + E;
   // 1. relative times and the anchor order (valid edges by (time, id))
   if (E) {
     int with_time = time_sorted ? 0 : 1;
     hipLaunchKernelGGL(k_reltime, dim3(nblk(E, 256)), dim3(256), 0, s, ts, tmin, a.src, a.dst, E, t_bits, a.t,
-                       bb.ka, bb.va, with_time, bb.ep);
+                       bb.ka, bb.va, with_time, ep_dt, ep_st);
     CK(hipGetLastError());
     int sort_bits = time_sorted ? (n_self ? 1 : 0) : t_bits + 1;
     uint32_t *ks, *vs;
@@ -530,7 +535,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     hipLaunchKernelGGL(k_row_ptr, dim3(nblk((uint64_t)Ev + 1, 256)), dim3(256), 0, s, ks, Ev, V, a.out_ptr);
     CK(hipGetLastError());
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.out_eid,
-                       (const uint4 *)bb.ep, 1, Ev, a.out_nbr, a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src,
+                       (const uint2 *)ep_dt, Ev, a.out_nbr, a.out_t, a.pos_out, (const uint32_t *)ks, a.out_src,
                        a.out_h);
     CK(hipGetLastError());
     CK(build_tix(a.out_ptr, a.out_t, a.out_src, V, Ev, a.out_tm, a.out_tix, a.tix_cnt, a.tix_off, bb.scan_tmp, s));
@@ -541,7 +546,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     hipLaunchKernelGGL(k_row_ptr, dim3(nblk((uint64_t)Ev + 1, 256)), dim3(256), 0, s, ks, Ev, V, a.in_ptr);
     CK(hipGetLastError());
     hipLaunchKernelGGL(k_fill_rows, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.in_eid,
-                       (const uint4 *)bb.ep, 0, Ev, a.in_nbr, a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst,
+                       (const uint2 *)ep_st, Ev, a.in_nbr, a.in_t, a.pos_in, (const uint32_t *)ks, a.in_dst,
                        a.in_h);
     CK(hipGetLastError());
     // 4. CSC-N: stable sort of the CSR order (source, time, id) by destination
@@ -550,7 +555,7 @@ hipError_t build_graph(const GraphArrays &a, const int64_t *ts, int64_t tmin, ui
     CK(hipMemcpyAsync(bb.va, a.out_eid, sizeof(uint32_t) * Ev, hipMemcpyDeviceToDevice, s));
     CK(radix_sort_pairs(bb.ka, bb.va, bb.kb, bb.vb, Ev, vbits, bb.hist, bb.hist2, bb.scan_tmp, s, &ks, &vs));
     hipLaunchKernelGGL(k_inn_keys, dim3(nblk(Ev, 256)), dim3(256), 0, s, (const uint32_t *)vs, a.inn_eid,
-                       (const uint4 *)bb.ep, Ev, a.inn_key);
+                       (const uint2 *)ep_st, Ev, a.inn_key);
     CK(hipGetLastError());
     // 5. same-pair links (ks still holds the destination of every CSC-N entry)
     hipLaunchKernelGGL(k_links, dim3(nblk(Ev, 256)), dim3(256), 0, s, ks, a.inn_key, a.inn_eid, Ev, a.pos_in,

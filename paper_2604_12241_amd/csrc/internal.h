@@ -33,7 +33,7 @@ struct BuildBuffers {
   uint32_t *ka = nullptr, *kb = nullptr, *va = nullptr, *vb = nullptr;
   uint32_t *hist = nullptr, *hist2 = nullptr, *scan_tmp = nullptr;
   uint64_t *stats = nullptr;  // [8] validation results, then 5 per validation block
-  uint4 *ep = nullptr;        // per edge id: (source, destination, relative time, 0)
+  uint4 *ep = nullptr;        // per edge id: (destination, time) pairs, then (source, time) pairs
   size_t cap_n = 0, cap_hist = 0, cap_tmp = 0;
 };
 
