@@ -170,7 +170,8 @@ struct SgLds {
   uint32_t i_work[kSgChunkMax], i_wlen[kSgChunkMax];
   uint32_t seg_off[AMLM_WAVE];  // exclusive offsets of the segment's sender windows
   int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax];
-  uint32_t i_q[kSgChunkMax];    // CSC position of each anchor (its v-window is in sg_win)
+  uint32_t i_q[kSgChunkMax];    // CSC position of each anchor
+  uint32_t i_r0[kSgChunkMax], i_r1[kSgChunkMax];  // its v-window [r0, r1) in v's in-row
   uint32_t i_k[kSgChunkMax];    // threshold k of each anchor
   uint32_t i_join[kSgChunkMax]; // 1 if the anchor's senders need the join
   uint32_t i_gsd[kSgChunkMax];  // 1 if u has k scatter destinations after tau
@@ -325,8 +326,7 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, 
 }
 
 // Anchors [s0, s1) of the chunk, all into vertex v.
-__device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t v,
-                           const uint4 *sg_win) {
+__device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t v) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
@@ -335,11 +335,13 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   const bool need_join = mp.col_sg >= 0 && k >= 2 &&
                          __ballot(lane >= s0 && lane < s1 && L.i_join[min(lane, kSgChunkMax - 1)] != 0) != 0;
   int shift = 0;
-  uint32_t vrs = rfl(g.in_ptr[v]), vre = rfl(g.in_ptr[v + 1]);
+  uint32_t vrs = 0, vre = 0;
   if (need_join) {
+    vrs = g.in_ptr[v];  // v's row, for the candidate checks
+    vre = g.in_ptr[v + 1];
     // gather side of the whole segment: v's in-neighbours in [lo_first, t_last]
     // (the anchors are time-sorted inside the segment)
-    uint32_t r0 = rfl(sg_win[L.i_q[s0]].z), r1 = rfl(sg_win[L.i_q[s1 - 1]].w);
+    uint32_t r0 = rfl(L.i_r0[s0]), r1 = rfl(L.i_r1[s1 - 1]);
     uint32_t nin = r1 - r0;
     int lg = 9;
     while (lg < kBloomLog2Max && (1u << lg) < nin * kBloomBitsPerEntry) lg++;
@@ -448,6 +450,8 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       L.i_gsd[lane] = (fl & kFlagGsDest) ? 1u : 0u;
       L.i_p0[lane] = pw.x;
       L.i_wlen[lane] = pw.y - pw.x;
+      L.i_r0[lane] = pw.z;
+      L.i_r1[lane] = pw.w;
       L.i_ns[lane] = 0;
       L.i_sg[lane] = 0;
       L.i_work[lane] = kBytesAnchorSg;
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       heads &= heads - 1;
       uint32_t s1 = heads ? (uint32_t)(__ffsll((long long)heads) - 1) : nr;
       uint32_t vs = rfl((uint32_t)__shfl(v, s0, AMLM_WAVE));
-      sg_segment(mp, L, s0, s1, vs, sg_win);
+      sg_segment(mp, L, s0, s1, vs);
     }
     // gather-scatter and the outputs, one lane per anchor
     uint32_t sg = 0, gs = 0, work = 0;
