@@ -143,6 +143,15 @@ amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
 amlm_status amlm_set_timing(amlm_graph *g, int enable);
 amlm_status amlm_stage_times(amlm_graph *g, float *ms);
 
+/* Pin the launch shape of later amlm_mine calls on g (0 keeps the default
+ * of a field): block = list items per scatter-gather work unit (clamped to
+ * [4, 8]); sg_blocks, cyc_blocks = persistent grid sizes; split_bytes =
+ * learned schedule only: an anchor whose predicted scatter-gather bytes
+ * exceed this is cut into slices of about this size, each its own work unit
+ * (default 65536).  Never changes a count.  AMLM_E_INVALID for a NULL g. */
+amlm_status amlm_tune_set(amlm_graph *g, uint32_t block, uint32_t sg_blocks, uint32_t cyc_blocks,
+                          uint32_t split_bytes);
+
 /* Synchronise hip_stream and report device-side errors of earlier mining
  * calls on g (AMLM_E_RANGE for a count overflow). Clears the error word. */
 amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream);

@@ -30,6 +30,7 @@ EXPORTS = [
     "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
     "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy", "amlm_mlp_predict",
+    "amlm_tune_set",
 ]
 
 
@@ -84,6 +85,7 @@ def lib():
             "amlm_server_destroy": (None, [p]),
             "amlm_last_error": (ctypes.c_char_p, []),
             "amlm_set_timing": (st, [p, ctypes.c_int]),
+            "amlm_tune_set": (st, [p, u32, u32, u32, u32]),
             "amlm_costmodel_get": (st, [p, p, p]),
             "amlm_mlp_forward": (st, [p, p, u32, p]),
             "amlm_mlp_predict": (st, [p, p, u32, p]),
@@ -210,6 +212,11 @@ STAGES = ["build", "anchor", "lists", "sg", "cyc", "model", "unused6", "unused7"
 
 def amlm_set_timing(g: Graph, enable: bool = True):
     _check(lib().amlm_set_timing(g.handle, 1 if enable else 0))
+
+
+def amlm_tune_set(g: Graph, block=0, sg_blocks=0, cyc_blocks=0, split_bytes=0):
+    """Pin the launch shape of later mining calls on g (0 = default)."""
+    _check(lib().amlm_tune_set(g.handle, block, sg_blocks, cyc_blocks, split_bytes))
 
 
 def amlm_stage_times(g: Graph) -> dict:

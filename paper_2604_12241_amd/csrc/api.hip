@@ -136,8 +136,12 @@ amlm_status alloc_mine_scratch(amlm_graph *g) {
   A_TRY(dalloc(g, (void **)&ms.bcnt_cy, 4 * (size_t)nb));
   A_TRY(dalloc(g, (void **)&ms.boff_sg, 4 * (size_t)nb));
   A_TRY(dalloc(g, (void **)&ms.boff_cy, 4 * (size_t)nb));
-  A_TRY(dalloc(g, (void **)&ms.scan_tmp, 4 * scan_tmp_words(nb)));
+  A_TRY(dalloc(g, (void **)&ms.scan_tmp, 4 * std::max(scan_tmp_words(nb), scan_tmp_words(ev))));
   A_TRY(dalloc(g, (void **)&ms.ctr, 4 * kCtrWords));
+  A_TRY(dalloc(g, (void **)&ms.nsub, 4 * ev));
+  A_TRY(dalloc(g, (void **)&ms.ucnt, 4 * ev));
+  A_TRY(dalloc(g, (void **)&ms.uoff, 4 * ev));
+  A_TRY(dalloc(g, (void **)&ms.units, 8 * max_units(ev, kMinBlock)));
   ms.cap_ev = ev;
   ms.cap_e = std::max<uint64_t>(g->E, 1);
   return AMLM_OK;
@@ -353,6 +357,7 @@ MineLaunch default_launch(const amlm_graph *g) {
   if (g->tune.sg_chunk) cfg.sg_chunk = g->tune.sg_chunk;
   if (g->tune.sg_blocks) cfg.sg_blocks = g->tune.sg_blocks;
   if (g->tune.cyc_blocks) cfg.cyc_blocks = g->tune.cyc_blocks;
+  if (g->tune.split_bytes) cfg.split_bytes = g->tune.split_bytes;
   return cfg;
 }
 
@@ -385,7 +390,6 @@ amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_de
     }
     cfg.learned = true;
     cfg.delta_hours = (float)p->delta / 3600.f;
-    cfg.bb = &g->bb;
   }
   HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
   return AMLM_OK;
@@ -431,6 +435,19 @@ extern "C" amlm_status amlm_set_timing(amlm_graph *g, int enable) {
     for (hipEvent_t &e : g->timer.ev) HIP_TRY(hipEventCreate(&e));
   g->timer.on = enable != 0;
   for (bool &u : g->timer.used) u = false;
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_tune_set(amlm_graph *g, uint32_t block, uint32_t sg_blocks, uint32_t cyc_blocks,
+                                     uint32_t split_bytes) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  g->tune.sg_chunk = block;
+  g->tune.sg_blocks = sg_blocks;
+  g->tune.cyc_blocks = cyc_blocks;
+  g->tune.split_bytes = split_bytes;
   return AMLM_OK;
 }
 

@@ -16,7 +16,7 @@ struct DeviceInfo {
 DeviceInfo &device_info();
 
 struct TuneParams {
-  uint32_t sg_chunk = 0, sg_blocks = 0, cyc_blocks = 0;  // 0 = default
+  uint32_t sg_chunk = 0, sg_blocks = 0, cyc_blocks = 0, split_bytes = 0;  // 0 = default
 };
 
 // Batched store state (batch.hip): sub-graph layout, device parameter

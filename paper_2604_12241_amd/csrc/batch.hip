@@ -196,7 +196,7 @@ static std::string batch_signature(const amlm_graph *g, uint32_t patterns, uint3
                                    const MineLaunch &cfg) {
   std::ostringstream o;
   o << patterns << "/" << schedule << "/" << Lmax << "/" << cfg.sg_blocks << "/" << cfg.sg_chunk << "/"
-    << cfg.cyc_blocks << "/" << cfg.learned_chunk << "/" << g->E << "/" << g->ms.cap_ev;
+    << cfg.cyc_blocks << "/" << cfg.learned_chunk << "/" << cfg.split_bytes << "/" << g->E << "/" << g->ms.cap_ev;
   return o.str();
 }
 
@@ -257,7 +257,6 @@ extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uin
   if (pm.schedule == AMLM_SCHED_LEARNED) {
     cfg.learned = true;
     cfg.delta_hours = (float)pm.delta / 3600.f;
-    cfg.bb = &g->bb;
   }
   std::string sig = batch_signature(g, pm.patterns, pm.schedule, Lmax, cfg);
   if (!B.exec || sig != B.sig) {
@@ -384,7 +383,7 @@ extern "C" amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint3
     g->tune = best;
   } else {
     DeviceInfo &di = device_info();
-    const uint32_t chunks[] = {16, 32, 64};
+    const uint32_t chunks[] = {kMinBlock, 6, kSgChunkMax};
     const uint32_t sg_full = (uint32_t)(di.num_cu * di.sg_occ), cyc_full = (uint32_t)(di.num_cu * di.cyc_occ);
     const uint32_t grids[][2] = {{sg_full, cyc_full}, {sg_full / 2, cyc_full / 2}};
     hipEvent_t e0, e1;

@@ -48,6 +48,8 @@ constexpr uint32_t kFlagThreads = 256, kFlagItems = 16, kFlagTile = kFlagThreads
 constexpr uint32_t kCtrSgWork = 0;
 constexpr uint32_t kCtrCycWork = 1;
 constexpr uint32_t kCtrNSg = 32, kCtrNCy = 33;
+constexpr uint32_t kCtrSplitW = 34;   // 64-bit: sender-window entries of the splittable anchors
+constexpr uint32_t kCtrNUnits = 36;   // scatter-gather work units
 constexpr uint32_t kCtrWords = 64;
 
 // Per-sub-graph parameters of a batched store (see batch.hip).
@@ -82,18 +84,31 @@ struct MineScratch {
   uint32_t *bcnt_sg = nullptr, *bcnt_cy = nullptr, *boff_sg = nullptr, *boff_cy = nullptr;
   uint32_t *scan_tmp = nullptr;
   uint32_t *ctr = nullptr;
+  // scatter-gather work units (see k_unit_fill): per list item its slice
+  // count and unit count, their offsets, and the units
+  uint32_t *nsub = nullptr, *ucnt = nullptr, *uoff = nullptr;
+  uint2 *units = nullptr;
   uint64_t cap_ev = 0, cap_e = 0;
 };
+
+// Units: light blocks of at least kMinBlock items (smaller requests are
+// raised), heavy slices bounded by the split rule; max_units() bounds both.
+constexpr uint32_t kMinBlock = 4;
+constexpr uint32_t kSplitMax = 64;   // an anchor is cut into at most this many slices
+inline uint64_t max_units(uint64_t ev, uint32_t block) { return ev / block + ev / 16 + ev / 8 + 64; }
+#ifndef AMLM_SPLIT_BYTES
+#define AMLM_SPLIT_BYTES 65536
+#endif
+constexpr uint32_t kSplitBytes = AMLM_SPLIT_BYTES;  // learned schedule: predicted bytes per slice
 
 struct MineLaunch {
   uint32_t sg_blocks, sg_chunk, cyc_blocks;
   bool learned = false;         // schedule scatter-gather chunks by the cost model
   uint32_t learned_chunk = kSgChunkMax;  // anchors per chunk in the learned schedule
+  uint32_t split_bytes = kSplitBytes;    // learned schedule: predicted bytes per slice
   float delta_hours = 24.f;
-  BuildBuffers *bb = nullptr;   // sort buffers reused by the learned schedule
 };
-constexpr uint32_t kChunkKeyInvalid = 0x1ffffu;
-constexpr int kChunkKeyBits = 17;
+
 
 // Optional HIP-event timing of the stages (recorded on the mining stream).
 enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kNumStages = 8 };

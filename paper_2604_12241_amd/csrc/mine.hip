@@ -412,31 +412,157 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
   }
 }
 
-__global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
-                                                 uint32_t *ctr, uint32_t chunk, const uint4 *sg_win,
-                                                 const uint32_t *chunk_tab, const uint8_t *flags_sg) {
+// ------------------------------------------------------------------ work units
+// A unit of k_sg work is a block of up to `block` consecutive list items, or
+// one slice of the sender window of a heavy anchor.  An anchor whose join
+// runs over a long sender window is cut into slices, each a unit of its own,
+// so that no unit dominates the kernel (on the 32M-edge graph the heaviest
+// 8-anchor chunk held 3.8 MB of join reads, milliseconds of one wave).
+// Slices add their partial SG_k and sender counts with atomics; k_split_gs
+// turns an anchor's accumulated sender count into GS_k afterwards.
+// unit = (first item, count) for a block; (item, kUnitHeavy | slices << 16 | slice)
+constexpr uint32_t kUnitHeavy = 0x80000000u;
+
+__device__ __forceinline__ uint32_t join_window(const MineParams &mp, const uint8_t *flags_sg, const uint4 *sg_win,
+                                                uint32_t q) {
+  // sender-window length of a scatter-gather anchor that runs a join, else 0
+  if (mp.col_sg < 0 || (flags_sg[q] & kFlagSgNoJoin) || k_of(mp, mp.g.in_dst[q]) < 2) return 0;
+  const uint4 pw = sg_win[q];
+  return pw.y - pw.x;
+}
+
+// Size of item i for the split rule: the predicted scatter-gather bytes when
+// the cost model runs (pred != NULL), else the sender-window length; 0 for
+// items without a join.
+__device__ __forceinline__ unsigned long long split_size(const MineParams &mp, const uint32_t *items,
+                                                         const uint8_t *flags_sg, const uint4 *sg_win,
+                                                         const float *pred, uint32_t i, uint32_t *w) {
+  *w = join_window(mp, flags_sg, sg_win, items[i]);
+  if (*w < 2) return 0;
+  if (!pred) return *w;
+  return (unsigned long long)fminf(expm1f(fminf(fmaxf(pred[i], 0.f), 40.f)), 2147483648.f);
+}
+
+__global__ __launch_bounds__(256) void k_split_weight(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
+                                                      const uint8_t *flags_sg, const uint4 *sg_win,
+                                                      const float *pred, uint32_t min_size, unsigned long long *W) {
+  __shared__ unsigned long long ws[256 / AMLM_WAVE];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long w = 0;
+  if (i < *n_items_p) {
+    uint32_t x;
+    const unsigned long long z = split_size(mp, items, flags_sg, sg_win, pred, i, &x);
+    if (z > min_size) w = z;
+  }
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, AMLM_WAVE);
+  if (lane_id() == 0) ws[threadIdx.x / AMLM_WAVE] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < 256 / AMLM_WAVE; q++) t += ws[q];
+    if (t) atomicAdd(W, t);
+  }
+}
+
+// Slices of item i (0 for a light item): its size over the slice size, which
+// is at least min_size and at least 16 W / Ev (W: the summed size of the
+// items above min_size), so the slices of all anchors stay within Ev / 8.
+__device__ __forceinline__ uint32_t item_slices(const MineParams &mp, const uint32_t *items, const uint8_t *flags_sg,
+                                                const uint4 *sg_win, const float *pred, uint32_t min_size,
+                                                unsigned long long W, uint32_t i) {
+  uint32_t w;
+  const unsigned long long z = split_size(mp, items, flags_sg, sg_win, pred, i, &w);
+  const unsigned long long ev = mp.g.Ev ? mp.g.Ev : 1;
+  const unsigned long long se = max((unsigned long long)min_size, (16ull * W + ev - 1) / ev);
+  if (z <= se) return 0;
+  return (uint32_t)min((unsigned long long)min(kSplitMax, w), (z + se - 1) / se);
+}
+
+__global__ void k_unit_count(MineParams mp, const uint32_t *items, const uint32_t *n_items_p, const uint8_t *flags_sg,
+                             const uint4 *sg_win, const float *pred, uint32_t min_size,
+                             const unsigned long long *W_p, uint32_t block, uint32_t n_max, uint32_t *nsub,
+                             uint32_t *cnt) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_max) return;
+  const uint32_t n = *n_items_p;
+  if (i >= n) {
+    cnt[i] = 0;
+    return;
+  }
+  const unsigned long long W = *W_p;
+  uint32_t ns = item_slices(mp, items, flags_sg, sg_win, pred, min_size, W, i);
+  if (ns == 1) ns = 0;
+  nsub[i] = ns;
+  bool start = false;
+  if (!ns) start = i % block == 0 || (i > 0 && item_slices(mp, items, flags_sg, sg_win, pred, min_size, W, i - 1) > 1);
+  cnt[i] = ns ? ns : (start ? 1u : 0u);
+}
+
+__global__ void k_unit_fill(MineParams mp, const uint32_t *items, const uint32_t *n_items_p, const uint32_t *nsub,
+                            const uint32_t *cnt, const uint32_t *off, uint32_t block, uint2 *units) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = *n_items_p;
+  if (i >= n || cnt[i] == 0) return;
+  const uint32_t ns = nsub[i], o = off[i];
+  if (ns) {
+    for (uint32_t s = 0; s < ns; s++) units[o + s] = make_uint2(i, kUnitHeavy | (ns << 16) | s);
+    // the slices accumulate into the outputs
+    const uint32_t eid = mp.g.in_eid[items[i]];
+    if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = 0;
+    if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = 0;
+  } else {
+    uint32_t len = 1;
+    while (len < block && i + len < n && (i + len) % block != 0 && nsub[i + len] == 0) len++;
+    units[o] = make_uint2(i, len);
+  }
+}
+
+// GS_k of the split anchors from their accumulated sender counts.
+__global__ void k_split_gs(MineParams mp, const uint32_t *items, const uint32_t *n_items_p, const uint32_t *nsub,
+                           const uint8_t *flags_sg) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_items_p || nsub[i] == 0) return;
+  const uint32_t q = items[i];
+  uint32_t *c = mp.counts + (uint64_t)mp.col_gs * mp.stride + mp.g.in_eid[q];
+  const uint32_t ns = *c;
+  const bool d_ok = (flags_sg[q] & kFlagGsDest) != 0;  // split anchors have k >= 2
+  *c = ns >= k_of(mp, mp.g.in_dst[q]) && d_ok ? ns : 0u;
+}
+
+// Units: with `units` NULL (static schedule) unit c is the block of items
+// [c * block, (c + 1) * block) and n_count_p points at the item count; else
+// units[c] and n_count_p points at the unit count.
+__global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t *items, const uint2 *units,
+                                                 const uint32_t *n_count_p, uint32_t block, uint32_t *ctr,
+                                                 const uint4 *sg_win, const uint8_t *flags_sg) {
   __shared__ SgLds L;
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
-  const uint32_t n_items = *n_items_p;
-  chunk = min(chunk, kSgChunkMax);
-  const uint32_t n_chunks = (n_items + chunk - 1) / chunk;
+  const uint32_t n_count = *n_count_p;
+  const uint32_t n_units = units ? n_count : (n_count + block - 1) / block;
   for (;;) {
-    // static: consecutive chunks of the CSC-ordered list; learned: the chunk
-    // table orders chunks by predicted cost, heaviest first
     uint32_t c = 0;
     if (lane == 0) c = atomicAdd(ctr, 1u);
     c = rfl((uint32_t)__shfl(c, 0, AMLM_WAVE));
-    if (c >= n_chunks) break;
-    const uint32_t base = (chunk_tab ? chunk_tab[c] : c) * chunk;
-    const uint32_t nr = min(chunk, n_items - base);
+    if (c >= n_units) break;
+    const uint2 un = units ? units[c] : make_uint2(c * block, min(block, n_count - c * block));
+    const bool heavy = (un.y & kUnitHeavy) != 0;
+    const uint32_t nr = heavy ? 1u : un.y;
     uint32_t v = 0xffffffffu;
     int64_t dl = 1;
     if (lane < nr) {
-      uint32_t q = items[base + lane];
+      uint32_t q = items[un.x + lane];
       uint32_t eid = g.in_eid[q];
       int32_t t = g.in_t[q];
       uint4 pw = sg_win[q];
+      uint32_t first_slice = 1;
+      if (heavy) {  // slice s of ns: an even share of the sender window
+        const uint32_t ns = (un.y >> 16) & 0x7fffu, sl = un.y & 0xffffu, w = pw.y - pw.x;
+        const uint32_t a = (uint32_t)((uint64_t)w * sl / ns), b = (uint32_t)((uint64_t)w * (sl + 1) / ns);
+        pw.y = pw.x + b;
+        pw.x += a;
+        first_slice = sl == 0;
+      }
       v = g.in_dst[q];
       L.i_q[lane] = q;
       L.i_eid[lane] = eid;
@@ -454,7 +580,7 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       L.i_r1[lane] = pw.w;
       L.i_ns[lane] = 0;
       L.i_sg[lane] = 0;
-      L.i_work[lane] = kBytesAnchorSg;
+      L.i_work[lane] = first_slice ? kBytesAnchorSg : 0u;
     }
     // segments: runs of anchors into the same v inside one time bucket of
     // width delta / 4, so that a segment's gather window stays short
@@ -481,8 +607,15 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
     }
     if (lane < nr) {
       uint32_t eid = L.i_eid[lane];
-      if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = sg;
-      if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = gs;
+      if (heavy) {
+        // a slice: partial SG_k, and its senders towards the GS_k of k_split_gs
+        if (mp.col_sg >= 0 && sg) credit(mp.counts + (uint64_t)mp.col_sg * mp.stride + eid, sg, mp.err);
+        const uint32_t ns = L.i_ns[lane];
+        if (mp.col_gs >= 0 && ns) credit(mp.counts + (uint64_t)mp.col_gs * mp.stride + eid, ns, mp.err);
+      } else {
+        if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = sg;
+        if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = gs;
+      }
       if (mp.work) atomicAdd(&mp.work[eid], work);
     }
   }
@@ -661,23 +794,6 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
 // consecutive list items (sum of expm1 of the predicted log-work), quantised
 // so that an ascending sort puts the heaviest chunk first; chunks past the
 // end of the list sort last.
-__global__ void k_chunk_keys(const float *pred, const uint32_t *n_items_p, uint32_t chunk, uint32_t max_chunks,
-                             uint32_t *keys, uint32_t *vals) {
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= max_chunks) return;
-  const uint32_t n = *n_items_p;
-  uint32_t key = kChunkKeyInvalid;
-  if (c * chunk < n) {
-    float cost = 0.f;
-    uint32_t e = min(n, (c + 1) * chunk);
-    for (uint32_t i = c * chunk; i < e; i++) cost += expm1f(fminf(fmaxf(pred[i], 0.f), 40.f));
-    float q = log2f(cost + 1.f) * 1024.f;
-    key = 0xffffu - (uint32_t)fminf(q, 65535.f);
-  }
-  keys[c] = key;
-  vals[c] = c;
-}
-
 // Order-preserving compaction of the indices i with flags[i] != 0 (block
 // counts, exclusive scan, scatter).
 __global__ void k_flag_count(const uint8_t *flags, uint32_t n, uint32_t *cnt) {
@@ -766,29 +882,51 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
     CK(hipGetLastError());
   }
   CK(tm->end(kStLists, s));
-  const uint32_t *chunk_tab = nullptr;
-  uint32_t chunk = cfg.sg_chunk;
-  if (want_sg && learned) {
-    // cost model: predicted work per list item, then chunks heavy-first
-    CK(tm->begin(kStModel, s));
-    chunk = cfg.learned_chunk;
-    CK(mlp_infer(global_model(), ms.feat, ms.list_sg, 0, n_sg, cfg.delta_hours, (float)mp.L, ms.pred, s));
-    uint32_t max_chunks = (Ev + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_chunk_keys, dim3((max_chunks + 255) / 256), dim3(256), 0, s, ms.pred, n_sg, chunk,
-                       max_chunks, cfg.bb->ka, cfg.bb->va);
-    CK(hipGetLastError());
-    uint32_t *ks, *vs;
-    CK(radix_sort_pairs(cfg.bb->ka, cfg.bb->va, cfg.bb->kb, cfg.bb->vb, max_chunks, kChunkKeyBits, cfg.bb->hist,
-                        cfg.bb->hist2, cfg.bb->scan_tmp, s, &ks, &vs));
-    chunk_tab = vs;
-    CK(tm->end(kStModel, s));
-  }
   if (want_sg) {
+    // learned schedule: the cost model predicts each item's work, which sets
+    // how finely the heavy anchors are sliced
+    const float *pred = nullptr;
+    if (learned) {
+      CK(tm->begin(kStModel, s));
+      CK(mlp_infer(global_model(), ms.feat, ms.list_sg, 0, n_sg, cfg.delta_hours, (float)mp.L, ms.pred, s));
+      pred = ms.pred;
+      CK(tm->end(kStModel, s));
+    }
     CK(tm->begin(kStSg, s));
-    hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, n_sg,
-                       ms.ctr + kCtrSgWork, chunk, (const uint4 *)ms.sg_win, chunk_tab,
-                       (const uint8_t *)flags_sg);
-    CK(hipGetLastError());
+    const uint32_t block = std::min(std::max(learned ? cfg.learned_chunk : cfg.sg_chunk, kMinBlock), kSgChunkMax);
+    const uint32_t nb = (Ev + 255) / 256;
+    if (learned) {
+      // work units: blocks of light items and slices of the anchors whose
+      // predicted work exceeds the split size, in list order
+      uint32_t *n_units = ms.ctr + kCtrNUnits;
+      unsigned long long *W = (unsigned long long *)(ms.ctr + kCtrSplitW);
+      hipLaunchKernelGGL(k_split_weight, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, flags_sg,
+                         (const uint4 *)ms.sg_win, pred, cfg.split_bytes, W);
+      CK(hipGetLastError());
+      hipLaunchKernelGGL(k_unit_count, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, flags_sg,
+                         (const uint4 *)ms.sg_win, pred, cfg.split_bytes, (const unsigned long long *)W, block, Ev,
+                         ms.nsub, ms.ucnt);
+      CK(hipGetLastError());
+      CK(scan_exclusive_u32(ms.ucnt, ms.uoff, Ev, n_units, ms.scan_tmp, s));
+      hipLaunchKernelGGL(k_unit_fill, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, ms.nsub, ms.ucnt, ms.uoff,
+                         block, ms.units);
+      CK(hipGetLastError());
+      hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, (const uint2 *)ms.units,
+                         (const uint32_t *)n_units, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
+                         (const uint8_t *)flags_sg);
+      CK(hipGetLastError());
+      if (mp.col_gs >= 0) {
+        hipLaunchKernelGGL(k_split_gs, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, ms.nsub,
+                           (const uint8_t *)flags_sg);
+        CK(hipGetLastError());
+      }
+    } else {
+      // static schedule: fixed blocks of the list
+      hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, (const uint2 *)nullptr,
+                         (const uint32_t *)n_sg, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
+                         (const uint8_t *)flags_sg);
+      CK(hipGetLastError());
+    }
     CK(tm->end(kStSg, s));
   }
   if (want_cyc) {

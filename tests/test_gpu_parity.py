@@ -135,6 +135,61 @@ def test_hub_heavy_cycles_spill():
     assert_same(gpu_mine(g, 400, 5, 3), oracle_mine(g, 400, 5, 3), "dense spill")
 
 
+def _heavy_sender_graph(seed, n_senders=300, n_anchors=6, n_noise=4000):
+    """Anchors u -> v whose sender windows hold hundreds of senders, each with
+    its own out-edges to shared intermediates that reach v: the scatter-gather
+    stage cuts these anchors into slices."""
+    rng = np.random.default_rng(seed)
+    u, v = 0, 1
+    senders = np.arange(2, 2 + n_senders)
+    mids = np.arange(2 + n_senders, 2 + n_senders + 24)
+    nv = int(mids[-1]) + 40
+    src, dst, ts = [], [], []
+    def add(a, b, t):
+        src.append(a); dst.append(b); ts.append(t)
+    for i, s_ in enumerate(senders):
+        for m in rng.choice(mids, size=int(rng.integers(0, 4)), replace=False):
+            add(s_, m, 100 + int(rng.integers(0, 400)))
+        add(s_, u, 600 + int(rng.integers(0, 300)))
+        if i % 7 == 0:
+            add(s_, u, 950 + int(rng.integers(0, 40)))  # repeated sender edges
+    for m in mids:
+        for _ in range(int(rng.integers(1, 4))):
+            add(int(m), v, 500 + int(rng.integers(0, 700)))
+    for j in range(n_anchors):
+        add(u, v, 1000 + 20 * j)
+        add(u, int(rng.choice(mids)), 1000 + 20 * j + 5)  # scatter side of u
+    for _ in range(n_noise):
+        a, b = rng.integers(0, nv, 2)
+        if a != b:
+            add(int(a), int(b), int(rng.integers(0, 1400)))
+    order = np.argsort(np.array(ts), kind="stable")
+    src = np.array(src, np.uint32)[order]
+    dst = np.array(dst, np.uint32)[order]
+    ts = W.T0 + np.array(ts, np.int64)[order]
+    return W.EdgeList(src, dst, ts, np.zeros(len(src), np.float32), nv)
+
+
+@pytest.mark.parametrize("seed,k", [(1, 2), (2, 3), (3, 2)])
+def test_split_heavy_sender_windows(seed, k):
+    """The learned schedule cuts anchors with much predicted work into slices
+    whose partial counts are added together (a tiny split size forces it on
+    this small graph); every column must equal the oracle's, as must the
+    static schedule's unsplit result."""
+    g = _heavy_sender_graph(seed)
+    ref = oracle_mine(g, 2000, 5, k)
+    assert ref[2].max() > 0 and ref[3].max() > 0  # columns FAN_OUT, FAN_IN, SG, GS, cycles
+    assert_same(gpu_mine(g, 2000, 5, k), ref, f"heavy senders seed {seed} k {k} static")
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    A.amlm_costmodel_train([G], [A.params(A.AMLM_ALL, 2000, 5, k)], epochs=2, batch=256, seed=seed)
+    for split in (64, 1024, 0):
+        A.amlm_tune_set(G, split_bytes=split)
+        c = A.amlm_mine(G, A.params(A.AMLM_ALL, 2000, 5, k, A.AMLM_SCHED_LEARNED))
+        A.amlm_graph_sync(G)
+        assert_same(A.to_u32(c), ref, f"heavy senders seed {seed} k {k} learned, split {split}")
+    G.close()
+
+
 def test_deterministic_repeat():
     g = W.mid(204, scale=0.01)
     a = gpu_mine(g, 86400, 6, 2)
