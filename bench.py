@@ -245,7 +245,7 @@ def main():
         step()
     A.amlm_graph_sync(G)
     dt, avg = timed(p, args.steps)
-    mine_ms = sum(avg.get(s, 0.0) for s in ("anchor", "lists", "sg", "cyc", "model"))
+    mine_ms = sum(avg.get(s, 0.0) for s in ("anchor", "lists", "units", "sg", "cyc", "model"))
     static = None
     if args.profile:
         # copy probe: 1 GiB read + 1 GiB written by the library's copy kernel

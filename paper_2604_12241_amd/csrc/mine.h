@@ -111,7 +111,7 @@ struct MineLaunch {
 
 
 // Optional HIP-event timing of the stages (recorded on the mining stream).
-enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kNumStages = 8 };
+enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kStUnits = 6, kNumStages = 8 };
 struct StageTimer {
   bool on = false;
   hipEvent_t ev[2 * kNumStages] = {};

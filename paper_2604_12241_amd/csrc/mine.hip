@@ -892,12 +892,12 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
       pred = ms.pred;
       CK(tm->end(kStModel, s));
     }
-    CK(tm->begin(kStSg, s));
     const uint32_t block = std::min(std::max(learned ? cfg.learned_chunk : cfg.sg_chunk, kMinBlock), kSgChunkMax);
     const uint32_t nb = (Ev + 255) / 256;
     if (learned) {
       // work units: blocks of light items and slices of the anchors whose
       // predicted work exceeds the split size, in list order
+      CK(tm->begin(kStUnits, s));
       uint32_t *n_units = ms.ctr + kCtrNUnits;
       unsigned long long *W = (unsigned long long *)(ms.ctr + kCtrSplitW);
       hipLaunchKernelGGL(k_split_weight, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, flags_sg,
@@ -911,6 +911,8 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
       hipLaunchKernelGGL(k_unit_fill, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, ms.nsub, ms.ucnt, ms.uoff,
                          block, ms.units);
       CK(hipGetLastError());
+      CK(tm->end(kStUnits, s));
+      CK(tm->begin(kStSg, s));
       hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, (const uint2 *)ms.units,
                          (const uint32_t *)n_units, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
                          (const uint8_t *)flags_sg);
@@ -922,6 +924,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
       }
     } else {
       // static schedule: fixed blocks of the list
+      CK(tm->begin(kStSg, s));
       hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, (const uint2 *)nullptr,
                          (const uint32_t *)n_sg, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
                          (const uint8_t *)flags_sg);
