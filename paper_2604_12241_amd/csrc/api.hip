@@ -269,6 +269,11 @@ extern "C" void amlm_graph_destroy(amlm_graph *g) {
   free_all(g);
   if (g->timer.ev[0])
     for (hipEvent_t &e : g->timer.ev) (void)hipEventDestroy(e);
+  if (g->aux) {
+    (void)hipEventDestroy(g->ev_fork);
+    (void)hipEventDestroy(g->ev_join);
+    (void)hipStreamDestroy(g->aux);
+  }
   delete g;
 }
 
@@ -391,6 +396,14 @@ amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_de
     cfg.learned = true;
     cfg.delta_hours = (float)p->delta / 3600.f;
   }
+  if (!g->aux) {
+    HIP_TRY(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+  }
+  cfg.aux = g->aux;
+  cfg.ev_fork = g->ev_fork;
+  cfg.ev_join = g->ev_join;
   HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
   return AMLM_OK;
 }

@@ -54,6 +54,8 @@ struct amlm_graph {
   MineScratch ms{};
   TuneParams tune{};
   StageTimer timer{};
+  hipStream_t aux = nullptr;  // second mining stream (cycle kernel), created on first use
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   BatchState batch{};
   amlm_status sticky = AMLM_OK;
   std::vector<void *> allocs;

@@ -478,23 +478,35 @@ __device__ __forceinline__ uint32_t item_slices(const MineParams &mp, const uint
   return (uint32_t)min((unsigned long long)min(kSplitMax, w), (z + se - 1) / se);
 }
 
-__global__ void k_unit_count(MineParams mp, const uint32_t *items, const uint32_t *n_items_p, const uint8_t *flags_sg,
-                             const uint4 *sg_win, const float *pred, uint32_t min_size,
-                             const unsigned long long *W_p, uint32_t block, uint32_t n_max, uint32_t *nsub,
-                             uint32_t *cnt) {
+__global__ __launch_bounds__(256) void k_unit_count(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
+                                                    const uint8_t *flags_sg, const uint4 *sg_win, const float *pred,
+                                                    uint32_t min_size, const unsigned long long *W_p, uint32_t block,
+                                                    uint32_t n_max, uint32_t *nsub, uint32_t *cnt) {
+  __shared__ uint32_t sl[256];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_max) return;
   const uint32_t n = *n_items_p;
+  const unsigned long long W = *W_p;
+  uint32_t ns = 0;
+  if (i < n) {
+    ns = item_slices(mp, items, flags_sg, sg_win, pred, min_size, W, i);
+    if (ns == 1) ns = 0;
+    nsub[i] = ns;
+  }
+  sl[threadIdx.x] = ns;
+  __syncthreads();
+  if (i >= n_max) return;
   if (i >= n) {
     cnt[i] = 0;
     return;
   }
-  const unsigned long long W = *W_p;
-  uint32_t ns = item_slices(mp, items, flags_sg, sg_win, pred, min_size, W, i);
-  if (ns == 1) ns = 0;
-  nsub[i] = ns;
   bool start = false;
-  if (!ns) start = i % block == 0 || (i > 0 && item_slices(mp, items, flags_sg, sg_win, pred, min_size, W, i - 1) > 1);
+  if (!ns) {
+    // the previous item's slices: from this block, or recomputed at its edge
+    uint32_t prev = 0;
+    if (i > 0) prev = threadIdx.x > 0 ? sl[threadIdx.x - 1]
+                                      : item_slices(mp, items, flags_sg, sg_win, pred, min_size, W, i - 1);
+    start = i % block == 0 || prev > 1;
+  }
   cnt[i] = ns ? ns : (start ? 1u : 0u);
 }
 
@@ -882,6 +894,24 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
     CK(hipGetLastError());
   }
   CK(tm->end(kStLists, s));
+  if (want_cyc) {
+    // independent of the scatter-gather stage: on the second stream if given
+    hipStream_t cs = s;
+    if (cfg.aux) {
+      CK(hipEventRecord(cfg.ev_fork, s));
+      CK(hipStreamWaitEvent(cfg.aux, cfg.ev_fork, 0));
+      cs = cfg.aux;
+    }
+    CK(tm->begin(kStCyc, cs));
+    // beside the scatter-gather stage the cycle kernel takes a fraction of
+    // the chip, so that it does not delay it
+    const uint32_t cyc_blocks = cfg.aux ? std::max(1u, cfg.cyc_blocks / kCycForkDiv) : cfg.cyc_blocks;
+    hipLaunchKernelGGL(k_cyc, dim3(cyc_blocks), dim3(kCycThreads), 0, cs, mp, ms.list_cy, n_cy,
+                       ms.ctr + kCtrCycWork);
+    CK(hipGetLastError());
+    CK(tm->end(kStCyc, cs));
+    if (cfg.aux) CK(hipEventRecord(cfg.ev_join, cs));
+  }
   if (want_sg) {
     // learned schedule: the cost model predicts each item's work, which sets
     // how finely the heavy anchors are sliced
@@ -932,13 +962,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
     }
     CK(tm->end(kStSg, s));
   }
-  if (want_cyc) {
-    CK(tm->begin(kStCyc, s));
-    hipLaunchKernelGGL(k_cyc, dim3(cfg.cyc_blocks), dim3(kCycThreads), 0, s, mp, ms.list_cy, n_cy,
-                       ms.ctr + kCtrCycWork);
-    CK(hipGetLastError());
-    CK(tm->end(kStCyc, s));
-  }
+  if (cfg.aux && want_cyc) CK(hipStreamWaitEvent(s, cfg.ev_join, 0));
 #undef CK
   return hipSuccess;
 }
