@@ -107,15 +107,11 @@ struct MineLaunch {
   uint32_t learned_chunk = kSgChunkMax;  // anchors per chunk in the learned schedule
   uint32_t split_bytes = kSplitBytes;    // learned schedule: predicted bytes per slice
   // optional second stream: the cycle kernel runs there, concurrently with
-  // the scatter-gather stage (fork and join through the two events)
+  // the cost model and work units (fork and join through the two events)
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float delta_hours = 24.f;
 };
-#ifndef AMLM_CYC_FORK_DIV
-#define AMLM_CYC_FORK_DIV 4
-#endif
-constexpr uint32_t kCycForkDiv = AMLM_CYC_FORK_DIV;  // grid divisor of the concurrent cycle kernel
 
 
 // Optional HIP-event timing of the stages (recorded on the mining stream).

@@ -895,7 +895,9 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   }
   CK(tm->end(kStLists, s));
   if (want_cyc) {
-    // independent of the scatter-gather stage: on the second stream if given
+    // independent of the scatter-gather stage: on the second stream if
+    // given, beside the cost model and the work units, and joined before
+    // k_sg, which keeps the chip to itself
     hipStream_t cs = s;
     if (cfg.aux) {
       CK(hipEventRecord(cfg.ev_fork, s));
@@ -903,10 +905,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
       cs = cfg.aux;
     }
     CK(tm->begin(kStCyc, cs));
-    // beside the scatter-gather stage the cycle kernel takes a fraction of
-    // the chip, so that it does not delay it
-    const uint32_t cyc_blocks = cfg.aux ? std::max(1u, cfg.cyc_blocks / kCycForkDiv) : cfg.cyc_blocks;
-    hipLaunchKernelGGL(k_cyc, dim3(cyc_blocks), dim3(kCycThreads), 0, cs, mp, ms.list_cy, n_cy,
+    hipLaunchKernelGGL(k_cyc, dim3(cfg.cyc_blocks), dim3(kCycThreads), 0, cs, mp, ms.list_cy, n_cy,
                        ms.ctr + kCtrCycWork);
     CK(hipGetLastError());
     CK(tm->end(kStCyc, cs));
@@ -942,6 +941,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
                          block, ms.units);
       CK(hipGetLastError());
       CK(tm->end(kStUnits, s));
+      if (cfg.aux && want_cyc) CK(hipStreamWaitEvent(s, cfg.ev_join, 0));
       CK(tm->begin(kStSg, s));
       hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, (const uint2 *)ms.units,
                          (const uint32_t *)n_units, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
@@ -954,6 +954,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
       }
     } else {
       // static schedule: fixed blocks of the list
+      if (cfg.aux && want_cyc) CK(hipStreamWaitEvent(s, cfg.ev_join, 0));
       CK(tm->begin(kStSg, s));
       hipLaunchKernelGGL(k_sg, dim3(cfg.sg_blocks), dim3(kSgThreads), 0, s, mp, ms.list_sg, (const uint2 *)nullptr,
                          (const uint32_t *)n_sg, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
@@ -962,7 +963,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
     }
     CK(tm->end(kStSg, s));
   }
-  if (cfg.aux && want_cyc) CK(hipStreamWaitEvent(s, cfg.ev_join, 0));
+  if (cfg.aux && want_cyc && !want_sg) CK(hipStreamWaitEvent(s, cfg.ev_join, 0));
 #undef CK
   return hipSuccess;
 }
