@@ -66,11 +66,15 @@ static void free_all(amlm_graph *g) {
   g->ms = MineScratch();
 }
 
-// Allocate the graph's arrays for E edges and V vertices.
+// Allocate the graph's arrays for E edges and V vertices, with 1/8 spare
+// capacity so that a graph rebuilt a little larger (a serving window) keeps
+// its buffers: a reallocation frees and allocates ~50 buffers, and freeing
+// synchronises the device.
 static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   if (E <= g->cap_e && V <= g->cap_v && g->cap_e) return AMLM_OK;
   free_all(g);
-  uint64_t e = std::max<uint64_t>(E, 1);
+  E = std::min<uint64_t>(E + E / 8 + 1024, 0xfffffffeull);
+  uint64_t e = E;
   uint64_t v1 = (uint64_t)V + 1;
   GraphArrays &a = g->arr;
   A_TRY(dalloc(g, (void **)&a.src, 4 * e));
@@ -118,20 +122,19 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   return AMLM_OK;
 }
 
+// Mining scratch, sized for the graph's edge capacity (so allocated once per
+// graph allocation).
 amlm_status alloc_mine_scratch(amlm_graph *g) {
   MineScratch &ms = g->ms;
-  uint64_t ev = std::max<uint64_t>(g->Ev, 1);
-  if (ms.flags && ms.cap_ev >= ev && ms.cap_e >= g->E) return AMLM_OK;
-  if (ms.flags) {
-    // grow: the old buffers stay owned by the graph until it is freed
-  }
-  uint32_t nb = (uint32_t)((std::max<uint64_t>(ev, g->E) + kFlagTile - 1) / kFlagTile);
-  A_TRY(dalloc(g, (void **)&ms.flags, ((ev + 3) & ~3ull) + ((std::max<uint64_t>(g->E, 1) + 3) & ~3ull)));
+  if (ms.flags && ms.cap_ev >= std::max<uint64_t>(g->Ev, 1) && ms.cap_e >= g->E) return AMLM_OK;
+  const uint64_t ev = std::max<uint64_t>(g->cap_e, 1);
+  uint32_t nb = (uint32_t)((ev + kFlagTile - 1) / kFlagTile);
+  A_TRY(dalloc(g, (void **)&ms.flags, 2 * ((ev + 3) & ~3ull)));
   A_TRY(dalloc(g, (void **)&ms.sg_win, 16 * ev));
   A_TRY(dalloc(g, (void **)&ms.feat, 4 * kMlpRaw * ev));
   A_TRY(dalloc(g, (void **)&ms.pred, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.list_sg, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * std::max<uint64_t>(g->E, 1)));
+  A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.bcnt_sg, 4 * (size_t)nb));
   A_TRY(dalloc(g, (void **)&ms.bcnt_cy, 4 * (size_t)nb));
   A_TRY(dalloc(g, (void **)&ms.boff_sg, 4 * (size_t)nb));
@@ -143,7 +146,7 @@ amlm_status alloc_mine_scratch(amlm_graph *g) {
   A_TRY(dalloc(g, (void **)&ms.uoff, 4 * ev));
   A_TRY(dalloc(g, (void **)&ms.units, 8 * max_units(ev, kMinBlock)));
   ms.cap_ev = ev;
-  ms.cap_e = std::max<uint64_t>(g->E, 1);
+  ms.cap_e = ev;
   return AMLM_OK;
 }
 
@@ -396,14 +399,19 @@ amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_de
     cfg.learned = true;
     cfg.delta_hours = (float)p->delta / 3600.f;
   }
-  if (!g->aux) {
-    HIP_TRY(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+  if (anchor_lo == 0) {
+    // full mining: the cycle kernel overlaps the cost model on a second
+    // stream (incremental mining of small serving windows stays on one
+    // stream: the server's slots already run concurrently)
+    if (!g->aux) {
+      HIP_TRY(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+    }
+    cfg.aux = g->aux;
+    cfg.ev_fork = g->ev_fork;
+    cfg.ev_join = g->ev_join;
   }
-  cfg.aux = g->aux;
-  cfg.ev_fork = g->ev_fork;
-  cfg.ev_join = g->ev_join;
   HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
   return AMLM_OK;
 }

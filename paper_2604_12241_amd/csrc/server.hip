@@ -164,6 +164,8 @@ static void run_job(amlm_server *S, ServerSlot &sl, ServerJob *job) {
   if (S->ncyc && n_ctx) {
     uint64_t cap = std::max<uint64_t>(1u << 16, n_ctx / 4);
     if (sl.dcap < cap) {
+      // regrown with room to spare: freeing synchronises the device
+      cap += cap / 2;
       if (sl.dbuf) (void)hipFree(sl.dbuf);
       sl.dbuf = nullptr;
       sl.dcap = 0;
