@@ -71,26 +71,6 @@ __device__ __forceinline__ float mlp_forward(const float *W, const float *x, flo
   return y;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *w16, const float *norm, const uint32_t *feat,
-                                                   const uint32_t *idx, const uint32_t *n_p, uint32_t n_host,
-                                                   float dh, float L, float *pred) {
-  __shared__ float W[kMlpParams];
-  __shared__ float nrm[2 * kMlpF];
-  for (int p = threadIdx.x; p < kMlpParams; p += blockDim.x) W[p] = dbf16(w16[p]);
-  if (threadIdx.x < 2 * kMlpF) nrm[threadIdx.x] = norm[threadIdx.x];
-  __syncthreads();
-  const uint32_t n = n_p ? *n_p : n_host;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    uint32_t r[kMlpRaw];
-    uint64_t row = idx ? idx[i] : i;
-#pragma unroll
-    for (int q = 0; q < kMlpRaw; q++) r[q] = feat[row * kMlpRaw + q];
-    float x[kMlpF], h1[kMlpH];
-    mlp_input(r, dh, L, nrm, x);
-    pred[i] = mlp_forward(W, x, h1);
-  }
-}
-
 // ---- MFMA inference: 16 anchors per v_mfma_f32_16x16x16_bf16 tile ----
 // Operand layout of the 16x16x16 BF16 MFMA (64 lanes, l = lane):
 //   A (16 x 16, M x K): lane l holds row l % 16, k = 4 (l / 16) + 0..3
