@@ -802,10 +802,6 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
   }
 }
 
-// Sort keys of the learned schedule: predicted cost of each chunk of `chunk`
-// consecutive list items (sum of expm1 of the predicted log-work), quantised
-// so that an ascending sort puts the heaviest chunk first; chunks past the
-// end of the list sort last.
 // Order-preserving compaction of the indices i with flags[i] != 0 (block
 // counts, exclusive scan, scatter).
 __global__ void k_flag_count(const uint8_t *flags, uint32_t n, uint32_t *cnt) {
