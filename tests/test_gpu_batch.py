@@ -73,6 +73,34 @@ def test_batch_equals_standalone_and_oracle_over_replays():
     B.close()
 
 
+def test_batch_learned_schedule_with_slices_over_replays():
+    """The learned schedule inside the captured launch: work units and
+    anchor slices (forced by a tiny split size) are rebuilt on every replay
+    from the device-side lists, and every replay equals the oracle."""
+    subs = _subgraphs(n=8, seed0=950)
+    B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices) for g, _ in subs])
+    train = [A.Graph(g.src, g.dst, g.ts, g.n_vertices) for g, _ in subs if g.n_edges > 1000][:2]
+    A.amlm_costmodel_train(train, [A.params(A.AMLM_ALL, 86400, 5, 2)] * len(train), epochs=2, batch=256, seed=3)
+    for G in train:
+        G.close()
+    A.amlm_tune_set(B, split_bytes=64)
+    ps = [A.params(A.AMLM_ALL, p.delta, p.max_cycle_len, p.k, A.AMLM_SCHED_LEARNED) for _, p in subs]
+    refs = [oracle.mine(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL, p.delta, p.max_cycle_len, p.k)
+            for g, p in subs]
+    other = W.mid(778, scale=0.002)
+    for rep in range(3):
+        outs = A.amlm_mine_batch(B, ps)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(A.to_u32(o), r, err_msg=f"learned replay {rep} graph {i}")
+        G = A.Graph(other.src, other.dst, other.ts, other.n_vertices)
+        A.amlm_mine(G, A.params(A.AMLM_ALL, 86400, 5, 2))
+        torch.cuda.synchronize()
+        G.close()
+    assert B.info_batch()[1] == 1
+    B.close()
+
+
 def test_batch_rejects_bad_input():
     with pytest.raises(A.AmlmError):
         A.Batch([(np.array([0, 5], np.uint32), np.array([1, 0], np.uint32),
