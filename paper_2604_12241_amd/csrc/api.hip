@@ -31,8 +31,11 @@ DeviceInfo &device_info() {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sg_ptr(), kSgThreads, 0) == hipSuccess && occ > 0)
       info.sg_occ = occ;
     occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_cyc_ptr(), kCycThreads, 0) == hipSuccess && occ > 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_cyc_ptr(false), kCycThreads, 0) == hipSuccess && occ > 0)
       info.cyc_occ = occ;
+    occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_cyc_ptr(true), kCycThreads, 0) == hipSuccess && occ > 0)
+      info.cyc_occ_small = occ;
   });
   return info;
 }
@@ -361,10 +364,11 @@ MineLaunch default_launch(const amlm_graph *g) {
   MineLaunch cfg;
   cfg.sg_blocks = (uint32_t)(di.num_cu * di.sg_occ);
   cfg.cyc_blocks = (uint32_t)(di.num_cu * di.cyc_occ);
+  cfg.cyc_blocks_small = (uint32_t)(di.num_cu * di.cyc_occ_small);
   cfg.sg_chunk = kSgChunkMax;  // anchors per work-stealing grab
   if (g->tune.sg_chunk) cfg.sg_chunk = g->tune.sg_chunk;
   if (g->tune.sg_blocks) cfg.sg_blocks = g->tune.sg_blocks;
-  if (g->tune.cyc_blocks) cfg.cyc_blocks = g->tune.cyc_blocks;
+  if (g->tune.cyc_blocks) cfg.cyc_blocks = cfg.cyc_blocks_small = g->tune.cyc_blocks;
   if (g->tune.split_bytes) cfg.split_bytes = g->tune.split_bytes;
   return cfg;
 }

@@ -10,7 +10,7 @@
 struct DeviceInfo {
   int num_cu = 256;
   int sg_occ = 4;
-  int cyc_occ = 3;
+  int cyc_occ = 3, cyc_occ_small = 3;
   char name[64] = "gfx950";
 };
 DeviceInfo &device_info();

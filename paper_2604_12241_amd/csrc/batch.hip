@@ -196,7 +196,7 @@ static std::string batch_signature(const amlm_graph *g, uint32_t patterns, uint3
                                    const MineLaunch &cfg) {
   std::ostringstream o;
   o << patterns << "/" << schedule << "/" << Lmax << "/" << cfg.sg_blocks << "/" << cfg.sg_chunk << "/"
-    << cfg.cyc_blocks << "/" << cfg.learned_chunk << "/" << cfg.split_bytes << "/" << g->E << "/" << g->ms.cap_ev;
+    << cfg.cyc_blocks << "/" << cfg.cyc_blocks_small << "/" << cfg.learned_chunk << "/" << cfg.split_bytes << "/" << g->E << "/" << g->ms.cap_ev;
   return o.str();
 }
 
@@ -384,7 +384,10 @@ extern "C" amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint3
   } else {
     DeviceInfo &di = device_info();
     const uint32_t chunks[] = {kMinBlock, 6, kSgChunkMax};
-    const uint32_t sg_full = (uint32_t)(di.num_cu * di.sg_occ), cyc_full = (uint32_t)(di.num_cu * di.cyc_occ);
+    uint32_t Lmax = 0;
+    for (uint32_t i = 0; i < n_params; i++) Lmax = std::max(Lmax, ps[i].max_cycle_len);
+    const int cyc_occ = Lmax <= kCycSmallL ? di.cyc_occ_small : di.cyc_occ;
+    const uint32_t sg_full = (uint32_t)(di.num_cu * di.sg_occ), cyc_full = (uint32_t)(di.num_cu * cyc_occ);
     const uint32_t grids[][2] = {{sg_full, cyc_full}, {sg_full / 2, cyc_full / 2}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));

@@ -41,6 +41,7 @@ constexpr uint32_t kLongPair = 64;                      // slices scanned by the
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
 constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
+constexpr uint32_t kCycSmallL = 6;   // cycle kernel built with fewer frames for L <= 6
 
 constexpr uint32_t kFlagThreads = 256, kFlagItems = 16, kFlagTile = kFlagThreads * kFlagItems;
 
@@ -102,7 +103,7 @@ inline uint64_t max_units(uint64_t ev, uint32_t block) { return ev / block + ev 
 constexpr uint32_t kSplitBytes = AMLM_SPLIT_BYTES;  // learned schedule: predicted bytes per slice
 
 struct MineLaunch {
-  uint32_t sg_blocks, sg_chunk, cyc_blocks;
+  uint32_t sg_blocks, sg_chunk, cyc_blocks, cyc_blocks_small;  // cycle grids for L > 6 and L <= 6
   bool learned = false;         // schedule scatter-gather chunks by the cost model
   uint32_t learned_chunk = kSgChunkMax;  // anchors per chunk in the learned schedule
   uint32_t split_bytes = kSplitBytes;    // learned schedule: predicted bytes per slice
@@ -133,7 +134,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
 
 // kernel handles for occupancy queries
 const void *k_sg_ptr();
-const void *k_cyc_ptr();
+const void *k_cyc_ptr(bool small);  // small: the build for L <= kCycSmallL
 
 // Algorithmic bytes per unit of work (what each stage must read, at the
 // width of the fields it needs), used for the work counters and the roofline:

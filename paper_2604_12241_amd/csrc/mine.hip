@@ -641,8 +641,8 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
 // 64) form the next frame, which is searched before the parent continues.
 // LDS use is bounded by L - 1 frames whatever the size of the search tree.
 struct CycFrame {
-  uint32_t par[AMLM_WAVE];   // slot of the parent in the frame below
-  uint32_t root[AMLM_WAVE];  // root (anchor) slot
+  uint8_t par[AMLM_WAVE];    // slot of the parent in the frame below
+  uint8_t root[AMLM_WAVE];   // root (anchor) slot
   uint32_t eid[AMLM_WAVE];   // edge from the parent to this node
   uint32_t vert[AMLM_WAVE];  // head vertex
   int32_t tau[AMLM_WAVE];    // time of the last edge (first hop: lo - 1)
@@ -651,14 +651,19 @@ struct CycFrame {
   uint32_t n, T, cur;
 };
 
+// Frame i holds paths of i edges, so cycles of up to L edges need frames
+// 0 .. L - 2: the kernel is built for L <= 6 (5 frames) and L <= 8 (7), and
+// the smaller LDS footprint of the first runs more waves per CU.
+template <int kFrames>
 struct CycLds {
   uint32_t r_eid[AMLM_WAVE], r_u[AMLM_WAVE], r_L[AMLM_WAVE];
   int32_t r_t[AMLM_WAVE];
-  CycFrame fr[kMaxDepth + 1];
+  CycFrame fr[kFrames];
 };
 
 // +inc on column `len` for the anchor and every path edge of node (i, slot)
-__device__ __forceinline__ void cyc_credit_path(const MineParams &mp, const CycLds &S, uint32_t i, uint32_t slot,
+template <class S_t>
+__device__ __forceinline__ void cyc_credit_path(const MineParams &mp, const S_t &S, uint32_t i, uint32_t slot,
                                                 uint32_t len, uint32_t inc) {
   uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)len - 2) * mp.stride;
   credit(col + S.r_eid[S.fr[i].root[slot]], inc, mp.err);
@@ -668,7 +673,8 @@ __device__ __forceinline__ void cyc_credit_path(const MineParams &mp, const CycL
   }
 }
 
-__device__ __forceinline__ bool cyc_on_path(const CycLds &S, uint32_t i, uint32_t slot, uint32_t w) {
+template <class S_t>
+__device__ __forceinline__ bool cyc_on_path(const S_t &S, uint32_t i, uint32_t slot, uint32_t w) {
   for (uint32_t j = i;; j--) {
     if (S.fr[j].vert[slot] == w) return true;
     if (j == 0) return false;
@@ -678,7 +684,8 @@ __device__ __forceinline__ bool cyc_on_path(const CycLds &S, uint32_t i, uint32_
 
 // Slice bounds of every node of frame i, or, at the last depth, the closing
 // edges counted by binary search and credited at once.
-__device__ void cyc_prepare(const MineParams &mp, CycLds &S, uint32_t i) {
+template <class S_t>
+__device__ void cyc_prepare(const MineParams &mp, S_t &S, uint32_t i) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   CycFrame &F = S.fr[i];
@@ -719,10 +726,11 @@ __device__ void cyc_prepare(const MineParams &mp, CycLds &S, uint32_t i) {
   }
 }
 
+template <int kFrames>
 __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32_t *roots, const uint32_t *n_in_p,
                                                      uint32_t *ctr) {
-  __shared__ CycLds lds[kCycThreads / AMLM_WAVE];
-  CycLds &S = lds[threadIdx.x / AMLM_WAVE];
+  __shared__ CycLds<kFrames> lds[kCycThreads / AMLM_WAVE];
+  CycLds<kFrames> &S = lds[threadIdx.x / AMLM_WAVE];
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
@@ -743,8 +751,8 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
       S.r_t[lane] = t;
       S.r_L[lane] = L_of(mp, u);
       CycFrame &F0 = S.fr[0];
-      F0.par[lane] = lane;
-      F0.root[lane] = lane;
+      F0.par[lane] = (uint8_t)lane;
+      F0.root[lane] = (uint8_t)lane;
       F0.eid[lane] = 0xffffffffu;
       F0.vert[lane] = v;
       F0.tau[lane] = window_lo(t, delta_of(mp, u)) - 1;  // first hop at time >= lo
@@ -788,7 +796,7 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
         CycFrame &G = S.fr[sp + 1];
         if (child) {
           uint32_t slot = __popcll(bc & lt);
-          G.par[slot] = a;
+          G.par[slot] = (uint8_t)a;
           G.root[slot] = F.root[a];
           G.eid[slot] = ceid;
           G.vert[slot] = w;
@@ -901,8 +909,12 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
       cs = cfg.aux;
     }
     CK(tm->begin(kStCyc, cs));
-    hipLaunchKernelGGL(k_cyc, dim3(cfg.cyc_blocks), dim3(kCycThreads), 0, cs, mp, ms.list_cy, n_cy,
-                       ms.ctr + kCtrCycWork);
+    if (mp.L <= kCycSmallL)
+      hipLaunchKernelGGL(k_cyc<kCycSmallL - 1>, dim3(cfg.cyc_blocks_small), dim3(kCycThreads), 0, cs, mp, ms.list_cy,
+                         n_cy, ms.ctr + kCtrCycWork);
+    else
+      hipLaunchKernelGGL(k_cyc<kMaxDepth + 1>, dim3(cfg.cyc_blocks), dim3(kCycThreads), 0, cs, mp, ms.list_cy, n_cy,
+                         ms.ctr + kCtrCycWork);
     CK(hipGetLastError());
     CK(tm->end(kStCyc, cs));
     if (cfg.aux) CK(hipEventRecord(cfg.ev_join, cs));
@@ -965,4 +977,6 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
 }
 
 const void *k_sg_ptr() { return (const void *)k_sg; }
-const void *k_cyc_ptr() { return (const void *)k_cyc; }
+const void *k_cyc_ptr(bool small) {
+  return small ? (const void *)k_cyc<kCycSmallL - 1> : (const void *)k_cyc<kMaxDepth + 1>;
+}
