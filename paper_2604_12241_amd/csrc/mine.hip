@@ -176,9 +176,11 @@ struct SgLds {
   uint32_t i_join[kSgChunkMax]; // 1 if the anchor's senders need the join
   uint32_t i_gsd[kSgChunkMax];  // 1 if u has k scatter destinations after tau
   // (anchor, sender) pairs of one batch
-  uint32_t pr_item[AMLM_WAVE], pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
+  uint32_t pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
+  uint8_t pr_item[AMLM_WAVE];
   // Bloom-positive candidates awaiting the exact check
-  uint32_t cq_pair[kCandCap], cq_pos[kCandCap];
+  uint32_t cq_pos[kCandCap];
+  uint8_t cq_pair[kCandCap];  // byte-wide slot fields keep the LDS, and so the waves per CU, in bounds
 };
 
 // Register-blocked Bloom filter over vertex hashes (vhash): a key selects
@@ -249,7 +251,7 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
   if (bc == 0) return;
   if (cand) {
     uint32_t slot = cq + __popcll(bc & lanemask_lt());
-    L.cq_pair[slot] = a;
+    L.cq_pair[slot] = (uint8_t)a;
     L.cq_pos[slot] = pos;
   }
   cq += __popcll(bc);
@@ -402,7 +404,7 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     uint32_t np = __popcll(bs);
     if (pair) {
       uint32_t slot = __popcll(bs & lt);
-      L.pr_item[slot] = it;
+      L.pr_item[slot] = (uint8_t)it;
       L.pr_b[slot] = b;
       L.pr_n[slot] = n;
       L.pr_cnt[slot] = 0;
