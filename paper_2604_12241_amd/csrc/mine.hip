@@ -647,8 +647,12 @@ struct CycFrame {
   uint8_t root[AMLM_WAVE];   // root (anchor) slot
   uint32_t eid[AMLM_WAVE];   // edge from the parent to this node
   uint32_t vert[AMLM_WAVE];  // head vertex
-  int32_t tau[AMLM_WAVE];    // time of the last edge (first hop: lo - 1)
-  uint32_t xb[AMLM_WAVE];    // first slice entry
+  // time of the last edge (first hop: lo - 1) until cyc_prepare reads it,
+  // then the first entry of the node's slice (one array, less LDS)
+  union {
+    int32_t tau[AMLM_WAVE];
+    uint32_t xb[AMLM_WAVE];
+  };
   uint32_t xoff[AMLM_WAVE];  // exclusive prefix of slice sizes
   uint32_t n, T, cur;
 };
