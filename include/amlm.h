@@ -73,10 +73,13 @@ typedef enum {
 #define AMLM_ALL 31u
 
 /* schedules for the scatter-gather and cycle work (never change a count) */
-#define AMLM_SCHED_STATIC 0u  /* anchors in time order, one wave per anchor,
-                                 chunks taken by atomic work stealing */
-#define AMLM_SCHED_LEARNED 1u /* the cost model's predicted work bins anchors
-                                 into lane / wave granularity, heavy first */
+#define AMLM_SCHED_STATIC 0u  /* anchors in time order, fixed-size blocks of
+                                 anchors taken by atomic work stealing */
+#define AMLM_SCHED_LEARNED 1u /* the cost model's predicted scatter-gather bytes
+                                 cut each anchor heavier than the split size
+                                 into sender-window slices (one work unit each)
+                                 and group light anchors into small blocks;
+                                 requires a trained or loaded cost model */
 
 typedef struct {
     uint32_t patterns;      /* OR of AMLM_FAN_OUT .. AMLM_CYCLES */
