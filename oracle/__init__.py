@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 FAN_OUT, FAN_IN, SG, GS, CYC = 1, 2, 4, 8, 16
 ALL = FAN_OUT | FAN_IN | SG | GS | CYC
+SG_UNORDERED = 32  # modifier of SG: the two legs of an intermediate in either order
 
 
 def build_oracle() -> str:

@@ -23,6 +23,10 @@
  *                (the intersection N2.out_neigh with N1.in_neigh; Section 3's
  *                per-intermediate partial order t_i < t_{i+1})
  *   SG_k(e)    = #{s in S(e) : |M_e(s)| >= k}   ("at least N", Section 4)
+ *   with OR_SG_UNORDERED, M_e(s) drops the order of the two legs:
+ *                t - delta <= ts_a < t and t - delta <= ts_b <= t, the
+ *                window-only checks of the compiled scatter-gather example
+ *                (Section 6) and the optional per-step order of Section 4
  *   GS_k(e)    = |S(e)| if |S(e)| >= k and |D(e)| >= k, else 0, with
  *                tau = earliest ts of an edge into u from s != v in [t-delta, t)
  *                and D(e) = distinct d with u -> d, tau < ts <= t
@@ -52,6 +56,7 @@
 #define OR_SG 4u
 #define OR_GS 8u
 #define OR_CYC 16u
+#define OR_SG_UNORDERED 32u /* modifies OR_SG; adds no column */
 
 typedef struct {
     uint64_t n;
@@ -164,7 +169,7 @@ static void scratch_free(og_scratch *s) {
 }
 
 /* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k (written to out4). */
-static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k,
+static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k, int unordered,
                      uint64_t out4[4]) {
     uint32_t u = g->src[e], v = g->dst[e];
     int64_t t = g->ts[e], lo = t - delta;
@@ -209,7 +214,8 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
         for (uint64_t p = r0; p < r1; p++) {
             uint64_t a = g->out_e[p];
             uint32_t m = g->dst[a];
-            if (sc->stamp_b[m] == cb && g->ts[a] < sc->maxb[m] && sc->stamp_m[m] != cm) {
+            /* maxb >= lo always: it is a gather time inside the window */
+            if (sc->stamp_b[m] == cb && (unordered || g->ts[a] < sc->maxb[m]) && sc->stamp_m[m] != cm) {
                 sc->stamp_m[m] = cm;
                 nm++;
             }
@@ -272,6 +278,8 @@ static int check_params(uint32_t patterns, int64_t delta, uint32_t L, uint32_t k
     if (delta < 0) return 3;
     if ((patterns & (OR_SG | OR_GS)) && k == 0) return 3;
     if ((patterns & OR_CYC) && (L < 2 || L > 8)) return 3;
+    if ((patterns & OR_SG_UNORDERED) && !(patterns & OR_SG)) return 3;
+    if (patterns & ~(OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_CYC | OR_SG_UNORDERED)) return 3;
     return 0;
 }
 
@@ -319,7 +327,7 @@ int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32
     if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS)) {
         for (uint64_t e = a_lo; e < a_hi; e++) {
             uint64_t r[4];
-            anchored(&g, &sc, e, delta, k, r);
+            anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, r);
             if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = clamp32(r[0]);
             if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = clamp32(r[1]);
             if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = clamp32(r[2]);
@@ -435,7 +443,7 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
         if (e >= n) { og_free(&g); scratch_free(&sc); return 3; }
         uint32_t col = 0;
         uint64_t r[4];
-        anchored(&g, &sc, e, delta, k, r);
+        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, r);
         if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[0]);
         if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[1]);
         if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[2]);

@@ -9,8 +9,10 @@ from __future__ import annotations
 import numpy as np
 
 
-def brute_counts(src, dst, ts, delta: int, L: int, k: int) -> np.ndarray:
-    """Columns FAN_OUT, FAN_IN, SG_k, GS_k, CYC_2..CYC_L; uint64 [4+L-1, n]."""
+def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = False) -> np.ndarray:
+    """Columns FAN_OUT, FAN_IN, SG_k, GS_k, CYC_2..CYC_L; uint64 [4+L-1, n].
+    sg_unordered: an intermediate's gather leg may come before its scatter
+    leg (both inside the window)."""
     src = [int(x) for x in src]
     dst = [int(x) for x in dst]
     ts = [int(x) for x in ts]
@@ -31,7 +33,8 @@ def brute_counts(src, dst, ts, delta: int, L: int, k: int) -> np.ndarray:
                     continue
                 m = dst[a]
                 for b in E:
-                    if src[b] == m and dst[b] == v and ts[a] < ts[b] <= t:
+                    after = lo <= ts[b] if sg_unordered else ts[a] < ts[b]
+                    if src[b] == m and dst[b] == v and after and ts[b] <= t:
                         M.add(m)
                         break
             if len(M) >= k:

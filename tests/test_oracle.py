@@ -39,6 +39,21 @@ def test_oracle_matches_brute_force(seed):
     np.testing.assert_array_equal(o.astype(np.uint64), b)
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_oracle_unordered_sg_matches_brute_force(seed):
+    """The unordered scatter-gather modifier against the literal enumeration
+    with the per-intermediate order dropped."""
+    rng = np.random.default_rng(3000 + seed)
+    nv = int(rng.integers(4, 12))
+    g = W.random_small(700 + seed, n_edges=int(rng.integers(30, 140)), n_vertices=nv,
+                       t_range=int(rng.integers(5, 50)))
+    delta = int(rng.integers(0, 40))
+    k = int(rng.integers(1, 4))
+    o = mine(g.src, g.dst, g.ts, g.n_vertices, delta, 3, k, patterns=oracle.ALL | oracle.SG_UNORDERED)
+    b = brute_counts(g.src, g.dst, g.ts, delta, 3, k, sg_unordered=True)
+    np.testing.assert_array_equal(o.astype(np.uint64), b)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_selected_matches_full(seed):
     """Through-edge cycle enumeration (any position) agrees with the
@@ -105,6 +120,29 @@ def test_scatter_gather_closed_form(K):
         np.testing.assert_array_equal(sg[K:], (np.arange(1, K + 1) >= k).astype(np.uint32))
         gs = o[3]
         np.testing.assert_array_equal(gs[K:], np.full(K, 1 if k == 1 else 0))
+
+
+@pytest.mark.parametrize("K", [1, 3, 6])
+def test_reversed_scatter_gather_closed_form(K):
+    """Every intermediate's gather leg m_j -> v comes before its scatter leg
+    s -> m_j, all inside one window: the ordered count sees only u as an
+    intermediate, the unordered one sees u and all K of the m_j."""
+    s_, u, v = 0, 1, 2
+    edges = [(3 + j, v, j) for j in range(K)]            # gathers first
+    edges += [(s_, 3 + j, K + j) for j in range(K)]      # then the scatters
+    edges += [(s_, u, 2 * K), (u, v, 2 * K + 1)]         # sender leg, anchor
+    src, dst, ts, nv = _motif_graph(edges, 3 + K)
+    for k in range(1, K + 3):
+        o = mine(src, dst, ts, nv, 86400, 4, k)
+        ou = mine(src, dst, ts, nv, 86400, 4, k, patterns=oracle.ALL | oracle.SG_UNORDERED)
+        assert o[2, -1] == (1 if k == 1 else 0)
+        assert ou[2, -1] == (1 if k <= K + 1 else 0)
+        # nothing else moves: the other anchors have no sender
+        np.testing.assert_array_equal(np.delete(ou, 2, axis=0), np.delete(o, 2, axis=0))
+        np.testing.assert_array_equal(ou[2, :-1], 0)
+    # a window that ends before the first gather leg drops the m_j again
+    o = mine(src, dst, ts, nv, 60 * (K + 1), 4, 2, patterns=oracle.ALL | oracle.SG_UNORDERED)
+    assert o[2, -1] == 0
 
 
 @pytest.mark.parametrize("k_in,k_out", [(2, 2), (3, 5), (6, 2), (8, 8)])
@@ -222,6 +260,12 @@ def test_i4_monotone(mid_small):
     assert (c[2:4] <= b[2:4]).all()
     d = mine(g.src, g.dst, g.ts, g.n_vertices, 86400, 3, 2)
     np.testing.assert_array_equal(d, b[:6])   # CYC_l does not depend on L >= l
+    # dropping the per-intermediate order only adds intermediates: SG grows,
+    # every other column stays
+    u = mine(g.src, g.dst, g.ts, g.n_vertices, 86400, 5, 2,
+             patterns=oracle.ALL | oracle.SG_UNORDERED).astype(np.int64)
+    assert (u[2] >= b[2]).all() and (u[2] > b[2]).any()
+    np.testing.assert_array_equal(np.delete(u, 2, axis=0), np.delete(b, 2, axis=0))
 
 
 def test_i5_relabel_shift_permute(mid_small):
@@ -283,6 +327,11 @@ def test_parameter_errors():
         mine(s, d, t, 2, 10, 4, 0)            # k = 0
     o = mine(s[:0], d[:0], t[:0], 2, 10, 4, 2)
     assert o.shape == (7, 0)
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.FAN_OUT | oracle.SG_UNORDERED)  # modifier without SG
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | 64)                       # unknown bit
+    assert mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | oracle.SG_UNORDERED).shape == (7, 2)
 
 
 def test_anchor_ranges_add_up(mid_small):
