@@ -160,7 +160,7 @@ def bench_batching(A, n_graphs=256, steps=5):
             "hipgraph_captures": captures}
 
 
-def cpu_baseline(g, delta, L, k, target_s=12.0):
+def cpu_baseline(g, delta, L, k, unordered=False, target_s=12.0):
     """The oracle (single thread) on a bounded, contiguous range of anchors in
     the middle of the graph (time order); its one-off graph set-up is not
     counted."""
@@ -168,7 +168,8 @@ def cpu_baseline(g, delta, L, k, target_s=12.0):
     n = g.n_edges
     m = min(n, 400_000)
     lo = n // 2 - m // 2
-    _, sec = oracle.mine_range(g.src, g.dst, g.ts, g.n_vertices, lo, lo + m, oracle.ALL, delta, L, k)
+    pats = oracle.ALL | (oracle.SG_UNORDERED if unordered else 0)
+    _, sec = oracle.mine_range(g.src, g.dst, g.ts, g.n_vertices, lo, lo + m, pats, delta, L, k)
     return {"value": m / sec, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"anchors [{lo}, {lo + m}) of {n} (time order, middle of the span), "
                       f"{sec:.1f} s of mining, graph set-up excluded",
@@ -182,6 +183,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="learned", choices=["static", "learned"])
+    ap.add_argument("--sg-order", default="ordered", choices=["ordered", "unordered"],
+                    help="scatter-gather legs of an intermediate strictly ordered (default) or window-only")
     ap.add_argument("--train-graphs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -210,8 +213,9 @@ def main():
         args.no_serve = args.no_batch = args.no_cpu_baseline = True
     if sched == A.AMLM_SCHED_LEARNED:
         train_cost_model(delta, L, k, args.train_graphs, args.model_cache)
-    p = A.params(A.AMLM_ALL, delta, L, k, sched)
-    p_static = A.params(A.AMLM_ALL, delta, L, k, A.AMLM_SCHED_STATIC)
+    pats = A.AMLM_ALL | (A.AMLM_SG_UNORDERED if args.sg_order == "unordered" else 0)
+    p = A.params(pats, delta, L, k, sched)
+    p_static = A.params(pats, delta, L, k, A.AMLM_SCHED_STATIC)
     G = A.Graph(src, dst, ts, g.n_vertices)
     E = g.n_edges
     counts = torch.empty((A.amlm_num_columns(p), E), dtype=torch.int32, device=dev)
@@ -279,6 +283,7 @@ def main():
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {E} edges, {g.n_vertices} accounts, "
                                f"delta={delta}s, L={L}, k={k}", "schedule": args.schedule,
+                   "sg_order": args.sg_order,
                    "n_edges": E, "n_vertices": g.n_vertices, "delta": delta, "L": L, "k": k},
         "mine_only_edges_per_s": E / (mine_ms * 1e-3) if mine_ms > 0 else None,
         "stage_ms": avg,
@@ -294,7 +299,7 @@ def main():
         out["batching"] = bench_batching(A)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(g, delta, L, k)
+        out["cpu_baseline"] = cpu_baseline(g, delta, L, k, args.sg_order == "unordered")
     print(json.dumps(out), flush=True)
     G.close()
 

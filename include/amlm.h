@@ -20,7 +20,8 @@
  *   FAN_IN(e)   in-edges of v with timestamp in [t - delta, t]
  *   S(e)        distinct s != v with an edge s -> u at a time in [t-delta, t)
  *   M_e(s)      distinct m with edges s -> m at time a and m -> v at time b,
- *               t - delta <= a < b <= t
+ *               t - delta <= a < b <= t (with AMLM_SG_UNORDERED: a in
+ *               [t - delta, t) and b in [t - delta, t], either order)
  *   SG_k(e)     number of s in S(e) with |M_e(s)| >= k   (Section 5,
  *               scatter-gather decomposition; Section 4, "at least N")
  *   GS_k(e)     |S(e)| if |S(e)| >= k and u has at least k distinct
@@ -71,6 +72,12 @@ typedef enum {
 #define AMLM_GS 8u
 #define AMLM_CYCLES 16u
 #define AMLM_ALL 31u
+/* modifier of AMLM_SG (adds no column): an intermediate m of sender s counts
+ * when s -> m lies in [t - delta, t) and m -> v in [t - delta, t], in either
+ * order; only the window bounds the two legs, as in Section 6's compiled
+ * scatter-gather example (Section 4: per-step order is optional).  Without
+ * it s -> m must come strictly before m -> v. */
+#define AMLM_SG_UNORDERED 32u
 
 /* schedules for the scatter-gather and cycle work (never change a count) */
 #define AMLM_SCHED_STATIC 0u  /* anchors in time order, fixed-size blocks of
@@ -82,7 +89,8 @@ typedef enum {
                                  requires a trained or loaded cost model */
 
 typedef struct {
-    uint32_t patterns;      /* OR of AMLM_FAN_OUT .. AMLM_CYCLES */
+    uint32_t patterns;      /* OR of AMLM_FAN_OUT .. AMLM_CYCLES, optionally
+                               AMLM_SG_UNORDERED with AMLM_SG */
     int64_t delta;          /* window length, same unit as the timestamps, >= 0 */
     uint32_t max_cycle_len; /* L, 2..8 (ignored without AMLM_CYCLES) */
     uint32_t k;             /* >= 1: SG / GS threshold (ignored without SG|GS) */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libamlm.so")
 
 AMLM_FAN_OUT, AMLM_FAN_IN, AMLM_SG, AMLM_GS, AMLM_CYCLES = 1, 2, 4, 8, 16
 AMLM_ALL = 31
+AMLM_SG_UNORDERED = 32  # modifier of AMLM_SG: an intermediate's two legs in either order
 AMLM_SCHED_STATIC, AMLM_SCHED_LEARNED = 0, 1
 STATUS = {0: "AMLM_OK", 1: "AMLM_E_INVALID", 2: "AMLM_E_RANGE", 3: "AMLM_E_NOMEM",
           4: "AMLM_E_DEVICE", 5: "AMLM_E_ORDER", 6: "AMLM_E_BUSY"}

@@ -303,8 +303,12 @@ amlm_status check_params(const amlm_params *p) {
     set_error("null params");
     return AMLM_E_INVALID;
   }
-  if (p->patterns == 0 || (p->patterns & ~AMLM_ALL)) {
-    set_error("patterns must be a non-empty subset of AMLM_ALL");
+  if ((p->patterns & AMLM_ALL) == 0 || (p->patterns & ~(AMLM_ALL | AMLM_SG_UNORDERED))) {
+    set_error("patterns must be a non-empty subset of AMLM_ALL (plus AMLM_SG_UNORDERED)");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_SG_UNORDERED) && !(p->patterns & AMLM_SG)) {
+    set_error("AMLM_SG_UNORDERED modifies AMLM_SG, which is not requested");
     return AMLM_E_INVALID;
   }
   if (p->delta < 0) {
@@ -352,6 +356,7 @@ MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *coun
   mp.col_sg = (p->patterns & AMLM_SG) ? c++ : -1;
   mp.col_gs = (p->patterns & AMLM_GS) ? c++ : -1;
   mp.col_cyc = (p->patterns & AMLM_CYCLES) ? c : -1;
+  mp.sg_unordered = (p->patterns & AMLM_SG_UNORDERED) ? 1u : 0u;
   mp.counts = counts;
   mp.stride = g->E;
   mp.work = work;

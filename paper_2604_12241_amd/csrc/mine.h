@@ -67,6 +67,7 @@ struct MineParams {
   const SubParams *sub;   // batched store: parameters per sub-graph
   uint32_t anchor_lo;     // only edges with id >= anchor_lo are anchors (0 = all)
   int col_fo, col_fi, col_sg, col_gs, col_cyc;  // -1 when not requested
+  uint32_t sg_unordered;  // 1: an intermediate's two legs in either order
   uint32_t *counts;
   uint64_t stride;   // row stride of counts (= number of edges)
   uint32_t *work;    // optional per-edge algorithmic bytes: [0, E) scatter-gather

@@ -236,8 +236,11 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
     uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
     if (q > vrs) {
       uint64_t kk = g.inn_key[q - 1];  // the last m -> v edge at or before t, if any
-      if ((uint32_t)(kk >> 32) == m && g.out_prv[pos] < lo && (int32_t)(uint32_t)kk > g.out_t[pos])
-        atomicAdd(&L.pr_cnt[a], 1u);
+      const int32_t tb = (int32_t)(uint32_t)kk;
+      // ordered: after this s -> m edge, the pair's first in the window;
+      // unordered: anywhere in the window
+      const bool timed = mp.sg_unordered ? tb >= lo : tb > g.out_t[pos];
+      if ((uint32_t)(kk >> 32) == m && g.out_prv[pos] < lo && timed) atomicAdd(&L.pr_cnt[a], 1u);
     }
   }
 }

@@ -31,6 +31,10 @@ def test_library_loads_and_reports_columns():
         assert getattr(L, name) is not None
     assert A.amlm_num_columns(A.params(L=6)) == 9
     assert A.amlm_num_columns(A.params(patterns=A.AMLM_FAN_OUT | A.AMLM_CYCLES, L=3)) == 3
+    # the unordered scatter-gather modifier adds no column and needs AMLM_SG
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | A.AMLM_SG_UNORDERED, L=4)) == 7
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_FAN_OUT | A.AMLM_SG_UNORDERED, L=4)) == 0
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | 64, L=4)) == 0
     assert A.amlm_num_columns(A.params(L=9)) == 0          # invalid L
     assert A.amlm_num_columns(A.params(k=0)) == 0          # invalid k
     assert A.amlm_num_columns(A.params(delta=-1)) == 0     # invalid window

@@ -35,6 +35,21 @@ def _subgraphs(n=10, seed0=900):
     return out
 
 
+def test_batch_unordered_sg_over_replays():
+    """The unordered scatter-gather modifier through the captured batch."""
+    subs = _subgraphs(n=6, seed0=950)
+    ps = [A.params(A.AMLM_ALL | A.AMLM_SG_UNORDERED, p.delta, p.max_cycle_len, p.k) for _, p in subs]
+    B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices) for g, _ in subs])
+    refs = [oracle.mine(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL | oracle.SG_UNORDERED, p.delta,
+                        p.max_cycle_len, p.k) for (g, _), p in zip(subs, ps)]
+    for rep in range(2):
+        outs = A.amlm_mine_batch(B, ps)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(A.to_u32(o), r, err_msg=f"unordered replay {rep} graph {i}")
+    B.close()
+
+
 def test_batch_equals_standalone_and_oracle_over_replays():
     subs = _subgraphs()
     B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices) for g, _ in subs])

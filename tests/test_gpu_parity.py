@@ -190,6 +190,56 @@ def test_split_heavy_sender_windows(seed, k):
     G.close()
 
 
+UNORD = A.AMLM_ALL | A.AMLM_SG_UNORDERED
+UNORD_O = oracle.ALL | oracle.SG_UNORDERED
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_unordered_sg_random_small(seed):
+    """The unordered scatter-gather modifier: only the verification's timing
+    test changes, so every column must still equal the oracle's."""
+    rng = np.random.default_rng(800 + seed)
+    g = W.random_small(40 + seed, n_edges=int(rng.integers(30, 400)), n_vertices=int(rng.integers(3, 20)),
+                       t_range=int(rng.integers(5, 80)))
+    for (delta, L, k) in [(int(rng.integers(0, 60)), int(rng.integers(2, 7)), int(rng.integers(1, 5))),
+                          (30, 4, 2), (1000, 3, 3)]:
+        assert_same(gpu_mine(g, delta, L, k, patterns=UNORD), oracle_mine(g, delta, L, k, patterns=UNORD_O),
+                    f"unordered seed {seed} d{delta} L{L} k{k}")
+
+
+def test_unordered_sg_mid_and_subset():
+    g = W.mid(205, scale=0.01)
+    ref = oracle_mine(g, 86400, 4, 2, patterns=UNORD_O)
+    ordered = oracle_mine(g, 86400, 4, 2)
+    assert (ref[2] > ordered[2]).any()  # the variant changes counts on this graph
+    assert_same(gpu_mine(g, 86400, 4, 2, patterns=UNORD), ref, "unordered mid")
+    assert_same(gpu_mine(g, 86400, 4, 2, patterns=A.AMLM_SG | A.AMLM_SG_UNORDERED), ref[[2]], "unordered SG only")
+    with pytest.raises(A.AmlmError) as ei:  # the modifier without SG
+        G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+        try:
+            A.amlm_mine(G, A.params(A.AMLM_GS | A.AMLM_SG_UNORDERED, 86400, 4, 2),
+                        counts=torch.zeros((1, g.n_edges), dtype=torch.int32, device="cuda"))
+        finally:
+            G.close()
+    assert ei.value.status == 1
+
+
+def test_unordered_sg_learned_slices():
+    """Sliced heavy anchors under the modifier: partial counts added by the
+    slices equal the oracle's."""
+    g = _heavy_sender_graph(41)
+    ref = oracle_mine(g, 2000, 5, 3, patterns=UNORD_O)
+    assert ref[2].max() > 0
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    A.amlm_costmodel_train([G], [A.params(A.AMLM_ALL, 2000, 5, 3)], epochs=2, batch=256, seed=41)
+    for split in (64, 0):
+        A.amlm_tune_set(G, split_bytes=split)
+        c = A.amlm_mine(G, A.params(UNORD, 2000, 5, 3, A.AMLM_SCHED_LEARNED))
+        A.amlm_graph_sync(G)
+        assert_same(A.to_u32(c), ref, f"unordered learned, split {split}")
+    G.close()
+
+
 def test_deterministic_repeat():
     g = W.mid(204, scale=0.01)
     a = gpu_mine(g, 86400, 6, 2)
@@ -202,13 +252,13 @@ def mid_full():
     return W.mid(202)
 
 
-def _sampled(g, counts, delta, L, k, n_sample=400, seed=0):
+def _sampled(g, counts, delta, L, k, n_sample=400, seed=0, patterns=oracle.ALL):
     rng = np.random.default_rng(seed)
     sel = rng.choice(g.n_edges, n_sample, replace=False)
     # add the heaviest anchors by fan-in / fan-out too
     sel = np.unique(np.concatenate([sel, np.argsort(counts[0])[-20:], np.argsort(counts[1])[-20:],
                                     np.argsort(counts[2])[-20:], np.nonzero(counts[4:].sum(axis=0))[0][:50]]))
-    ref = oracle.mine_selected(g.src, g.dst, g.ts, g.n_vertices, sel, oracle.ALL, delta, L, k)
+    ref = oracle.mine_selected(g.src, g.dst, g.ts, g.n_vertices, sel, patterns, delta, L, k)
     assert_same(counts[:, sel], ref, "sampled")
     return sel
 
@@ -221,6 +271,18 @@ def test_mid_full_size_sampled(mid_full):
     cf = oracle.count_cycles_first(g.src, g.dst, g.ts, g.n_vertices, 86400, 6)
     for l in range(2, 7):
         assert int(c[4 + l - 2].astype(np.uint64).sum()) == l * int(cf[l])
+
+
+def test_unordered_sg_mid_full_size_sampled(mid_full):
+    """The unordered modifier on the whole 5M-edge graph: sampled edges
+    against the oracle; on every edge SG can only grow and the other columns
+    equal the ordered mining's."""
+    g = mid_full
+    c = gpu_mine(g, 86400, 6, 2, patterns=UNORD)
+    _sampled(g, c, 86400, 6, 2, patterns=UNORD_O, seed=5)
+    o = gpu_mine(g, 86400, 6, 2)
+    assert (c[2] >= o[2]).all() and (c[2] > o[2]).any()
+    np.testing.assert_array_equal(np.delete(c, 2, axis=0), np.delete(o, 2, axis=0))
 
 
 @pytest.fixture(scope="module")
@@ -243,3 +305,8 @@ def test_large_full_size_sampled_learned_schedule(large_full):
     static = gpu_mine(g, 86400, 6, 2, schedule=A.AMLM_SCHED_STATIC, on_device=True)
     np.testing.assert_array_equal(learned, static)
     _sampled(g, learned, 86400, 6, 2, n_sample=300, seed=3)
+    # the unordered scatter-gather modifier in the same configuration
+    lu = gpu_mine(g, 86400, 6, 2, patterns=UNORD, schedule=A.AMLM_SCHED_LEARNED, on_device=True)
+    assert (lu[2] >= learned[2]).all()
+    np.testing.assert_array_equal(np.delete(lu, 2, axis=0), np.delete(learned, 2, axis=0))
+    _sampled(g, lu, 86400, 6, 2, n_sample=150, seed=4, patterns=UNORD_O)
