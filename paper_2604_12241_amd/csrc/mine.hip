@@ -237,10 +237,11 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
     if (q > vrs) {
       uint64_t kk = g.inn_key[q - 1];  // the last m -> v edge at or before t, if any
       const int32_t tb = (int32_t)(uint32_t)kk;
-      // ordered: after this s -> m edge, the pair's first in the window;
-      // unordered: anywhere in the window
-      const bool timed = mp.sg_unordered ? tb >= lo : tb > g.out_t[pos];
-      if ((uint32_t)(kk >> 32) == m && g.out_prv[pos] < lo && timed) atomicAdd(&L.pr_cnt[a], 1u);
+      // the pair's first s -> m edge in the window; then the gather leg:
+      // after it (ordered) or anywhere in the window (unordered).  The
+      // short-circuit order keeps the time loads off the false positives.
+      if ((uint32_t)(kk >> 32) == m && g.out_prv[pos] < lo && (mp.sg_unordered ? tb >= lo : tb > g.out_t[pos]))
+        atomicAdd(&L.pr_cnt[a], 1u);
     }
   }
 }
