@@ -193,18 +193,23 @@ def _read_golden(name):
 def test_t720_scatter_gather_orderings():
     gold = _read_golden("t720.txt")
     edges = [(0, 1), (0, 2), (0, 3), (1, 4), (2, 4), (3, 4)]   # s=0, m=1..3, d=4
-    hits, total = 0, 0
+    hits, hits_u, total = 0, 0, 0
     for perm in itertools.permutations(range(6)):
         total += 1
         src = np.array([a for a, _ in edges], dtype=np.uint32)
         dst = np.array([b for _, b in edges], dtype=np.uint32)
         ts = T0 + np.array(perm, dtype=np.int64)
-        o = mine(src, dst, ts, 5, 100, 2, 3, oracle.SG)
         latest_gather = 3 + int(np.argmax(ts[3:]))
-        hits += int(o[0, latest_gather])
-        assert o[0].sum() == o[0, latest_gather]
+        for pats in (oracle.SG, oracle.SG | oracle.SG_UNORDERED):
+            o = mine(src, dst, ts, 5, 100, 2, 3, pats)
+            assert o[0].sum() == o[0, latest_gather]
+            if pats == oracle.SG:
+                hits += int(o[0, latest_gather])
+            else:
+                hits_u += int(o[0, latest_gather])
     assert total == gold["orderings"]
     assert hits == gold["per_intermediate_instances"]
+    assert hits_u == gold["unordered_instances"]
 
 
 # ---------------------------------------------------------------- invariants
