@@ -68,6 +68,31 @@ def test_incremental_equals_full_recompute_and_alone_equals_mix():
     R.close()
 
 
+def test_incremental_unordered_sg_equals_full_recompute():
+    """The unordered scatter-gather modifier through the server's window
+    graphs: resident counts + new rows + deltas equal the oracle's mining of
+    the union graph."""
+    base, batches = _setup()
+    pats = A.AMLM_ALL | A.AMLM_SG_UNORDERED
+    p = A.params(pats, D, L, K)
+    R = A.Graph(base.src, base.dst, base.ts, base.n_vertices)
+    r_counts = A.to_u32(A.amlm_mine(R, p)).astype(np.uint64)
+    mix = _run(A.Server(R, p, max_slots=4), batches, sequential=False)
+    src = np.concatenate([base.src] + [b.src for b in batches])
+    dst = np.concatenate([base.dst] + [b.dst for b in batches])
+    ts = np.concatenate([base.ts] + [b.ts for b in batches])
+    acc = np.zeros((r_counts.shape[0], src.shape[0]), np.uint64)
+    acc[:, :base.n_edges] = r_counts
+    pos = base.n_edges
+    for (c, (de, dc, dv), _), b in zip(mix, batches):
+        acc[:, pos:pos + b.n_edges] += c
+        np.add.at(acc, (dc.astype(np.int64), de.astype(np.int64)), dv)
+        pos += b.n_edges
+    full = oracle.mine(src, dst, ts, base.n_vertices, oracle.ALL | oracle.SG_UNORDERED, D, L, K)
+    np.testing.assert_array_equal(acc, full.astype(np.uint64))
+    R.close()
+
+
 def test_stream_errors():
     base, batches = _setup()
     p = A.params(A.AMLM_ALL, D, L, K)
