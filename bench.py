@@ -29,18 +29,30 @@ WORKLOADS = {
 }
 
 
+MINING_SOURCES = ("mine.hip", "mine.h", "common.h", "internal.h")
+
+
+def mining_source_sha1():
+    """sha1 (12 hex digits) over the sources the mining kernels are built
+    from, in the order of MINING_SOURCES."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in MINING_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_12241_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
 def recorded_traffic(kernel):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3
-    summary, or None if the mining source changed since it was taken."""
-    import hashlib
+    summary, or None if the mining sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic_large32M.json")
-    src = os.path.join(ROOT, "paper_2604_12241_amd", "csrc", "mine.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+        sha = mining_source_sha1()
     except (OSError, ValueError):
         return None
-    if rec.get("mine_hip_sha1") != sha:
+    if rec.get("mining_sources_sha1") != sha:
         return None
     return rec.get("traffic_bytes_per_dispatch", {}).get(kernel)
 

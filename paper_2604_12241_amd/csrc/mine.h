@@ -20,7 +20,7 @@ constexpr int kSgThreads = 64;   // one wave per block
 #define AMLM_BLOOM_LOG2_MAX 15
 #endif
 #ifndef AMLM_BLOOM_BITS_PER_ENTRY
-#define AMLM_BLOOM_BITS_PER_ENTRY 32
+#define AMLM_BLOOM_BITS_PER_ENTRY 128
 #endif
 #ifndef AMLM_BLOOM_K
 #define AMLM_BLOOM_K 4
@@ -33,7 +33,10 @@ constexpr int kSgThreads = 64;   // one wave per block
 #endif
 constexpr int kBloomLog2Max = AMLM_BLOOM_LOG2_MAX;      // 32 Kbit (4 KB) filter: occupancy beats a lower false-positive rate
 constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
-constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;  // filter bits per gathered entry
+// filter bits per gathered entry, up to the maximum size: 128 gives short
+// segments a sparse filter (fewer false positives to verify); 32 and 64 were
+// slower, 256 and more no faster
+constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;
 constexpr int kBloomK = AMLM_BLOOM_K;                   // bits set per key, all in one 32-bit word
 constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
