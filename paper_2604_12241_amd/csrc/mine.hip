@@ -601,8 +601,9 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       L.i_work[lane] = first_slice ? kBytesAnchorSg : 0u;
     }
     // segments: runs of anchors into the same v inside one time bucket of
-    // width delta / 4, so that a segment's gather window stays short
-    const int32_t seg_span = (int32_t)max((int64_t)1, min(dl / 4, (int64_t)0x40000000));
+    // width 2 delta share one filter; narrower buckets (delta / 4 .. delta)
+    // rebuilt it more often than its shorter gather window saved
+    const int32_t seg_span = (int32_t)max((int64_t)1, min(2 * dl, (int64_t)0x40000000));
     int32_t tb = lane < nr ? L.i_t[lane] / seg_span : 0;
     uint32_t vprev = __shfl_up(v, 1, AMLM_WAVE);
     int32_t tbprev = __shfl_up(tb, 1, AMLM_WAVE);
