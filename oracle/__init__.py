@@ -45,6 +45,8 @@ def _load():
         lib.oracle_mine.restype = ctypes.c_int
         lib.oracle_mine_range.argtypes = [u64, u32, p, p, p, u32, i64, u32, u32, u64, u64, p, p]
         lib.oracle_mine_range.restype = ctypes.c_int
+        lib.oracle_mine_ex.argtypes = [u64, u32, p, p, p, u32, i64, u32, u32, u64, u64, u32, p, p, p]
+        lib.oracle_mine_ex.restype = ctypes.c_int
         lib.oracle_mine_selected.argtypes = [u64, u32, p, p, p, u32, i64, u32, u32, p, u64, p]
         lib.oracle_mine_selected.restype = ctypes.c_int
         lib.oracle_count_cycles_first.argtypes = [u64, u32, p, p, p, i64, u32, p]
@@ -94,6 +96,26 @@ def mine_range(src, dst, ts, n_vertices: int, a_lo: int, a_hi: int, patterns: in
     _check(lib.oracle_mine_range(n, n_vertices, src.ctypes.data, dst.ctypes.data, ts.ctypes.data,
                                  patterns, delta, L, k, a_lo, a_hi, out.ctypes.data, ctypes.byref(sec)))
     return out, sec.value
+
+
+def mine_ex(src, dst, ts, n_vertices: int, patterns: int = ALL, delta: int = 86400, L: int = 4,
+            k: int = 2, a_lo: int = 0, a_hi: int | None = None, ceiling: int = 0, work: bool = False):
+    """Anchors restricted to edge ids [a_lo, a_hi) (default: all), counts
+    saturating at ``ceiling`` (0 = 2^32 - 1).  Returns (counts uint32
+    [ncols, n], work uint64 [3, n] or None, seconds): work rows are the
+    algorithmic bytes B_io, B_sg/gs, B_cyc of each anchor."""
+    lib = _load()
+    src, dst, ts = _arrays(src, dst, ts)
+    n = src.shape[0]
+    if a_hi is None:
+        a_hi = n
+    out = np.zeros((num_columns(patterns, L), n), dtype=np.uint32)
+    wk = np.zeros((3, n), dtype=np.uint64) if work else None
+    sec = ctypes.c_double()
+    _check(lib.oracle_mine_ex(n, n_vertices, src.ctypes.data, dst.ctypes.data, ts.ctypes.data, patterns,
+                              delta, L, k, a_lo, a_hi, ceiling, out.ctypes.data,
+                              wk.ctypes.data if work else None, ctypes.byref(sec)))
+    return out, wk, sec.value
 
 
 def mine_selected(src, dst, ts, n_vertices: int, sel, patterns: int = ALL, delta: int = 86400,

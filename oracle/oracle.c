@@ -40,7 +40,33 @@
  * Stage outputs are vertex sets (Algorithm 1: the output of a stage is nodes,
  * not edges), so S, M and D count distinct vertices; FAN counts edges; cycles
  * are edge sets, so parallel edges give distinct cycles.  Every count is
- * accumulated in 64 bits and clamped to 2^32 - 1 on output.
+ * accumulated in 64 bits and saturates on output at a ceiling (2^32 - 1
+ * unless the caller lowers it, which lets small graphs reach it).
+ *
+ * Algorithmic bytes (optional output, one 64-bit counter per anchor and
+ * stage) follow a canonical procedure of the method: what an exact miner
+ * must read and write for each anchor e = (u -> v, t) when nothing is reused
+ * across anchors, an element being a neighbour id plus a time (8 bytes):
+ *   B_io(e)    = 12 (src, dst, ts of the edge) + 4 per output column
+ *   B_sg/gs(e) = 8 |IN(u) in [t-delta, t)|                    (sender scan)
+ *              + 8 sum over s in S(e) of min(n_s, |IN(v) in [t-delta, t]|)
+ *                n_s: elements of s's out-slice [t-delta, t) scanned in time
+ *                order until k-1 intermediates other than u have qualified
+ *                (all of them if fewer do): the set intersection of the
+ *                compiled scatter-gather example, bounded by the smaller
+ *                side as in Section 6's degree-ordered intersection and
+ *                ended early as in Algorithm 1's break conditions
+ *              + 8 (elements of OUT(u) in (tau, t] scanned until k distinct
+ *                destinations are seen), only when GS is asked for and
+ *                |S(e)| >= k
+ *   B_cyc(e)   = 12 |OUT(h) in interval| for each partial path of depth
+ *                0 .. L-3 (depth 0: head v, interval [t-delta, t); deeper:
+ *                (time of the last path edge, t)), + 8 ceil(log2 indeg(u))
+ *                for each partial path of depth L-2 whose head has an
+ *                out-edge in its interval (the closing edge found by binary
+ *                search, Section 6's 4-cycle example), + 8 l for every
+ *                l-cycle found (its credits)
+ * Only SG / GS and CYC stages that are asked for are charged.
  *
  * Columns, in this order, for the requested patterns only:
  *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.   Layout [ncols][n_edges].
@@ -136,7 +162,8 @@ static uint64_t upper_ts(const og_graph *g, const uint64_t *row, uint64_t b, uin
     return b;
 }
 
-static uint32_t clamp32(uint64_t x) { return x > 0xffffffffull ? 0xffffffffu : (uint32_t)x; }
+/* saturation at the ceiling (2^32 - 1 by default) */
+static uint32_t sat(uint64_t x, uint32_t ceiling) { return x > ceiling ? ceiling : (uint32_t)x; }
 
 uint32_t oracle_num_columns(uint32_t patterns, uint32_t L) {
     uint32_t c = 0;
@@ -168,12 +195,15 @@ static void scratch_free(og_scratch *s) {
     free(s->stamp_s); free(s->stamp_b); free(s->stamp_m); free(s->stamp_d); free(s->maxb); free(s->slist);
 }
 
-/* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k (written to out4). */
+/* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k (written to out4).
+ * want_sg / want_gs: which of the scatter-gather columns are asked for (they
+ * only decide what *work is charged).  work (may be NULL) receives B_sg/gs. */
 static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k, int unordered,
-                     uint64_t out4[4]) {
+                     int want_sg, int want_gs, uint64_t out4[4], uint64_t *work) {
     uint32_t u = g->src[e], v = g->dst[e];
     int64_t t = g->ts[e], lo = t - delta;
     out4[0] = out4[1] = out4[2] = out4[3] = 0;
+    if (work) *work = 0;
     if (u == v) return;
 
     /* FAN: sizes of the window slices (rows are sorted by timestamp) */
@@ -195,6 +225,8 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
         if (!have_tau) { have_tau = 1; tau = g->ts[a]; } /* rows are time-sorted */
         if (sc->stamp_s[s] != cs) { sc->stamp_s[s] = cs; sc->slist[nS++] = s; }
     }
+    uint64_t w = 0;
+    if (want_sg || want_gs) w += 8 * (p1 - p0);
 
     /* SG_k: latest gather time into v per in-neighbour m, over [lo, t] */
     uint64_t cb = ++sc->clock;
@@ -205,12 +237,16 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
         if (sc->stamp_b[m] != cb) { sc->stamp_b[m] = cb; sc->maxb[m] = g->ts[b]; }
         else if (g->ts[b] > sc->maxb[m]) sc->maxb[m] = g->ts[b];
     }
+    const uint64_t r_gather = q1 - q0; /* |IN(v) in [lo, t]| */
     uint64_t sg = 0;
     for (uint64_t i = 0; i < nS; i++) {
         uint32_t s = (uint32_t)sc->slist[i];
         uint64_t cm = ++sc->clock, nm = 0;
         uint64_t sb = g->out_ptr[s], se = g->out_ptr[s + 1];
         uint64_t r0 = lower_ts(g, g->out_e, sb, se, lo), r1 = lower_ts(g, g->out_e, sb, se, t);
+        /* canonical scan length: elements up to the (k-1)-th qualifying
+           intermediate other than u, or the whole slice */
+        uint64_t n_s = k >= 2 ? r1 - r0 : 0, found = 0;
         for (uint64_t p = r0; p < r1; p++) {
             uint64_t a = g->out_e[p];
             uint32_t m = g->dst[a];
@@ -218,9 +254,11 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
             if (sc->stamp_b[m] == cb && (unordered || g->ts[a] < sc->maxb[m]) && sc->stamp_m[m] != cm) {
                 sc->stamp_m[m] = cm;
                 nm++;
+                if (m != u && k >= 2 && ++found == k - 1) n_s = p - r0 + 1;
             }
         }
         if (nm >= k) sg++;
+        if (want_sg) w += 8 * (n_s < r_gather ? n_s : r_gather);
     }
     out4[2] = sg;
 
@@ -228,12 +266,18 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
     if (nS >= k && have_tau) {
         uint64_t cd = ++sc->clock, nd = 0;
         uint64_t d0 = upper_ts(g, g->out_e, ob, oe, tau), d1 = upper_ts(g, g->out_e, ob, oe, t);
+        uint64_t scanned = d1 - d0;
         for (uint64_t p = d0; p < d1; p++) {
             uint32_t d = g->dst[g->out_e[p]];
-            if (sc->stamp_d[d] != cd) { sc->stamp_d[d] = cd; nd++; }
+            if (sc->stamp_d[d] != cd) {
+                sc->stamp_d[d] = cd;
+                if (++nd == k && scanned == d1 - d0) scanned = p - d0 + 1;
+            }
         }
         if (nd >= k) out4[3] = nS;
+        if (want_gs) w += 8 * scanned;
     }
+    if (work) *work = w;
 }
 
 /* ---- cycles anchored on their last edge, credited to every member edge ---- */
@@ -244,8 +288,16 @@ typedef struct {
     uint64_t anchor;
     uint64_t path_e[16];
     uint32_t path_v[16];
-    uint64_t *acc; /* [L-1][n] accumulators, column l-2 */
+    uint64_t *acc;      /* [L-1][n] accumulators, column l-2 */
+    uint64_t work;      /* B_cyc of the current anchor */
+    uint64_t close_b;   /* bytes of one closing search: 8 ceil(log2 indeg(u)) */
 } cyc_ctx;
+
+static uint64_t ceil_log2(uint64_t x) {
+    uint64_t c = 0;
+    while (((uint64_t)1 << c) < x) c++;
+    return c;
+}
 
 static void cyc_dfs(cyc_ctx *c, uint32_t h, uint32_t d, int64_t tlast) {
     const og_graph *g = c->g;
@@ -253,6 +305,10 @@ static void cyc_dfs(cyc_ctx *c, uint32_t h, uint32_t d, int64_t tlast) {
     /* first hop: [lo, t); later hops: (tlast, t) */
     uint64_t p0 = d == 0 ? lower_ts(g, g->out_e, rb, re, c->lo) : upper_ts(g, g->out_e, rb, re, tlast);
     uint64_t p1 = lower_ts(g, g->out_e, rb, re, c->t);
+    /* canonical bytes: scan the slice at depths 0 .. L-3, one closing search
+       at depth L-2 (the loop below still walks it, to count the cycles) */
+    if (d + 3 <= c->L) c->work += 12 * (p1 - p0);
+    else if (p1 > p0) c->work += c->close_b;
     for (uint64_t p = p0; p < p1; p++) {
         uint64_t j = g->out_e[p];
         uint32_t w = g->dst[j];
@@ -262,6 +318,7 @@ static void cyc_dfs(cyc_ctx *c, uint32_t h, uint32_t d, int64_t tlast) {
             for (uint32_t q = 0; q < d; q++) col[c->path_e[q]]++;
             col[j]++;
             col[c->anchor]++;
+            c->work += 8 * (uint64_t)l;
         } else if (d + 1 <= c->L - 2) {
             int seen = 0;
             for (uint32_t q = 0; q <= d; q++)
@@ -293,16 +350,20 @@ static double now_s(void) {
  * Mining with the anchors restricted to edge ids [a_lo, a_hi): the anchored
  * columns of those edges, and every cycle whose LAST edge is one of them,
  * credited to all of its edges.  Over disjoint ranges the results add up to
- * the full mining.  counts: [ncols][n] uint32 (caller-owned).  seconds, if not
- * NULL, receives the wall time of the anchor loops (graph set-up excluded).
- * Returns 0 on success, 1 on an out-of-range vertex id, 2 on allocation
- * failure, 3 on invalid parameters.
+ * the full mining.  counts: [ncols][n] uint32 (caller-owned); every count
+ * saturates at `ceiling` (0 means 2^32 - 1).  work (may be NULL): [3][n]
+ * uint64, the algorithmic bytes B_io, B_sg/gs and B_cyc of each anchor in
+ * the range (zero elsewhere).  seconds, if not NULL, receives the wall time
+ * of the anchor loops (graph set-up excluded).  Returns 0 on success, 1 on
+ * an out-of-range vertex id, 2 on allocation failure, 3 on invalid
+ * parameters.
  */
-int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
-                      uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint64_t a_lo, uint64_t a_hi,
-                      uint32_t *counts, double *seconds) {
+int oracle_mine_ex(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                   uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint64_t a_lo, uint64_t a_hi,
+                   uint32_t ceiling, uint32_t *counts, uint64_t *work, double *seconds) {
     int rc = check_params(patterns, delta, L, k);
     if (rc) return rc;
+    if (ceiling == 0) ceiling = 0xffffffffu;
     if (a_hi > n) a_hi = n;
     if (a_lo > a_hi) a_lo = a_hi;
     og_graph g;
@@ -311,6 +372,7 @@ int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32
     if ((rc = scratch_init(&sc, nv))) return rc;
     uint32_t ncols = oracle_num_columns(patterns, L);
     memset(counts, 0, sizeof(uint32_t) * (size_t)ncols * n);
+    if (work) memset(work, 0, sizeof(uint64_t) * 3 * (size_t)n);
     uint32_t col = 0;
     int c_fo = -1, c_fi = -1, c_sg = -1, c_gs = -1, c_cy = -1;
     if (patterns & OR_FAN_OUT) c_fo = col++;
@@ -324,14 +386,17 @@ int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32
         if (!acc) { og_free(&g); scratch_free(&sc); return 2; }
     }
     double t0 = now_s();
+    if (work)
+        for (uint64_t e = a_lo; e < a_hi; e++) work[e] = 12 + 4 * (uint64_t)ncols;
     if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS)) {
         for (uint64_t e = a_lo; e < a_hi; e++) {
             uint64_t r[4];
-            anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, r);
-            if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = clamp32(r[0]);
-            if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = clamp32(r[1]);
-            if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = clamp32(r[2]);
-            if (c_gs >= 0) counts[(uint64_t)c_gs * n + e] = clamp32(r[3]);
+            anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, (patterns & OR_SG) != 0,
+                     (patterns & OR_GS) != 0, r, work ? work + n + e : NULL);
+            if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = sat(r[0], ceiling);
+            if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = sat(r[1], ceiling);
+            if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = sat(r[2], ceiling);
+            if (c_gs >= 0) counts[(uint64_t)c_gs * n + e] = sat(r[3], ceiling);
         }
     }
     if (c_cy >= 0) {
@@ -342,14 +407,17 @@ int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32
             if (src[e] == dst[e]) continue;
             c.u = src[e]; c.t = ts[e]; c.lo = ts[e] - delta; c.anchor = e;
             c.path_v[0] = dst[e];
+            c.work = 0;
+            c.close_b = 8 * ceil_log2(g.in_ptr[src[e] + 1] - g.in_ptr[src[e]]);
             cyc_dfs(&c, dst[e], 0, 0);
+            if (work) work[2 * n + e] = c.work;
         }
     }
     double t1 = now_s();
     if (c_cy >= 0) {
         for (uint32_t l = 0; l + 1 < L; l++)
             for (uint64_t e = 0; e < n; e++)
-                counts[(uint64_t)(c_cy + l) * n + e] = clamp32(acc[(uint64_t)l * n + e]);
+                counts[(uint64_t)(c_cy + l) * n + e] = sat(acc[(uint64_t)l * n + e], ceiling);
         free(acc);
     }
     if (seconds) *seconds = t1 - t0;
@@ -358,7 +426,14 @@ int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32
     return 0;
 }
 
-/* Full mining of every edge (see oracle_mine_range). */
+/* oracle_mine_ex at the default ceiling, without work counters */
+int oracle_mine_range(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
+                      uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint64_t a_lo, uint64_t a_hi,
+                      uint32_t *counts, double *seconds) {
+    return oracle_mine_ex(n, nv, src, dst, ts, patterns, delta, L, k, a_lo, a_hi, 0, counts, NULL, seconds);
+}
+
+/* Full mining of every edge (see oracle_mine_ex). */
 int oracle_mine(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
                 uint32_t patterns, int64_t delta, uint32_t L, uint32_t k, uint32_t *counts) {
     return oracle_mine_range(n, nv, src, dst, ts, patterns, delta, L, k, 0, n, counts, NULL);
@@ -443,18 +518,18 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
         if (e >= n) { og_free(&g); scratch_free(&sc); return 3; }
         uint32_t col = 0;
         uint64_t r[4];
-        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, r);
-        if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[0]);
-        if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[1]);
-        if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[2]);
-        if (patterns & OR_GS) out[(uint64_t)(col++) * n_sel + i] = clamp32(r[3]);
+        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, r, NULL);
+        if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = sat(r[0], 0xffffffffu);
+        if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = sat(r[1], 0xffffffffu);
+        if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = sat(r[2], 0xffffffffu);
+        if (patterns & OR_GS) out[(uint64_t)(col++) * n_sel + i] = sat(r[3], 0xffffffffu);
         if ((patterns & OR_CYC) && src[e] != dst[e]) {
             thr_ctx c;
             memset(&c, 0, sizeof(c));
             c.g = &g; c.e = e; c.t = ts[e]; c.delta = delta; c.u = src[e]; c.L = L;
             c.path_v[0] = dst[e];
             thr_dfs(&c, dst[e], 0, 0, ts[e], ts[e], ts[e]);
-            for (uint32_t l = 2; l <= L; l++) out[(uint64_t)(col + l - 2) * n_sel + i] = clamp32(c.cnt[l]);
+            for (uint32_t l = 2; l <= L; l++) out[(uint64_t)(col + l - 2) * n_sel + i] = sat(c.cnt[l], 0xffffffffu);
         }
     }
     og_free(&g);

@@ -70,3 +70,95 @@ def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = 
     for c1 in E:
         extend([c1])
     return out
+
+
+def brute_work(src, dst, ts, delta: int, L: int, k: int, want_sg=True, want_gs=True, want_cyc=True,
+               ncols: int | None = None, sg_unordered: bool = False) -> np.ndarray:
+    """Algorithmic bytes of each anchor under the canonical procedure of the
+    method (uint64 [3, n]: B_io, B_sg/gs, B_cyc), restated literally with
+    Python loops and sorted lists.  Rows and slices are ordered by (ts, edge
+    id); an element is 8 bytes (12 in the cycle scan)."""
+    src = [int(x) for x in src]
+    dst = [int(x) for x in dst]
+    ts = [int(x) for x in ts]
+    n = len(src)
+    if ncols is None:
+        ncols = 4 + L - 1
+    E = [i for i in range(n) if src[i] != dst[i]]
+    out = np.zeros((3, n), dtype=np.uint64)
+    out[0, :] = 12 + 4 * ncols
+
+    def slice_of(pred):
+        return sorted((f for f in E if pred(f)), key=lambda f: (ts[f], f))
+
+    def ceil_log2(x):
+        c = 0
+        while (1 << c) < x:
+            c += 1
+        return c
+
+    for e in E:
+        u, v, t = src[e], dst[e], ts[e]
+        lo = t - delta
+        if want_sg or want_gs:
+            w = 0
+            sender = slice_of(lambda a: dst[a] == u and lo <= ts[a] < t)
+            w += 8 * len(sender)
+            S = {src[a] for a in sender if src[a] != v}
+            r = len([b for b in E if dst[b] == v and lo <= ts[b] <= t])
+            if want_sg:
+                for s in S:
+                    sl = slice_of(lambda a: src[a] == s and lo <= ts[a] < t)
+                    if k < 2:
+                        n_s = 0
+                    else:
+                        n_s = len(sl)
+                        seen, found = set(), 0
+                        for idx, a in enumerate(sl):
+                            m = dst[a]
+                            if m == u or m in seen:
+                                continue
+                            ok = any(src[b] == m and dst[b] == v and ts[b] <= t
+                                     and (lo <= ts[b] if sg_unordered else ts[a] < ts[b]) for b in E)
+                            if ok:
+                                seen.add(m)
+                                found += 1
+                                if found == k - 1:
+                                    n_s = idx + 1
+                                    break
+                    w += 8 * min(n_s, r)
+            if want_gs and len(S) >= k:
+                tau = min(ts[a] for a in sender if src[a] != v)
+                sc = slice_of(lambda b: src[b] == u and tau < ts[b] <= t)
+                scanned, seen = len(sc), set()
+                for idx, b in enumerate(sc):
+                    if dst[b] not in seen:
+                        seen.add(dst[b])
+                        if len(seen) == k:
+                            scanned = idx + 1
+                            break
+                w += 8 * scanned
+            out[1, e] = w
+        if want_cyc:
+            indeg_u = len([f for f in E if dst[f] == u])
+            acc = [0]
+
+            def visit(h, d, tlast, on_path):
+                if d == 0:
+                    sl = slice_of(lambda f: src[f] == h and lo <= ts[f] < t)
+                else:
+                    sl = slice_of(lambda f: src[f] == h and tlast < ts[f] < t)
+                if d <= L - 3:
+                    acc[0] += 12 * len(sl)
+                elif sl:
+                    acc[0] += 8 * ceil_log2(indeg_u)
+                for f in sl:
+                    x = dst[f]
+                    if x == u:
+                        acc[0] += 8 * (d + 2)
+                    elif d + 1 <= L - 2 and x not in on_path:
+                        visit(x, d + 1, ts[f], on_path | {x})
+
+            visit(v, 0, None, {v})
+            out[2, e] = acc[0]
+    return out

@@ -351,3 +351,92 @@ def test_anchor_ranges_add_up(mid_small):
         acc += part
         assert sec >= 0
     np.testing.assert_array_equal(acc, full)
+
+
+# ---------------------------------------------------------------- algorithmic bytes
+
+from tests.brute import brute_work  # noqa: E402
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_work_counters_match_brute_force(seed):
+    """The oracle's per-anchor algorithmic bytes against a literal Python
+    restatement of the canonical procedure, for several pattern subsets."""
+    rng = np.random.default_rng(4000 + seed)
+    g = W.random_small(900 + seed, n_edges=int(rng.integers(20, 120)), n_vertices=int(rng.integers(3, 12)),
+                       t_range=int(rng.integers(5, 50)))
+    delta, L, k = int(rng.integers(0, 40)), int(rng.integers(2, 7)), int(rng.integers(1, 4))
+    cases = [(oracle.ALL, (True, True, True)), (oracle.SG | oracle.FAN_OUT, (True, False, False)),
+             (oracle.GS | oracle.CYC, (False, True, True)), (oracle.ALL | oracle.SG_UNORDERED, (True, True, True))]
+    for pats, (s_, g_, c_) in cases:
+        c, w, _ = oracle.mine_ex(g.src, g.dst, g.ts, g.n_vertices, pats, delta, L, k, work=True)
+        b = brute_work(g.src, g.dst, g.ts, delta, L, k, s_, g_, c_, ncols=c.shape[0],
+                       sg_unordered=bool(pats & oracle.SG_UNORDERED))
+        np.testing.assert_array_equal(w, b)
+
+
+def test_work_counters_closed_forms():
+    """Hand-computed bytes on isolated motifs (times T0 + 60 j, one window)."""
+    L = 6
+    io = 12 + 4 * (4 + L - 1)
+    # fan-out: no sender into u, v has no out-edge: only the row's own bytes
+    s, d, t, nv = _motif_graph(*W.motif_fan_out(5))
+    _, w, _ = oracle.mine_ex(s, d, t, nv, oracle.ALL, 86400, L, 2, work=True)
+    np.testing.assert_array_equal(w[0], io)
+    assert w[1:].sum() == 0
+    # scatter-gather with K intermediates, anchor = gather leg g_j: one sender
+    # edge (8) and one sender s whose scan stops at the (k-1)-th qualifying m_i
+    # (i < j) or, with fewer, covers the gather window of j entries
+    K = 6
+    s, d, t, nv = _motif_graph(*W.motif_scatter_gather(K))
+    for k in (2, 3, 4):
+        _, w, _ = oracle.mine_ex(s, d, t, nv, oracle.SG, 86400, L, k, work=True)
+        j = np.arange(1, K + 1)
+        np.testing.assert_array_equal(w[1, K:], 8 + 8 * np.minimum(j, k - 1))
+        np.testing.assert_array_equal(w[1, :K], 0)
+    # with GS and k = 1: no join, and the scatter scan stops at u's first
+    # destination after tau (the gather leg itself)
+    _, w, _ = oracle.mine_ex(s, d, t, nv, oracle.GS, 86400, L, 1, work=True)
+    np.testing.assert_array_equal(w[1, K:], 16)
+    # l-cycle anchored on its last edge: one element per depth, scanned at
+    # depths 0 .. L-3, a closing search at depth L-2 (u has 1 + x in-edges:
+    # 8 ceil(log2(1 + x)) bytes), and 8 l for the cycle
+    for l in (2, 3, 4, 5, 6):
+        edges, nvl = W.motif_cycle(l)
+        for extra in (0, 3):
+            # extra in-edges of u = l - 1 from fresh accounts, long before the window
+            ee = [(nvl + q, l - 1, -100000 - q) for q in range(extra)] + edges
+            s, d, t, nv = _motif_graph(ee, nvl + extra)
+            _, w, _ = oracle.mine_ex(s, d, t, nv, oracle.CYC, 86400, L, 2, work=True)
+            last = len(ee) - 1
+            if l <= L - 1:
+                want = 12 * (l - 1) + 8 * l
+            else:
+                want = 12 * (L - 2) + 8 * int(np.ceil(np.log2(1 + extra))) + 8 * L
+            assert int(w[2, last]) == want, (l, extra)
+            assert w[2, :last].sum() == 0
+
+
+@pytest.mark.parametrize("l,m", [(3, 4), (4, 3), (5, 2)])
+def test_saturation_ceiling_closed_form(l, m):
+    """An l-cycle whose edges are each repeated m times (copies share their
+    time): every copy lies on m^(l-1) cycles and sees m out-edges of its
+    source.  Counts saturate at the ceiling."""
+    edges, nv = W.motif_cycle(l)
+    rep = [e for e in edges for _ in range(m)]
+    s, d, t, nv = _motif_graph(rep, nv)
+    full, _, _ = oracle.mine_ex(s, d, t, nv, oracle.FAN_OUT | oracle.CYC, 86400, l, 1)
+    np.testing.assert_array_equal(full[0], m)
+    np.testing.assert_array_equal(full[1 + l - 2], m ** (l - 1))
+    for ceiling in (1, m, m ** (l - 1) - 1, m ** (l - 1), 2 ** 32 - 1):
+        c, _, _ = oracle.mine_ex(s, d, t, nv, oracle.FAN_OUT | oracle.CYC, 86400, l, 1, ceiling=ceiling)
+        np.testing.assert_array_equal(c[0], min(m, ceiling))
+        np.testing.assert_array_equal(c[1 + l - 2], min(m ** (l - 1), ceiling))
+
+
+def test_saturation_is_elementwise_min(mid_small):
+    g = mid_small
+    full, _, _ = oracle.mine_ex(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL, 86400, 5, 2)
+    for ceiling in (1, 3, 17):
+        c, _, _ = oracle.mine_ex(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL, 86400, 5, 2, ceiling=ceiling)
+        np.testing.assert_array_equal(c, np.minimum(full, ceiling))
