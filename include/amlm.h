@@ -7,12 +7,12 @@
  * patterns of the paper's multi-stage framework (Section 5): windowed
  * fan-out / fan-in, scatter-gather through at least k intermediates,
  * gather-scatter, and time-respecting cycles of length 2..L inside a window
- * delta.  The counts are the per-transaction features of Section 8 ("the
- * number of instances of each pattern the transaction participates in").
+ * delta.  The counts are the per-transaction features of Section 8 (Table 2:
+ * for each transaction, how many instances of each pattern it belongs to).
  *
  * Definitions.  Edge i = (src_i -> dst_i, ts_i).  Self-loops (src == dst)
- * are removed from every pattern ("differentiate ... eliminating
- * self-connections", Section 6) and their rows are all zero.  For an anchor
+ * take part in no pattern (Section 6's differentiate operation removes an
+ * account's edges to itself) and their rows are all zero.  For an anchor
  * edge e = (u -> v, t) the window is [t - delta, t] (Find_Start(t - delta)
  * and the break on timestamps past t, Section 6):
  *
@@ -23,7 +23,8 @@
  *               t - delta <= a < b <= t (with AMLM_SG_UNORDERED: a in
  *               [t - delta, t) and b in [t - delta, t], either order)
  *   SG_k(e)     number of s in S(e) with |M_e(s)| >= k   (Section 5,
- *               scatter-gather decomposition; Section 4, "at least N")
+ *               scatter-gather decomposition; Section 4: a threshold
+ *               on how many intermediates take part)
  *   GS_k(e)     |S(e)| if |S(e)| >= k and u has at least k distinct
  *               destinations at times in (tau, t], tau being the earliest
  *               time of an edge into u from S(e) in the window; else 0
@@ -35,8 +36,9 @@
  *
  * Stage outputs are vertex sets (Algorithm 1), so S, M and the gather-scatter
  * destinations count distinct accounts; FAN counts edges; cycles are edge
- * sets (parallel edges give distinct cycles).  A count that would exceed
- * 2^32 - 1 makes the call fail with AMLM_E_RANGE.
+ * sets (parallel edges give distinct cycles).  Counts saturate: a count
+ * whose exact value exceeds 2^32 - 1 (or the ceiling set by
+ * amlm_graph_set_ceiling) is reported as that value.
  *
  * Output layout: counts[col * n_edges + i] for edge i, with one column per
  * requested pattern in the order FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.
@@ -58,9 +60,11 @@ typedef enum {
     AMLM_OK = 0,
     AMLM_E_INVALID = 1, /* bad argument: vertex id >= n_vertices, L outside 2..8,
                            k == 0, delta < 0, null pointer, unknown pattern bit */
-    AMLM_E_RANGE = 2,   /* timestamp span >= 2^31 - 1 seconds, or a count overflow */
+    AMLM_E_RANGE = 2,   /* timestamp span >= 2^31 - 1 seconds */
     AMLM_E_NOMEM = 3,   /* device allocation failed or over the server's HBM budget */
-    AMLM_E_DEVICE = 4,  /* a HIP runtime error; sticky on the handle */
+    AMLM_E_DEVICE = 4,  /* a HIP runtime error; sticky: every later call on the
+                           same handle (except destroy, info and status)
+                           returns it */
     AMLM_E_ORDER = 5,   /* a stream batch is not strictly later than what came before */
     AMLM_E_BUSY = 6     /* no free server slot and the caller asked not to wait */
 } amlm_status;
@@ -100,157 +104,201 @@ typedef struct {
 typedef struct amlm_graph amlm_graph;
 
 /*
- * Build the device graph store: validates ids and the time span, then builds
- * time-sorted out- and in-adjacency (CSR / CSC), a neighbour-sorted copy of
- * the in-adjacency and the same-neighbour time links the kernels use.
+ * Build the device graph store (Section 6: the input is a temporal edge
+ * list; the generated code walks neighbour lists sorted by time, finds each
+ * window start by search and intersects sorted neighbour lists): validates
+ * ids and the time span, then builds time-sorted out- and in-adjacency
+ * (CSR / CSC), a neighbour-sorted copy of the in-adjacency and the
+ * same-neighbour time links the kernels use.
  *
  * src, dst: n_edges vertex ids (< n_vertices).  ts: n_edges timestamps (any
- * int64; max - min must be < 2^31 - 1).  amount: optional, carried and
- * ignored by every pattern (may be NULL).  inputs_on_device: 0 if the four
- * pointers are host memory (copied), 1 if they are device memory on the
- * current device (read, not retained).  hip_stream: a hipStream_t (NULL =
- * default stream); the call synchronises that stream before returning.
- * n_edges may be 0.  n_edges must be < 2^32 - 1.  On success *out owns its
- * device memory until amlm_graph_destroy.
+ * int64; max - min must be < 2^31 - 1, else AMLM_E_RANGE).  amount:
+ * optional, carried and ignored by every pattern (may be NULL).
+ * inputs_on_device: 0 if the four pointers are host memory (copied), 1 if
+ * they are device memory on the current device (read, not retained).
+ * hip_stream: a hipStream_t (NULL = default stream); the call synchronises
+ * that stream before returning.  n_edges may be 0 and must be < 2^32 - 1.
+ * Errors: AMLM_E_INVALID (null pointer, id >= n_vertices), AMLM_E_RANGE,
+ * AMLM_E_NOMEM, AMLM_E_DEVICE.  On success *out owns its device memory until
+ * amlm_graph_destroy.
  */
 amlm_status amlm_graph_create(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
                               const float *amount, uint64_t n_edges, uint32_t n_vertices,
                               int inputs_on_device, void *hip_stream, amlm_graph **out);
 
-/* Rebuild the same handle from a new edge list of any size (device buffers
- * are reused when they are large enough).  Same arguments and errors as
- * amlm_graph_create.  Queued on hip_stream; synchronises it on return. */
+/* Rebuild the same handle from a new edge list of any size (Section 6, as
+ * for amlm_graph_create; device buffers are reused when they are large
+ * enough).  Same arguments and errors as amlm_graph_create.  Queued on
+ * hip_stream; synchronises it on return. */
 amlm_status amlm_graph_rebuild(amlm_graph *g, const uint32_t *src, const uint32_t *dst,
                                const int64_t *ts, uint64_t n_edges, uint32_t n_vertices,
                                int inputs_on_device, void *hip_stream);
 
+/* Free the handle and its device memory (synchronises the device).  NULL is
+ * ignored. */
 void amlm_graph_destroy(amlm_graph *g);
 
-/* n_edges, number of non-self-loop edges, and the timestamp base (min ts) */
+/* n_edges, number of non-self-loop edges (Section 6's differentiate removes
+ * the others), n_vertices and the timestamp base (min ts).  Pointers may be
+ * NULL. */
 amlm_status amlm_graph_info(const amlm_graph *g, uint64_t *n_edges, uint64_t *n_valid,
                             uint32_t *n_vertices, int64_t *t_base);
 
-/* Number of output columns for these parameters (0 on invalid parameters). */
+/* The handle's sticky status: AMLM_OK, or AMLM_E_DEVICE once a HIP runtime
+ * call failed inside a call on it (the handle then only supports destroy,
+ * info and this call).  AMLM_E_INVALID for NULL. */
+amlm_status amlm_graph_status(const amlm_graph *g);
+
+/* Counts of later mining calls on g saturate at `ceiling` instead of
+ * 2^32 - 1 (0 restores 2^32 - 1).  The paper fixes no width for the counts;
+ * saturation keeps every result an order-independent function of the graph,
+ * and a low ceiling lets a small graph reach it (tests).  AMLM_E_INVALID for
+ * NULL. */
+amlm_status amlm_graph_set_ceiling(amlm_graph *g, uint32_t ceiling);
+
+/* Number of output columns for these parameters (0 on invalid parameters):
+ * one per requested pattern of Section 5, cycles one per length 2..L. */
 uint32_t amlm_num_columns(const amlm_params *p);
 
 /*
- * Mine every edge of g.  counts_dev: caller-owned device memory of
- * amlm_num_columns(p) * n_edges uint32 on the graph's device, layout
- * [col][edge].  Asynchronous on hip_stream (NULL = default stream): the
- * host is not synchronised and the counts are valid once the stream has
- * reached this point.  Parameter errors are reported before any device
- * work.  A count overflow (> 2^32 - 1) is detected on the device and
- * reported as AMLM_E_RANGE by the next call on the handle that
- * synchronises (amlm_graph_sync).
+ * Mine every edge of g (Sections 5 and 6: every pattern composed of stages,
+ * evaluated for every transaction as the anchor of its instances; Section 8
+ * uses the counts as per-transaction features).  counts_dev: caller-owned
+ * device memory of amlm_num_columns(p) * n_edges uint32 on the graph's
+ * device, layout [col][edge].  Asynchronous on hip_stream (NULL = default
+ * stream): the host is not synchronised and the counts are valid once the
+ * stream has reached this point.  Parameter errors (AMLM_E_INVALID) are
+ * reported before any device work; the learned schedule without a cost
+ * model is AMLM_E_INVALID.  The handle's scratch memory is allocated on the
+ * first call (AMLM_E_NOMEM).
  */
 amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, void *hip_stream);
 
-/* Stage timing with HIP events on the mining stream (for benchmarks).
- * After amlm_set_timing(g, 1), every amlm_graph_rebuild / amlm_mine on g
- * records its stages; amlm_stage_times waits for the last recorded events and
- * returns milliseconds per stage in ms[8]: 0 graph build, 1 anchor pass,
- * 2 work-list compaction, 3 scatter-gather kernel, 4 cycle kernel, 5 cost
- * model inference, 6 work units of the learned schedule; -1 for a stage
- * that did not run. */
+/* Stage timing with HIP events on the mining stream (no paper passage; for
+ * benchmarks).  After amlm_set_timing(g, 1), every amlm_graph_rebuild /
+ * amlm_mine on g records its stages; amlm_stage_times waits for the last
+ * recorded events and returns milliseconds per stage in ms[8]: 0 graph
+ * build, 1 anchor pass, 2 work-list compaction, 3 scatter-gather kernel,
+ * 4 cycle kernel, 5 cost model inference, 6 work units of the learned
+ * schedule; -1 for a stage that did not run. */
 amlm_status amlm_set_timing(amlm_graph *g, int enable);
 amlm_status amlm_stage_times(amlm_graph *g, float *ms);
 
-/* Pin the launch shape of later amlm_mine calls on g (0 keeps the default
- * of a field): block = list items per scatter-gather work unit (clamped to
- * [4, 8]); sg_blocks, cyc_blocks = persistent grid sizes; split_bytes =
- * learned schedule only: an anchor whose predicted scatter-gather bytes
- * exceed this is cut into slices of about this size, each its own work unit
- * (default 65536).  Never changes a count.  AMLM_E_INVALID for a NULL g. */
+/* Pin the launch shape of later amlm_mine calls on g (no paper passage; the
+ * launch shape of the persistent kernels; 0 keeps the default of a field):
+ * block = list items per scatter-gather work unit (clamped to [4, 8]);
+ * sg_blocks, cyc_blocks = persistent grid sizes; split_bytes = learned
+ * schedule only: an anchor whose predicted scatter-gather bytes exceed this
+ * is cut into slices of about this size, each its own work unit (default
+ * 65536).  Never changes a count.  AMLM_E_INVALID for a NULL g. */
 amlm_status amlm_tune_set(amlm_graph *g, uint32_t block, uint32_t sg_blocks, uint32_t cyc_blocks,
                           uint32_t split_bytes);
 
-/* Synchronise hip_stream and report device-side errors of earlier mining
- * calls on g (AMLM_E_RANGE for a count overflow). Clears the error word. */
+/* Synchronise hip_stream (no paper passage): AMLM_E_DEVICE if the stream
+ * reports a HIP error (sticky on g), or g's sticky status. */
 amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream);
 
 /*
- * Per-anchor work of the plain (static-schedule) miner, in algorithmic bytes:
- * work_dev[i] for edge i is what the scatter-gather / gather-scatter stage
- * reads for anchor i (its senders' window, the staged gather window, the
- * senders' out-windows and the scatter window), and work_dev[n_edges + i]
- * what the cycle stage reads for searches rooted at anchor i (partial paths
- * expanded and their time slices, closing searches).  These are the cost
- * model's training labels and the roofline's byte counts.  work_dev: device
- * uint32 [2][n_edges].  Counts are written to counts_dev as amlm_mine does.
+ * Mining as amlm_mine, plus per-anchor byte counters in work_dev: device
+ * uint64 [4][n_edges], rows
+ *   0  B_io: the edge row read (src, dst, ts: 12 bytes) and its counts written
+ *   1  B_sg/gs: the method's scatter-gather bytes of anchor i: its sender
+ *      window, for each distinct sender s the smaller of s's scanned
+ *      out-window (cut at the (k-1)-th qualifying intermediate other than u)
+ *      and v's in-window, and the scatter scan of GS_k (Section 6's compiled
+ *      scatter-gather example, its degree-ordered set intersection and
+ *      Algorithm 1's early breaks), 8 bytes per element
+ *   2  B_cyc: the method's cycle bytes of searches rooted at anchor i: slices
+ *      of partial paths of depth 0 .. L-3 (12 bytes per element), one
+ *      closing binary search per partial path of depth L-2 (8 ceil(log2
+ *      in-degree(u)) bytes, Section 6's 4-cycle example) and 8 bytes per
+ *      credited cycle edge
+ *   3  the bytes the scatter-gather kernel itself reads for anchor i (the
+ *      learned cost model's training label)
+ * Rows 0-2 follow a canonical procedure that no schedule changes: they are
+ * the roofline's algorithmic bytes.  Slower than amlm_mine (an extra
+ * accounting pass); not for timing.
  */
 amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
-                           uint32_t *work_dev, void *hip_stream);
+                           uint64_t *work_dev, void *hip_stream);
 
 /* ---- batching: many independent graphs in one launch ---- */
 
 /*
- * Batched store: n_graphs independent graphs (for example one partition per
- * institution) held in one graph store with disjoint vertex ranges, so that
- * one launch sequence mines all of them.  src / dst hold each graph's LOCAL
- * vertex ids (graph i: 0 <= id < n_vertices[i]); graph i owns edges
- * [edge_offsets[i], edge_offsets[i + 1]) of the concatenated arrays
- * (edge_offsets[0] = 0, n_graphs + 1 entries).  The timestamps of all graphs
- * together must span < 2^31 - 1.  Pointers as for amlm_graph_create; the
- * call synchronises hip_stream.  Destroy with amlm_graph_destroy.
+ * Batched store (no paper passage: the paper mines one graph; this holds
+ * many independent ones, for example one partition per institution, in one
+ * graph store with disjoint vertex ranges, so that one launch sequence mines
+ * all of them).  src / dst hold each graph's LOCAL vertex ids (graph i:
+ * 0 <= id < n_vertices[i]); graph i owns edges [edge_offsets[i],
+ * edge_offsets[i + 1]) of the concatenated arrays (edge_offsets[0] = 0,
+ * n_graphs + 1 entries).  The timestamps of all graphs together must span
+ * < 2^31 - 1.  Pointers and errors as for amlm_graph_create; the call
+ * synchronises hip_stream.  Destroy with amlm_graph_destroy.
  */
 amlm_status amlm_batch_create(const uint32_t *src, const uint32_t *dst, const int64_t *ts,
                               const uint64_t *edge_offsets, const uint32_t *n_vertices, uint32_t n_graphs,
                               int inputs_on_device, void *hip_stream, amlm_graph **out);
 
 /*
- * Mine every graph of a batched store with its own parameters ps[i]: the
- * same pattern set and schedule for all, delta, L and k per graph.
- * counts_dev[i]: device memory of amlm_num_columns(&ps[i]) * n_edges_i
- * uint32, layout [col][edge] of graph i (edge ids local to graph i).  The
- * launch sequence (anchor pass, work lists, scatter-gather and cycle
- * kernels, split into the per-graph outputs) is captured once into a
- * hipGraph per launch signature and replayed on hip_stream; parameters and
- * output pointers are read from device memory at replay, so they may change
- * between calls.  Asynchronous like amlm_mine.
+ * Mine every graph of a batched store with its own parameters ps[i] (the
+ * patterns of Section 5 per graph): the same pattern set and schedule for
+ * all, delta, L and k per graph.  counts_dev[i]: device memory of
+ * amlm_num_columns(&ps[i]) * n_edges_i uint32, layout [col][edge] of graph i
+ * (edge ids local to graph i).  The launch sequence (anchor pass, work
+ * lists, scatter-gather and cycle kernels, split into the per-graph outputs)
+ * is captured once into a hipGraph per launch signature and replayed on
+ * hip_stream; parameters and output pointers are read from device memory at
+ * replay, so they may change between calls.  Asynchronous like amlm_mine.
  */
 amlm_status amlm_mine_batch(amlm_graph *batch, const amlm_params *ps, uint32_t *const *counts_dev,
                             void *hip_stream);
 
 /* Number of sub-graphs of a batched store and how many hipGraph captures
- * amlm_mine_batch has made so far. */
+ * amlm_mine_batch has made so far (no paper passage). */
 amlm_status amlm_batch_info(const amlm_graph *g, uint32_t *n_graphs, uint32_t *captures);
 
 /*
- * Autotune the mining launch shape of g (work-stealing chunk size and grid
- * sizes of the persistent kernels) by timed runs with HIP events, keep the
- * best on the handle, and cache it in the JSON file cache_path (keyed by
- * device, graph size and parameters; NULL = no cache).  A cached entry is
- * used without timing.  For a batched store pass one parameter set per graph
- * and counts_dev as for amlm_mine_batch; otherwise n_params = 1 and
- * counts_dev[0].  chosen (may be NULL) receives {chunk, sg_blocks,
- * cyc_blocks}.  Counts written during tuning are the mining results.
+ * Autotune the mining launch shape of g (no paper passage: work-stealing
+ * chunk size and grid sizes of the persistent kernels) by timed runs with
+ * HIP events, keep the best on the handle, and cache it in the JSON file
+ * cache_path (keyed by device, graph size and parameters; NULL = no cache).
+ * A cached entry is used without timing.  For a batched store pass one
+ * parameter set per graph and counts_dev as for amlm_mine_batch; otherwise
+ * n_params = 1 and counts_dev[0].  chosen (may be NULL) receives {chunk,
+ * sg_blocks, cyc_blocks}.  Counts written during tuning are the mining
+ * results.
  */
 amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint32_t n_params, uint32_t *const *counts_dev,
                           const char *cache_path, void *hip_stream, uint32_t *chosen);
 
-/* ---- learned cost model (scheduling only; never changes a count) ---- */
+/* ---- learned cost model (scheduling only; never changes a count) ----
+ * The paper has no learned component; its optimiser orders set operations
+ * by an estimated cost (Section 6).  Here a network estimates each anchor's
+ * scatter-gather work so the scheduler can cut heavy anchors into slices. */
 
 /*
  * Train the 12 -> 64 -> 64 -> 1 MLP (BF16 weights, FP32 accumulation) on the
- * per-anchor work labels of the given graphs, on the GPU, with the library's
- * own forward / backward / Adam kernels, and keep it as the process-wide
- * model.  If out_path is not NULL the weights are also written there.
- * epochs, batch: training loop shape (0 = defaults: 4 epochs, 4096).
- * Deterministic for a fixed seed.
+ * per-anchor work labels (row 3 of amlm_mine_work) of the given graphs, on
+ * the GPU, with the library's own forward / backward / Adam kernels, and
+ * keep it as the process-wide model.  If out_path is not NULL the weights
+ * are also written there.  epochs, batch: training loop shape (0 = defaults:
+ * 4 epochs, 4096).  Deterministic for a fixed seed.
  */
 amlm_status amlm_costmodel_train(amlm_graph *const *train_graphs, const amlm_params *ps, uint32_t n,
                                  uint32_t epochs, uint32_t batch, uint64_t seed,
                                  const char *out_path, void *hip_stream);
-/* Load / save the process-wide model (weights, input mean and 1/std). */
+/* Load / save the process-wide model (weights, input mean and 1/std); no
+ * paper passage. */
 amlm_status amlm_costmodel_load(const char *path);
 amlm_status amlm_costmodel_save(const char *path);
 /* Copy the loaded model out: weights[5057] (FP32 master values, flat layout
  * W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3), mean[12], inv_std[12].
- * Any pointer may be NULL. */
+ * Any pointer may be NULL.  No paper passage. */
 amlm_status amlm_costmodel_get(float *weights, float *mean, float *inv_std);
 
-/* Network primitives on host arrays (copied to and from the device).  The
- * weights are rounded to BF16 (nearest even) before use; arithmetic is FP32.
+/* Network primitives on host arrays (copied to and from the device; no paper
+ * passage).  The weights are rounded to BF16 (nearest even) before use;
+ * arithmetic is FP32.
  * amlm_mlp_forward: y[i] = f(x[i]) for standardised inputs x[n][12].
  * amlm_mlp_grad: gradient of mean_i (f(x[i]) - y[i])^2 with respect to the
  * 5057 parameters, accumulated over samples in a fixed order (deterministic);
@@ -263,55 +311,68 @@ amlm_status amlm_mlp_predict(const float *weights, const float *x, uint32_t n, f
 amlm_status amlm_mlp_grad(const float *weights, const float *x, const float *y, uint32_t n, float *grad,
                           float *loss);
 
-/* ---- streaming server (continuous batching) ---- */
+/* ---- streaming server (continuous batching) ----
+ * Section 5's streaming integration: a new transaction adds to the counts of
+ * every pattern instance it completes, and the work stays local to the
+ * instances it touches instead of recomputing the graph. */
 
 typedef struct amlm_server amlm_server;
 
 /*
  * A server keeps the edges of `resident` plus every submitted batch in HBM
- * and mines each submitted batch incrementally: the new edges' own columns
- * come from instances that end at them; cycles closed by a new edge also
- * credit older edges, which are reported as sparse deltas.  Batches must be
- * strictly later in time than everything before them (AMLM_E_ORDER
- * otherwise).  hbm_budget_bytes bounds the device memory the in-flight
- * batches may hold (0 = no bound); max_slots bounds how many batches are
- * mined concurrently, each on its own HIP stream.
+ * and mines each submitted batch incrementally (Section 5, streaming): the
+ * new edges' own columns come from instances that end at them; cycles closed
+ * by a new edge also credit older edges, which are reported as sparse
+ * deltas.  Batches must be strictly later in time than everything before
+ * them (AMLM_E_ORDER otherwise).  hbm_budget_bytes bounds the device memory
+ * the in-flight batches may hold (0 = no bound); max_slots bounds how many
+ * batches are mined concurrently, each on its own HIP stream.
  */
 amlm_status amlm_server_create(amlm_graph *resident, const amlm_params *p, uint64_t hbm_budget_bytes,
                                uint32_t max_slots, amlm_server **out);
 
 /* Copy a batch of n host edges, order it after the previous batches, and
- * start mining it as soon as a slot and budget are free (blocking when
- * wait != 0, else AMLM_E_BUSY).  *ticket identifies the batch. */
+ * start mining it as soon as a slot and budget are free (Section 5,
+ * streaming; blocking when wait != 0, else AMLM_E_BUSY).  *ticket
+ * identifies the batch. */
 amlm_status amlm_server_submit(amlm_server *s, const uint32_t *src, const uint32_t *dst,
                                const int64_t *ts, uint64_t n, int wait, uint64_t *ticket);
 
 /*
- * Wait for a batch.  new_counts_host: [ncols][n] for the batch's own edges
- * (host memory, may be NULL).  Deltas for older edges: up to cap entries of
- * (edge id, column, increment); *n_deltas gets the total number (entries
- * past cap are dropped; call again with a larger cap is not supported, so
- * size cap generously).  Edge ids of stream edges continue after the
- * resident graph's: n_edges + running index.
+ * Wait for a batch (Section 5, streaming).  new_counts_host: [ncols][n] for
+ * the batch's own edges (host memory, may be NULL).  Deltas for older edges:
+ * up to cap entries of (edge id, column, increment); *n_deltas gets the
+ * total number (entries past cap are dropped; size cap generously).  Edge
+ * ids of stream edges continue after the resident graph's: n_edges +
+ * running index.  The batch's results are released by this call.
  */
 amlm_status amlm_server_wait(amlm_server *s, uint64_t ticket, uint32_t *new_counts_host,
                              uint64_t *n_deltas, uint64_t *delta_eid, uint32_t *delta_col,
                              uint32_t *delta_val, uint64_t cap);
 
 /* Per-ticket timing (host wall clock, seconds): submit -> admitted ->
- * finished. */
+ * finished (no paper passage; for latency measurements). */
 amlm_status amlm_server_ticket_times(amlm_server *s, uint64_t ticket, double *t_submit,
                                      double *t_admit, double *t_done);
 
+/* Stop the server's slots and free everything it holds. */
 void amlm_server_destroy(amlm_server *s);
 
 /* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
  * pointers) by the library's own streaming kernel: the achievable-bandwidth
- * probe and the calibration of the hardware byte counters.  Asynchronous. */
+ * probe and the calibration of the hardware byte counters (no paper
+ * passage).  Asynchronous. */
 amlm_status amlm_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
 
 /* Thread-local message describing the last error on this thread. */
 const char *amlm_last_error(void);
+
+/* ---- testing aids ---- */
+
+/* The next build or mining call on g fails as if a HIP runtime call had
+ * failed inside it: it returns AMLM_E_DEVICE, which stays sticky on g.
+ * Exercises the sticky-error path without a real device fault. */
+amlm_status amlm_graph_inject_device_error(amlm_graph *g);
 
 #ifdef __cplusplus
 }

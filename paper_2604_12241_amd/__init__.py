@@ -31,7 +31,7 @@ EXPORTS = [
     "amlm_server_destroy", "amlm_last_error", "amlm_set_timing", "amlm_stage_times",
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
     "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy", "amlm_mlp_predict",
-    "amlm_tune_set",
+    "amlm_tune_set", "amlm_graph_status", "amlm_graph_set_ceiling", "amlm_graph_inject_device_error",
 ]
 
 
@@ -92,6 +92,9 @@ def lib():
             "amlm_mlp_predict": (st, [p, p, u32, p]),
             "amlm_mlp_grad": (st, [p, p, p, u32, p, p]),
             "amlm_stage_times": (st, [p, ctypes.POINTER(ctypes.c_float)]),
+            "amlm_graph_status": (st, [p]),
+            "amlm_graph_set_ceiling": (st, [p, u32]),
+            "amlm_graph_inject_device_error": (st, [p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -197,13 +200,19 @@ def amlm_mine(g: Graph, p: amlm_params, counts=None, stream=None):
     return counts
 
 
+WORK_ROWS = ["io", "sg", "cyc", "sg_impl"]
+
+
 def amlm_mine_work(g: Graph, p: amlm_params, counts=None, work=None, stream=None):
+    """Mining plus per-anchor byte counters: returns (counts, work) with work
+    an int64 tensor [4, n_edges] (rows WORK_ROWS: the method's algorithmic
+    bytes B_io, B_sg/gs, B_cyc, then the scatter-gather kernel's own bytes)."""
     import torch
     ncols = amlm_num_columns(p)
     if counts is None:
         counts = torch.empty((ncols, g.n_edges), dtype=torch.int32, device="cuda")
     if work is None:
-        work = torch.empty((2, g.n_edges), dtype=torch.int32, device="cuda")
+        work = torch.empty((4, g.n_edges), dtype=torch.int64, device="cuda")
     _check(lib().amlm_mine_work(g.handle, ctypes.byref(p), _ptr(counts), _ptr(work), _stream_handle(stream)))
     return counts, work
 
@@ -228,6 +237,22 @@ def amlm_stage_times(g: Graph) -> dict:
 
 def amlm_graph_sync(g: Graph, stream=None):
     _check(lib().amlm_graph_sync(g.handle, _stream_handle(stream)))
+
+
+def amlm_graph_status(g: Graph) -> int:
+    """The handle's sticky status (0 = healthy)."""
+    return int(lib().amlm_graph_status(g.handle))
+
+
+def amlm_graph_set_ceiling(g: Graph, ceiling: int):
+    """Counts of later mining calls saturate at ``ceiling`` (0 = 2^32 - 1)."""
+    _check(lib().amlm_graph_set_ceiling(g.handle, int(ceiling)))
+
+
+def amlm_graph_inject_device_error(g: Graph):
+    """Testing aid: the next build or mining call fails with a sticky
+    AMLM_E_DEVICE."""
+    _check(lib().amlm_graph_inject_device_error(g.handle))
 
 
 class Batch(Graph):

@@ -118,7 +118,6 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
   A_TRY(dalloc(g, (void **)&b.scan_tmp, 4 * tw));
   A_TRY(dalloc(g, (void **)&b.stats, 8 * (8 + 5 * kValidateBlocks)));
   A_TRY(dalloc(g, (void **)&b.ep, 16 * e));
-  A_TRY(dalloc(g, (void **)&g->err_dev, 64));
   A_TRY(dalloc(g, (void **)&g->ts_stage, 8 * e));
   g->cap_e = E;
   g->cap_v = V;
@@ -188,8 +187,28 @@ GraphView graph_view(const amlm_graph *g) {
 
 // ------------------------------------------------------------------ graph
 
+amlm_status sticky_check(amlm_graph *g) {
+  if (g->sticky != AMLM_OK) {
+    set_error("the graph handle had a HIP runtime error earlier (sticky); destroy it");
+    return g->sticky;
+  }
+  if (g->inject) {
+    g->inject = 0;
+    g->sticky = AMLM_E_DEVICE;
+    set_error("injected HIP runtime error (testing aid)");
+    return AMLM_E_DEVICE;
+  }
+  return AMLM_OK;
+}
+
+amlm_status sticky_note(amlm_graph *g, amlm_status st) {
+  if (st == AMLM_E_DEVICE && g) g->sticky = AMLM_E_DEVICE;
+  return st;
+}
+
 static amlm_status do_build(amlm_graph *g, const uint32_t *src, const uint32_t *dst, const int64_t *ts,
                             uint64_t n_edges, uint32_t n_vertices, int on_device, hipStream_t s) {
+  A_TRY(sticky_check(g));
   if (n_edges >= 0xffffffffull) {
     set_error("n_edges must be < 2^32 - 1");
     return AMLM_E_INVALID;
@@ -231,7 +250,6 @@ static amlm_status do_build(amlm_graph *g, const uint32_t *src, const uint32_t *
   HIP_TRY(build_graph(a, ts_dev, vr.tmin, (uint32_t)n_edges, g->Ev, n_vertices, t_bits, vr.unsorted == 0,
                       vr.self_loops, g->bb, s));
   HIP_TRY(g->timer.end(kStBuild, s));
-  HIP_TRY(launch_fill_u32(g->err_dev, 0, 16, s));
   A_TRY(alloc_mine_scratch(g));
   HIP_TRY(hipStreamSynchronize(s));
   return AMLM_OK;
@@ -265,7 +283,7 @@ extern "C" amlm_status amlm_graph_rebuild(amlm_graph *g, const uint32_t *src, co
     set_error("null graph");
     return AMLM_E_INVALID;
   }
-  return do_build(g, src, dst, ts, n_edges, n_vertices, inputs_on_device, (hipStream_t)hip_stream);
+  return sticky_note(g, do_build(g, src, dst, ts, n_edges, n_vertices, inputs_on_device, (hipStream_t)hip_stream));
 }
 
 extern "C" void amlm_graph_destroy(amlm_graph *g) {
@@ -341,7 +359,7 @@ extern "C" uint32_t amlm_num_columns(const amlm_params *p) {
   return c;
 }
 
-MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, uint32_t *work) {
+MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, unsigned long long *work) {
   MineParams mp;
   mp.g = graph_view(g);
   mp.delta = p->delta;
@@ -359,8 +377,8 @@ MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *coun
   mp.sg_unordered = (p->patterns & AMLM_SG_UNORDERED) ? 1u : 0u;
   mp.counts = counts;
   mp.stride = g->E;
+  mp.ceil = g->ceiling;
   mp.work = work;
-  mp.err = g->err_dev;
   return mp;
 }
 
@@ -378,24 +396,17 @@ MineLaunch default_launch(const amlm_graph *g) {
   return cfg;
 }
 
-amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
-                        hipStream_t s, uint32_t anchor_lo) {
-  if (!g) {
-    set_error("null graph");
-    return AMLM_E_INVALID;
-  }
+static amlm_status mine_impl(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,
+                             hipStream_t s, uint32_t anchor_lo) {
   A_TRY(check_params(p));
   if (g->E && !counts_dev) {
     set_error("null counts");
     return AMLM_E_INVALID;
   }
-  if (g->sticky != AMLM_OK) {
-    set_error("graph has a sticky device error");
-    return g->sticky;
-  }
+  A_TRY(sticky_check(g));
   uint32_t ncols = amlm_num_columns(p);
   HIP_TRY(launch_fill_u32(counts_dev, 0, (uint64_t)ncols * g->E, s));
-  if (work_dev) HIP_TRY(launch_fill_u32(work_dev, 0, 2 * g->E, s));
+  if (work_dev) HIP_TRY(launch_fill_u32((uint32_t *)work_dev, 0, 2ull * kWorkRows * g->E, s));
   A_TRY(alloc_mine_scratch(g));
   MineParams mp = make_params(g, p, counts_dev, work_dev);
   mp.anchor_lo = anchor_lo;
@@ -425,17 +436,26 @@ amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_de
   return AMLM_OK;
 }
 
+amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,
+                        hipStream_t s, uint32_t anchor_lo) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  return sticky_note(g, mine_impl(g, p, counts_dev, work_dev, s, anchor_lo));
+}
+
 extern "C" amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, void *hip_stream) {
   return mine_common(g, p, counts_dev, nullptr, (hipStream_t)hip_stream);
 }
 
-extern "C" amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
-                                      void *hip_stream) {
+extern "C" amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
+                                      uint64_t *work_dev, void *hip_stream) {
   if (g && g->E && !work_dev) {
     set_error("null work");
     return AMLM_E_INVALID;
   }
-  return mine_common(g, p, counts_dev, work_dev, (hipStream_t)hip_stream);
+  return mine_common(g, p, counts_dev, (unsigned long long *)work_dev, (hipStream_t)hip_stream);
 }
 
 extern "C" amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream) {
@@ -443,16 +463,38 @@ extern "C" amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream) {
     set_error("null graph");
     return AMLM_E_INVALID;
   }
-  hipStream_t s = (hipStream_t)hip_stream;
-  uint32_t err = 0;
-  HIP_TRY(hipMemcpyAsync(&err, g->err_dev, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (err) {
-    HIP_TRY(launch_fill_u32(g->err_dev, 0, 1, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    set_error("a cycle count exceeded 2^32 - 1");
-    return AMLM_E_RANGE;
+  A_TRY(sticky_check(g));
+  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e != hipSuccess) {
+    set_error(std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    return sticky_note(g, AMLM_E_DEVICE);
   }
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_graph_status(const amlm_graph *g) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  return g->sticky;
+}
+
+extern "C" amlm_status amlm_graph_inject_device_error(amlm_graph *g) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  g->inject = 1;
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_graph_set_ceiling(amlm_graph *g, uint32_t ceiling) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  g->ceiling = ceiling ? ceiling : 0xffffffffu;
   return AMLM_OK;
 }
 

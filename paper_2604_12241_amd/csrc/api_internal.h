@@ -50,23 +50,31 @@ struct amlm_graph {
   GraphArrays arr{};
   BuildBuffers bb{};
   int64_t *ts_stage = nullptr;
-  uint32_t *err_dev = nullptr;
   MineScratch ms{};
   TuneParams tune{};
   StageTimer timer{};
   hipStream_t aux = nullptr;  // second mining stream (cycle kernel), created on first use
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   BatchState batch{};
+  uint32_t ceiling = 0xffffffffu;  // counts saturate here
+  // AMLM_E_DEVICE once a HIP runtime call failed inside a call on this
+  // handle; every later call except destroy / info / status returns it
   amlm_status sticky = AMLM_OK;
+  uint32_t inject = 0;             // testing aid: fail the next mining or build call
   std::vector<void *> allocs;
   uint64_t device_bytes = 0;
 };
 
 amlm_status check_params(const amlm_params *p);
 GraphView graph_view(const amlm_graph *g);
-MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, uint32_t *work);
+MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, unsigned long long *work);
 MineLaunch default_launch(const amlm_graph *g);
 amlm_status alloc_mine_scratch(amlm_graph *g);
 // Mining with the edges of id >= anchor_lo as the only anchors (0 = all).
-amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, uint32_t *work_dev,
+amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,
                         hipStream_t s, uint32_t anchor_lo = 0);
+// Sticky device errors: returns g's sticky status if set; otherwise, if a
+// fault was injected for this call, records it and returns AMLM_E_DEVICE.
+amlm_status sticky_check(amlm_graph *g);
+// Records AMLM_E_DEVICE as g's sticky status; returns st unchanged.
+amlm_status sticky_note(amlm_graph *g, amlm_status st);

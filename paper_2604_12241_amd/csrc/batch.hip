@@ -200,19 +200,16 @@ static std::string batch_signature(const amlm_graph *g, uint32_t patterns, uint3
   return o.str();
 }
 
-extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uint32_t *const *counts_dev,
-                                       void *hip_stream) {
-  if (!g || !ps || !counts_dev) {
-    set_error("null argument");
-    return AMLM_E_INVALID;
-  }
+static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_t *const *counts_dev,
+                                   void *hip_stream) {
+  A_TRY(sticky_check(g));
   BatchState &B = g->batch;
   if (B.n == 0) {
     set_error("not a batched graph store (use amlm_batch_create)");
     return AMLM_E_INVALID;
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  uint32_t Lmax = 2, kmin = ~0u;
+  uint32_t Lmax = 2, kmax = 1;
   std::vector<SubParams> sub(B.n);
   std::vector<uint32_t> ncols(B.n);
   for (uint32_t i = 0; i < B.n; i++) {
@@ -226,7 +223,7 @@ extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uin
     sub[i].L = L;
     sub[i].k = ps[i].k ? ps[i].k : 1;
     Lmax = std::max(Lmax, L);
-    kmin = std::min(kmin, sub[i].k);
+    kmax = std::max(kmax, sub[i].k);
     ncols[i] = ncols_of(ps[i].patterns, L);
     if (B.eoff[i + 1] > B.eoff[i] && !counts_dev[i]) {
       set_error("null counts for a non-empty graph");
@@ -235,7 +232,7 @@ extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uin
   }
   amlm_params pm = ps[0];
   pm.max_cycle_len = Lmax;
-  pm.k = kmin;
+  pm.k = kmax;  // the kernels read each sub-graph's own k; this only says whether any joins
   const uint32_t nc_max = ncols_of(pm.patterns, Lmax);
   A_TRY(alloc_mine_scratch(g));
   if (!B.comb || B.comb_cols < nc_max) {
@@ -293,6 +290,15 @@ extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uin
   }
   HIP_TRY(hipGraphLaunch(B.exec, s));
   return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_mine_batch(amlm_graph *g, const amlm_params *ps, uint32_t *const *counts_dev,
+                                       void *hip_stream) {
+  if (!g || !ps || !counts_dev) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  return sticky_note(g, mine_batch_impl(g, ps, counts_dev, hip_stream));
 }
 
 extern "C" amlm_status amlm_batch_info(const amlm_graph *g, uint32_t *n_graphs, uint32_t *captures) {
@@ -364,13 +370,10 @@ static void cache_store(const char *path, const std::string &key, const TunePara
   o << "}\n";
 }
 
-extern "C" amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint32_t n_params,
-                                     uint32_t *const *counts_dev, const char *cache_path, void *hip_stream,
-                                     uint32_t *chosen) {
-  if (!g || !ps || !counts_dev || n_params == 0) {
-    set_error("null argument");
-    return AMLM_E_INVALID;
-  }
+static amlm_status autotune_impl(amlm_graph *g, const amlm_params *ps, uint32_t n_params,
+                                 uint32_t *const *counts_dev, const char *cache_path, void *hip_stream,
+                                 uint32_t *chosen) {
+  A_TRY(sticky_check(g));
   const bool batched = g->batch.n > 0;
   if (batched && n_params != g->batch.n) {
     set_error("a batched store needs one parameter set per graph");
@@ -428,4 +431,14 @@ extern "C" amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint3
     chosen[2] = g->tune.cyc_blocks;
   }
   return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint32_t n_params,
+                                     uint32_t *const *counts_dev, const char *cache_path, void *hip_stream,
+                                     uint32_t *chosen) {
+  if (!g || !ps || !counts_dev || n_params == 0) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  return sticky_note(g, autotune_impl(g, ps, n_params, counts_dev, cache_path, hip_stream, chosen));
 }

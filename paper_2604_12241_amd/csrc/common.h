@@ -9,8 +9,6 @@
 #define AMLM_INT_MAX 0x7fffffff
 #define AMLM_INT_MIN (-0x7fffffff - 1)
 
-// Device error word bits (sticky until amlm_graph_sync reads them).
-#define AMLM_ERR_OVERFLOW 1u   // a count went past 2^32 - 1
 
 // Graph store in HBM.  All positions and edge ids fit in 32 bits.
 //  * anchors: valid (non-self-loop) edge ids in (time, id) order
@@ -204,8 +202,15 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
-// Saturation-checked credit: adds inc to *p and flags an overflow.
-__device__ __forceinline__ void credit(uint32_t *p, uint32_t inc, uint32_t *err) {
-  uint32_t old = atomicAdd(p, inc);
-  if (old + inc < old) atomicOr(err, AMLM_ERR_OVERFLOW);
+// Saturating credit: adds inc to *p, which ends at ceil if the sum of all
+// credits to it passes ceil (or 2^32 - 1).  A thread whose add wraps raises
+// the word to 2^32 - 1 and one whose add lands above ceil lowers it to ceil;
+// every add that finds the word at or above ceil (or wraps it) does the same
+// afterwards, so the last operation on a saturated word leaves ceil in it,
+// whatever the interleaving, while sums that stay within ceil are untouched.
+__device__ __forceinline__ void credit(uint32_t *p, uint32_t inc, uint32_t ceil) {
+  const uint32_t old = atomicAdd(p, inc);
+  const uint32_t sum = old + inc;
+  if (sum < old) atomicMax(p, 0xffffffffu);
+  if ((sum < old || sum > ceil) && ceil != 0xffffffffu) atomicMin(p, ceil);
 }

@@ -364,8 +364,9 @@ __global__ void k_adam(float *master, float *m, float *v, const float *grad, uin
 }
 
 // raw features of every anchor (time order) + its scatter-gather label
-__global__ void k_sample_features(GraphView g, int64_t delta, const uint32_t *work, uint32_t *feat, float *label,
-                                  uint32_t *keep) {
+// (work: the scatter-gather kernel's own bytes per edge id, kWorkSgImpl row)
+__global__ void k_sample_features(GraphView g, int64_t delta, const unsigned long long *work, uint32_t *feat,
+                                  float *label, uint32_t *keep) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.Ev) return;
   uint32_t eid = g.anc[p];
@@ -390,7 +391,7 @@ __global__ void k_sample_features(GraphView g, int64_t delta, const uint32_t *wo
   r[7] = ire - irs;
 #pragma unroll
   for (int q = 0; q < kMlpRaw; q++) feat[(uint64_t)p * kMlpRaw + q] = r[q];
-  uint32_t w = work[eid];
+  const unsigned long long w = work[eid];
   label[p] = log1pf((float)w);
   keep[p] = w > 0;
 }
@@ -622,7 +623,8 @@ extern "C" amlm_status amlm_costmodel_train(amlm_graph *const *gs, const amlm_pa
   float *lab_all;
   uint64_t cap = 0;
   for (uint32_t i = 0; i < n_graphs; i++) cap = std::max<uint64_t>(cap, gs[i]->E);
-  uint32_t *fs, *wk, *ctmp;
+  uint32_t *fs, *ctmp;
+  unsigned long long *wk;
   float *ls;
   A_TRY(b.get(&feat_all, total * kMlpRaw));
   A_TRY(b.get(&lab_all, total));
@@ -632,7 +634,7 @@ extern "C" amlm_status amlm_costmodel_train(amlm_graph *const *gs, const amlm_pa
   A_TRY(b.get(&koff, cap));
   A_TRY(b.get(&klist, cap));
   A_TRY(b.get(&cnt_dev, 4));
-  A_TRY(b.get(&wk, 2 * cap));
+  A_TRY(b.get(&wk, kWorkRows * cap));
   uint32_t ncol_max = 16;
   A_TRY(b.get(&ctmp, cap * ncol_max));
   uint32_t *scan_tmp;
@@ -643,7 +645,7 @@ extern "C" amlm_status amlm_costmodel_train(amlm_graph *const *gs, const amlm_pa
     A_TRY(mine_common(g, &ps[i], ctmp, wk, s));
     if (g->Ev == 0) continue;
     hipLaunchKernelGGL(k_sample_features, dim3((g->Ev + 255) / 256), dim3(256), 0, s, graph_view(g), ps[i].delta,
-                       wk, fs, ls, keep);
+                       (const unsigned long long *)(wk + kWorkSgImpl * g->E), fs, ls, keep);
     HIP_TRY(hipGetLastError());
     HIP_TRY(scan_exclusive_u32(keep, koff, g->Ev, cnt_dev, scan_tmp, s));
     hipLaunchKernelGGL(k_compact_keep, dim3((g->Ev + 255) / 256), dim3(256), 0, s, keep, koff, g->Ev, klist);

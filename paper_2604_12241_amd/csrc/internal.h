@@ -20,14 +20,6 @@ void set_error(const std::string &msg);
     }                                                                            \
   } while (0)
 
-// ---------------------------------------------------------------- device memory
-struct DeviceArena {
-  // every allocation of a graph, freed together
-  void *ptrs[64] = {};
-  size_t sizes[64] = {};
-  int n = 0;
-};
-
 // ---------------------------------------------------------------- build
 struct BuildBuffers {
   uint32_t *ka = nullptr, *kb = nullptr, *va = nullptr, *vb = nullptr;

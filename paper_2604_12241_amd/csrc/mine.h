@@ -73,10 +73,14 @@ struct MineParams {
   uint32_t sg_unordered;  // 1: an intermediate's two legs in either order
   uint32_t *counts;
   uint64_t stride;   // row stride of counts (= number of edges)
-  uint32_t *work;    // optional per-edge algorithmic bytes: [0, E) scatter-gather
-                     // stage, [E, 2E) cycle stage
-  uint32_t *err;     // device error word
+  uint32_t ceil;     // every count saturates at this value (2^32 - 1 by default)
+  // optional per-edge byte counters, rows of `stride` entries: kWorkIo,
+  // kWorkSg, kWorkCyc the method's algorithmic bytes of each anchor (the
+  // canonical procedure: see k_alg_sg and k_cyc), kWorkSgImpl the bytes the
+  // scatter-gather kernel itself reads for it (the cost model's label)
+  unsigned long long *work;
 };
+enum { kWorkIo = 0, kWorkSg = 1, kWorkCyc = 2, kWorkSgImpl = 3, kWorkRows = 4 };
 
 struct MineScratch {
   uint8_t *flags = nullptr;   // [0, Ev): scatter-gather flag per CSC position;
@@ -140,16 +144,19 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
 const void *k_sg_ptr();
 const void *k_cyc_ptr(bool small);  // small: the build for L <= kCycSmallL
 
-// Algorithmic bytes per unit of work (what each stage must read, at the
-// width of the fields it needs), used for the work counters and the roofline:
+// Bytes the scatter-gather kernel reads per unit of its own work, at the
+// width of the fields it loads (its work counter, kWorkSgImpl: the cost
+// model's training label):
 constexpr uint32_t kBytesAnchorSg = 16;      // anchor (edge id, u, v, t)
 constexpr uint32_t kBytesSenderEntry = 12;   // in-window of u: neighbour, next-same-pair time, time
 constexpr uint32_t kBytesGatherEntry = 4;    // in-window of v: neighbour id
 constexpr uint32_t kBytesJoinEntry = 4;      // out-window of a sender: neighbour id
 constexpr uint32_t kBytesScatterEntry = 4;   // out-window of u after tau: previous-same-pair time
-constexpr uint32_t kBytesPathNode = 16;      // a partial path (head, time, edge, parent)
-constexpr uint32_t kBytesPathEntry = 12;     // out-slice entry of a path head: neighbour, time, edge id
-constexpr uint32_t kBytesClosureSearch = 16; // closing-edge binary search result
+// The method's algorithmic bytes (kWorkIo .. kWorkCyc): an element of a
+// scanned slice is a neighbour id and a time, 8 bytes, 12 in the cycle scan
+// (plus the edge id it credits); an edge row is read as (src, dst, ts) and
+// written as one count per column.
+constexpr uint32_t kAlgEdgeRow = 12, kAlgCount = 4, kAlgElem = 8, kAlgCycElem = 12, kAlgCycleEdge = 8;
 
 // Window, cycle length and threshold of the (sub-)graph that vertex x belongs to.
 __device__ __forceinline__ int64_t delta_of(const MineParams &mp, uint32_t x) {

@@ -34,6 +34,7 @@ __device__ __forceinline__ int32_t window_lo(int32_t t, int64_t delta) {
 }
 
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t x) { return x <= 1 ? 0u : 32u - (uint32_t)__clz(x - 1); }
 __device__ __forceinline__ int32_t rfl(int32_t x) { return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x); }
 
 // ------------------------------------------------------------------ anchor passes
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
     uint32_t hi = gallop_upper_right(g.out_t, p + 1, re, t);
     uint32_t lb = gallop_lower_left(g.out_t, rs, p, lo);
     fan_out = hi - lb;
-    if (mp.col_fo >= 0) mp.counts[(uint64_t)mp.col_fo * mp.stride + eid] = fan_out;
+    if (mp.col_fo >= 0) mp.counts[(uint64_t)mp.col_fo * mp.stride + eid] = min(fan_out, mp.ceil);
   }
   if (mp.col_sg >= 0 || mp.col_gs >= 0) {
     uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
@@ -73,8 +74,8 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
           if (k == 1) {
             // every sender has u as its first intermediate and v is always a
             // scatter destination after the first gather: SG_1 = GS_1 = |S|
-            if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = ns;
-            if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = ns;
+            if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = min(ns, mp.ceil);
+            if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = min(ns, mp.ceil);
           } else {
             item = true;
           }
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
           uint32_t nd = 0, c = d0;
           for (; c < d1 && nd < k; c++) nd += g.out_prv[c] <= tau;
           if (nd >= k) fl |= kFlagGsDest;
-          if (mp.work) atomicAdd(&mp.work[eid], kBytesScatterEntry * (c - d0));
+          if (mp.work) atomicAdd(&mp.work[kWorkSgImpl * mp.stride + eid], (unsigned long long)(kBytesScatterEntry * (c - d0)));
         }
       }
       flags_sg[q] = fl;
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
     uint32_t rs = g.in_ptr[v], re = g.in_ptr[v + 1];
     uint32_t hi = gallop_upper_right(g.in_t, q + 1, re, t);
     uint32_t lb = gallop_lower_left(g.in_t, rs, q, lo);
-    if (mp.col_fi >= 0) mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = hi - lb;
+    if (mp.col_fi >= 0) mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = min(hi - lb, mp.ceil);
     if (is_sg) {
       sg_win[q].z = lb;
       sg_win[q].w = hi;
@@ -157,6 +158,95 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
       feat[(uint64_t)q * kMlpRaw + 3] = q1 - q0;
       feat[(uint64_t)q * kMlpRaw + 6] = ve - vs;
     }
+  }
+}
+
+// ------------------------------------------------------------------ algorithmic bytes
+// The method's algorithmic bytes per anchor, by a canonical procedure that
+// does not depend on how the kernels below organise their work (nothing is
+// reused across anchors; an element is a neighbour id and a time):
+//   row kWorkIo:  the edge's (src, dst, ts) and its output counts;
+//   row kWorkSg:  the sender scan of u's in-window [t - delta, t); for each
+//                 distinct sender s, min(n_s, |IN(v) in [t - delta, t]|)
+//                 elements, n_s being how far a scan of s's out-window in
+//                 (time, id) order gets before k - 1 intermediates other than
+//                 u have qualified (the whole window if fewer do): the
+//                 compiled scatter-gather intersection, bounded by its smaller
+//                 side (Section 6's degree-ordered intersection) and ended
+//                 early (Algorithm 1's break); and, for GS_k when |S| >= k, the
+//                 scan of u's out-row after tau until k distinct destinations;
+//   row kWorkCyc: counted by k_cyc (slices scanned at depths 0 .. L-3, one
+//                 closing search at depth L-2, 8 bytes per credited edge).
+// Accounting only (amlm_mine_work): one wave per anchor, one lane per sender
+// edge, each lane scanning its sender's window serially.
+__global__ __launch_bounds__(256) void k_alg_io(MineParams mp, uint32_t ncols) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mp.g.E || i < mp.anchor_lo) return;
+  mp.work[kWorkIo * mp.stride + i] = kAlgEdgeRow + (unsigned long long)kAlgCount * ncols;
+}
+
+__global__ __launch_bounds__(256) void k_alg_sg(MineParams mp) {
+  const GraphView &g = mp.g;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * (blockDim.x / AMLM_WAVE);
+  for (uint32_t q = blockIdx.x * (blockDim.x / AMLM_WAVE) + threadIdx.x / AMLM_WAVE; q < g.Ev; q += nw) {
+    const uint32_t eid = g.in_eid[q];
+    if (eid < mp.anchor_lo) continue;
+    const uint32_t v = g.in_dst[q], u = g.in_nbr[q];
+    const int32_t t = g.in_t[q];
+    const int32_t lo = window_lo(t, delta_of(mp, u));
+    const uint32_t k = k_of(mp, u);
+    const uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
+    const uint32_t p1 = lower_bound_i32(g.in_t, cs, ce, t);
+    const uint32_t p0 = lower_bound_i32(g.in_t, cs, p1, lo);
+    const uint32_t vrs = g.in_ptr[v], vre = g.in_ptr[v + 1];
+    // |IN(v) in [lo, t]|: the anchor sits at q inside v's row
+    const uint32_t r = upper_bound_i32(g.in_t, q + 1, vre, t) - lower_bound_i32(g.in_t, vrs, q, lo);
+    uint32_t ns = 0;
+    unsigned long long join = 0;
+    for (uint32_t j = p0 + lane; j < p1; j += AMLM_WAVE) {
+      const uint32_t s = g.in_nbr[j];
+      if (s == v || g.in_nxt[j] < t) continue;  // not the last s -> u edge before t
+      ns++;
+      if (mp.col_sg < 0 || k < 2) continue;
+      const uint32_t rs = g.out_ptr[s], re = g.out_ptr[s + 1];
+      const uint32_t b = lower_bound_i32(g.out_t, rs, re, lo);
+      const uint32_t n_full = lower_bound_i32(g.out_t, b, re, t) - b;
+      uint32_t n_s = min(n_full, r), found = 0;
+      for (uint32_t i = 0; i < min(n_full, r); i++) {
+        const uint32_t pos = b + i, m = g.out_nbr[pos];
+        if (m == u || g.out_prv[pos] >= lo) continue;  // u, or not the first s -> m edge of the window
+        const uint32_t qk = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+        if (qk == vrs) continue;
+        const uint64_t kk = g.inn_key[qk - 1];  // the last m -> v edge at or before t, if any
+        const int32_t tb = (int32_t)(uint32_t)kk;
+        if ((uint32_t)(kk >> 32) != m || !(mp.sg_unordered ? tb >= lo : tb > g.out_t[pos])) continue;
+        if (++found == k - 1) {
+          n_s = i + 1;
+          break;
+        }
+      }
+      join += n_s;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      ns += __shfl_xor(ns, o, AMLM_WAVE);
+      join += __shfl_xor(join, o, AMLM_WAVE);
+    }
+    if (lane != 0 || p1 == p0) continue;
+    unsigned long long w = (unsigned long long)kAlgElem * (p1 - p0) + (unsigned long long)kAlgElem * join;
+    if (mp.col_gs >= 0 && ns >= k) {
+      // tau: the earliest sender edge (senders exclude v); then u's
+      // destinations in (tau, t] until k distinct ones
+      uint32_t j = p0;
+      while (g.in_nbr[j] == v) j++;
+      const int32_t tau = g.in_t[j];
+      const uint32_t urs = g.out_ptr[u], ure = g.out_ptr[u + 1];
+      const uint32_t d0 = upper_bound_i32(g.out_t, urs, ure, tau), d1 = upper_bound_i32(g.out_t, d0, ure, t);
+      uint32_t c = d0, nd = 0;
+      for (; c < d1 && nd < k; c++) nd += g.out_prv[c] <= tau;
+      w += (unsigned long long)kAlgElem * (c - d0);
+    }
+    mp.work[kWorkSg * mp.stride + eid] = w;
   }
 }
 
@@ -535,16 +625,23 @@ __global__ void k_unit_fill(MineParams mp, const uint32_t *items, const uint32_t
   }
 }
 
-// GS_k of the split anchors from their accumulated sender counts.
+// GS_k of the split anchors from their accumulated sender counts, and the
+// ceiling on both of their accumulated columns.
 __global__ void k_split_gs(MineParams mp, const uint32_t *items, const uint32_t *n_items_p, const uint32_t *nsub,
                            const uint8_t *flags_sg) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *n_items_p || nsub[i] == 0) return;
-  const uint32_t q = items[i];
-  uint32_t *c = mp.counts + (uint64_t)mp.col_gs * mp.stride + mp.g.in_eid[q];
-  const uint32_t ns = *c;
-  const bool d_ok = (flags_sg[q] & kFlagGsDest) != 0;  // split anchors have k >= 2
-  *c = ns >= k_of(mp, mp.g.in_dst[q]) && d_ok ? ns : 0u;
+  const uint32_t q = items[i], eid = mp.g.in_eid[q];
+  if (mp.col_gs >= 0) {
+    uint32_t *c = mp.counts + (uint64_t)mp.col_gs * mp.stride + eid;
+    const uint32_t ns = *c;
+    const bool d_ok = (flags_sg[q] & kFlagGsDest) != 0;  // split anchors have k >= 2
+    *c = ns >= k_of(mp, mp.g.in_dst[q]) && d_ok ? min(ns, mp.ceil) : 0u;
+  }
+  if (mp.col_sg >= 0) {
+    uint32_t *c = mp.counts + (uint64_t)mp.col_sg * mp.stride + eid;
+    *c = min(*c, mp.ceil);
+  }
 }
 
 // Units: with `units` NULL (static schedule) unit c is the block of items
@@ -628,14 +725,16 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
       uint32_t eid = L.i_eid[lane];
       if (heavy) {
         // a slice: partial SG_k, and its senders towards the GS_k of k_split_gs
-        if (mp.col_sg >= 0 && sg) credit(mp.counts + (uint64_t)mp.col_sg * mp.stride + eid, sg, mp.err);
+        // (plain adds: the sums are at most the number of accounts; the
+        // ceiling is applied by k_split_gs)
+        if (mp.col_sg >= 0 && sg) atomicAdd(mp.counts + (uint64_t)mp.col_sg * mp.stride + eid, sg);
         const uint32_t ns = L.i_ns[lane];
-        if (mp.col_gs >= 0 && ns) credit(mp.counts + (uint64_t)mp.col_gs * mp.stride + eid, ns, mp.err);
+        if (mp.col_gs >= 0 && ns) atomicAdd(mp.counts + (uint64_t)mp.col_gs * mp.stride + eid, ns);
       } else {
-        if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = sg;
-        if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = gs;
+        if (mp.col_sg >= 0) mp.counts[(uint64_t)mp.col_sg * mp.stride + eid] = min(sg, mp.ceil);
+        if (mp.col_gs >= 0) mp.counts[(uint64_t)mp.col_gs * mp.stride + eid] = min(gs, mp.ceil);
       }
-      if (mp.work) atomicAdd(&mp.work[eid], work);
+      if (mp.work) atomicAdd(&mp.work[kWorkSgImpl * mp.stride + eid], (unsigned long long)work);
     }
   }
 }
@@ -677,9 +776,9 @@ template <class S_t>
 __device__ __forceinline__ void cyc_credit_path(const MineParams &mp, const S_t &S, uint32_t i, uint32_t slot,
                                                 uint32_t len, uint32_t inc) {
   uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)len - 2) * mp.stride;
-  credit(col + S.r_eid[S.fr[i].root[slot]], inc, mp.err);
+  credit(col + S.r_eid[S.fr[i].root[slot]], inc, mp.ceil);
   for (uint32_t j = i; j >= 1; j--) {
-    credit(col + S.fr[j].eid[slot], inc, mp.err);
+    credit(col + S.fr[j].eid[slot], inc, mp.ceil);
     slot = S.fr[j].par[slot];
   }
 }
@@ -717,14 +816,22 @@ __device__ void cyc_prepare(const MineParams &mp, S_t &S, uint32_t i) {
       if (qb > qa) {
         cyc_credit_path(mp, S, i, lane, Lr, qb - qa);
         uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)Lr - 2) * mp.stride;
-        for (uint32_t q = qa; q < qb; q++) credit(col + g.inn_eid[q], 1u, mp.err);
+        for (uint32_t q = qa; q < qb; q++) credit(col + g.inn_eid[q], 1u, mp.ceil);
       }
-      if (mp.work) atomicAdd(&mp.work[mp.stride + S.r_eid[r]], kBytesClosureSearch);
+      if (mp.work) {
+        // one closing search when the head has an out-edge in (tau, t), and
+        // the credits of the cycles found
+        const uint32_t rs = g.out_ptr[h], re = g.out_ptr[h + 1];
+        const uint32_t x0 = upper_bound_i32(g.out_t, rs, re, tau);
+        unsigned long long w = (unsigned long long)kAlgCycleEdge * Lr * (qb - qa);
+        if (x0 < re && g.out_t[x0] < t) w += kAlgElem * ceil_log2_u32(ure - urs);
+        if (w) atomicAdd(&mp.work[kWorkCyc * mp.stride + S.r_eid[r]], w);
+      }
     } else {
       uint32_t rs = g.out_ptr[h], re = g.out_ptr[h + 1];
       xb = upper_bound_i32(g.out_t, rs, re, tau);
       nsz = lower_bound_i32(g.out_t, xb, re, t) - xb;
-      if (mp.work) atomicAdd(&mp.work[mp.stride + S.r_eid[r]], kBytesPathNode + kBytesPathEntry * nsz);
+      if (mp.work && nsz) atomicAdd(&mp.work[kWorkCyc * mp.stride + S.r_eid[r]], (unsigned long long)kAlgCycElem * nsz);
     }
   }
   uint32_t incl = wave_incl_scan(nsz);
@@ -794,7 +901,9 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
         if (w == S.r_u[F.root[a]]) {
           // closing hop: a cycle of sp + 2 edges
           cyc_credit_path(mp, S, sp, a, sp + 2, 1u);
-          credit(mp.counts + (uint64_t)(mp.col_cyc + sp) * mp.stride + g.out_eid[pos], 1u, mp.err);
+          credit(mp.counts + (uint64_t)(mp.col_cyc + sp) * mp.stride + g.out_eid[pos], 1u, mp.ceil);
+          if (mp.work) atomicAdd(&mp.work[kWorkCyc * mp.stride + S.r_eid[F.root[a]]],
+                                 (unsigned long long)kAlgCycleEdge * (sp + 2));
         } else if ((uint32_t)sp + 3 <= S.r_L[F.root[a]] && !cyc_on_path(S, sp, a, w)) {
           child = true;
           ceid = g.out_eid[pos];
@@ -872,12 +981,18 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
     e = (x);                        \
     if (e != hipSuccess) return e;  \
   } while (0)
-  const uint32_t Ev = mp.g.Ev;
+  const uint32_t Ev = mp.g.Ev, E = mp.g.E;
   // work-stealing counters and list sizes
   CK(launch_fill_u32(ms.ctr, 0, kCtrWords, s));
+  if (mp.work && E) {
+    // accounting run: every edge row's own bytes
+    const uint32_t ncols = (mp.col_fo >= 0) + (mp.col_fi >= 0) + (mp.col_sg >= 0) + (mp.col_gs >= 0) +
+                           (mp.col_cyc >= 0 ? mp.L - 1 : 0);
+    hipLaunchKernelGGL(k_alg_io, dim3((E + 255) / 256), dim3(256), 0, s, mp, ncols);
+    CK(hipGetLastError());
+  }
   if (Ev == 0) return hipSuccess;
   CK(tm->begin(kStAnchor, s));
-  const uint32_t E = mp.g.E;
   CK(launch_fill_u32((uint32_t *)ms.flags, 0, (Ev + 3) / 4 + (E + 3) / 4, s));
   uint8_t *flags_sg = ms.flags, *flags_cy = ms.flags + 4 * ((Ev + 3) / 4);
   const bool learned = cfg.learned && mp.col_sg >= 0 && mp.k >= 2;
@@ -887,6 +1002,11 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   hipLaunchKernelGGL(k_anchor_in, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, flags_cy, ms.sg_win, feat);
   CK(hipGetLastError());
   CK(tm->end(kStAnchor, s));
+  if (mp.work && (mp.col_sg >= 0 || mp.col_gs >= 0)) {
+    // accounting run: the method's scatter-gather bytes of every anchor
+    hipLaunchKernelGGL(k_alg_sg, dim3(std::min<uint32_t>((Ev + 3) / 4, 65536)), dim3(256), 0, s, mp);
+    CK(hipGetLastError());
+  }
   const bool want_sg = mp.col_sg >= 0 || mp.col_gs >= 0;
   const bool want_cyc = mp.col_cyc >= 0;
   if (!want_sg && !want_cyc) return hipSuccess;
@@ -966,7 +1086,7 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
                          (const uint32_t *)n_units, block, ms.ctr + kCtrSgWork, (const uint4 *)ms.sg_win,
                          (const uint8_t *)flags_sg);
       CK(hipGetLastError());
-      if (mp.col_gs >= 0) {
+      {
         hipLaunchKernelGGL(k_split_gs, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, ms.nsub,
                            (const uint8_t *)flags_sg);
         CK(hipGetLastError());

@@ -122,9 +122,10 @@ def test_errors():
     G.close()
 
 
-def test_hub_heavy_cycles_spill():
-    """A hub with thousands of window out-edges and dense returns forces the
-    cycle search past its LDS pool, through the spill rounds."""
+def test_hub_heavy_cycles_deep_frames():
+    """A hub with thousands of window out-edges and dense returns: search
+    trees far wider than one 64-path frame, so every frame is refilled many
+    times and the depth-first stack runs to its last frame."""
     rng = np.random.default_rng(11)
     n = 6000
     nv = 40
@@ -132,7 +133,7 @@ def test_hub_heavy_cycles_spill():
     dst = rng.integers(0, nv, n).astype(np.uint32)
     ts = W.T0 + rng.integers(0, 4000, n).astype(np.int64)
     g = W.EdgeList(src, dst, ts, np.zeros(n, np.float32), nv)
-    assert_same(gpu_mine(g, 400, 5, 3), oracle_mine(g, 400, 5, 3), "dense spill")
+    assert_same(gpu_mine(g, 400, 5, 3), oracle_mine(g, 400, 5, 3), "dense hub")
 
 
 def _heavy_sender_graph(seed, n_senders=300, n_anchors=6, n_noise=4000):
