@@ -180,7 +180,8 @@ amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
  * recorded events and returns milliseconds per stage in ms[8]: 0 graph
  * build, 1 anchor pass, 2 work-list compaction, 3 scatter-gather kernel,
  * 4 cycle kernel, 5 cost model inference, 6 work units of the learned
- * schedule; -1 for a stage that did not run. */
+ * schedule, 7 the whole mining (first mining kernel to the last, the
+ * overlapped cycle stream included); -1 for a stage that did not run. */
 amlm_status amlm_set_timing(amlm_graph *g, int enable);
 amlm_status amlm_stage_times(amlm_graph *g, float *ms);
 

@@ -1,0 +1,89 @@
+"""The oracle over disjoint anchor ranges in parallel processes (test
+infrastructure only, like the rest of this package).
+
+Each worker mines the anchors of one contiguous edge-id range with the plain
+single-threaded oracle (``mine_ex`` with ``a_lo, a_hi``).  The anchored
+columns (FAN_OUT, FAN_IN, SG, GS) of different ranges are disjoint; cycles are
+enumerated once, from their last edge, so a cycle is found by exactly one
+worker and its credits to every one of its edges add up across workers.  The
+merge therefore sums the cycle columns in 64 bits and saturates once, which
+gives the full mining exactly.
+
+Workers are forked: the edge arrays are shared copy-on-write, and the caller
+must not have initialised a GPU runtime in this process.
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+import time
+
+import numpy as np
+
+from . import CYC, FAN_IN, FAN_OUT, GS, SG, mine_ex, num_columns
+
+_ARGS = None   # set in the parent before forking; read by the workers
+
+
+def _anchored_columns(patterns):
+    return sum(1 for b in (FAN_OUT, FAN_IN, SG, GS) if patterns & b)
+
+
+def _worker(rng):
+    src, dst, ts, nv, patterns, delta, L, k, ceiling = _ARGS
+    lo, hi = rng
+    t0 = time.perf_counter()
+    out, _, sec = mine_ex(src, dst, ts, nv, patterns, delta, L, k, a_lo=lo, a_hi=hi, ceiling=ceiling)
+    na = _anchored_columns(patterns)
+    anchored = np.ascontiguousarray(out[:na, lo:hi])
+    cyc = []
+    for c in range(na, out.shape[0]):
+        idx = np.flatnonzero(out[c]).astype(np.uint32)
+        cyc.append((idx, out[c, idx]))
+    return lo, hi, anchored, cyc, sec, time.perf_counter() - t0
+
+
+def default_procs():
+    """Worker count: the host's cores, at most 16 (a GPU machine's CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def mine_parallel(src, dst, ts, n_vertices, patterns, delta, L, k, procs=None, ranges=None, ceiling=0):
+    """All columns of every edge by ``procs`` workers over disjoint anchor
+    ranges (default: ``procs`` equal ranges of edge ids).  Returns (counts
+    uint32 [ncols, n], info) where info holds the ranges, each worker's
+    anchor-loop seconds (graph set-up excluded) and its wall seconds."""
+    global _ARGS
+    n = len(src)
+    procs = procs or default_procs()
+    if ranges is None:
+        cuts = np.linspace(0, n, procs + 1).round().astype(np.int64)
+        ranges = [(int(cuts[i]), int(cuts[i + 1])) for i in range(procs)]
+    ncols = num_columns(patterns, L)
+    na = _anchored_columns(patterns)
+    cap = 0xFFFFFFFF if ceiling == 0 else int(ceiling)
+    _ARGS = (np.ascontiguousarray(src, np.uint32), np.ascontiguousarray(dst, np.uint32),
+             np.ascontiguousarray(ts, np.int64), int(n_vertices), int(patterns), int(delta), int(L), int(k),
+             int(ceiling))
+    counts = np.zeros((ncols, n), dtype=np.uint32)
+    acc = np.zeros((ncols - na, n), dtype=np.uint64) if ncols > na else None
+    info = {"procs": procs, "ranges": [], "loop_s": [], "wall_s": []}
+    ctx = mp.get_context("fork")
+    try:
+        with ctx.Pool(min(procs, len(ranges))) as pool:
+            for lo, hi, anchored, cyc, sec, wall in pool.imap_unordered(_worker, ranges):
+                counts[:na, lo:hi] = anchored
+                for c, (idx, val) in enumerate(cyc):
+                    acc[c, idx] += val.astype(np.uint64)   # idx: distinct within one worker
+                info["ranges"].append((lo, hi))
+                info["loop_s"].append(sec)
+                info["wall_s"].append(wall)
+    finally:
+        _ARGS = None
+    if acc is not None:
+        counts[na:] = np.minimum(acc, np.uint64(cap)).astype(np.uint32)
+    return counts, info

@@ -217,7 +217,7 @@ def amlm_mine_work(g: Graph, p: amlm_params, counts=None, work=None, stream=None
     return counts, work
 
 
-STAGES = ["build", "anchor", "lists", "sg", "cyc", "model", "units", "unused7"]
+STAGES = ["build", "anchor", "lists", "sg", "cyc", "model", "units", "mine"]
 
 
 def amlm_set_timing(g: Graph, enable: bool = True):

@@ -41,6 +41,18 @@ constexpr int kBloomK = AMLM_BLOOM_K;                   // bits set per key, all
 constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
 constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave
+#ifndef AMLM_REV_RATIO
+#define AMLM_REV_RATIO 16
+#endif
+// a pair's join iterates the gather side when the sender's out-window is
+// more than this many times longer
+constexpr uint32_t kRevRatio = AMLM_REV_RATIO;
+#ifndef AMLM_EAGER_NEED
+#define AMLM_EAGER_NEED 1
+#endif
+// pairs that need at most this many intermediates besides u confirm their
+// filter hits after every scan step (early exit), the others in batches of 64
+constexpr uint32_t kEagerNeed = AMLM_EAGER_NEED;
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
 constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
@@ -124,7 +136,7 @@ struct MineLaunch {
 
 
 // Optional HIP-event timing of the stages (recorded on the mining stream).
-enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kStUnits = 6, kNumStages = 8 };
+enum { kStBuild = 0, kStAnchor = 1, kStLists = 2, kStSg = 3, kStCyc = 4, kStModel = 5, kStUnits = 6, kStMine = 7, kNumStages = 8 };
 struct StageTimer {
   bool on = false;
   hipEvent_t ev[2 * kNumStages] = {};
@@ -152,6 +164,8 @@ constexpr uint32_t kBytesSenderEntry = 12;   // in-window of u: neighbour, next-
 constexpr uint32_t kBytesGatherEntry = 4;    // in-window of v: neighbour id
 constexpr uint32_t kBytesJoinEntry = 4;      // out-window of a sender: neighbour id
 constexpr uint32_t kBytesScatterEntry = 4;   // out-window of u after tau: previous-same-pair time
+constexpr uint32_t kBytesRevEntry = 20;      // gather entry of the reverse join: neighbour, next time,
+                                             // time, and the key found by the search
 // The method's algorithmic bytes (kWorkIo .. kWorkCyc): an element of a
 // scanned slice is a neighbour id and a time, 8 bytes, 12 in the cycle scan
 // (plus the edge id it credits); an edge row is read as (src, dst, ts) and

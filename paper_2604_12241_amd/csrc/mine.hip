@@ -268,6 +268,7 @@ struct SgLds {
   // (anchor, sender) pairs of one batch
   uint32_t pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
   uint8_t pr_item[AMLM_WAVE];
+  uint8_t pr_rev[AMLM_WAVE];   // 1: the pair joins from the gather side (sg_join_rev)
   // Bloom-positive candidates awaiting the exact check
   uint32_t cq_pos[kCandCap];
   uint8_t cq_pair[kCandCap];  // byte-wide slot fields keep the LDS, and so the waves per CU, in bounds
@@ -355,18 +356,66 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
   }
 }
 
+// Reverse join of the pairs in `rev` (degree-ordered intersection, Section
+// 6: the smaller side is iterated).  Pair `slot` holds the sender in pr_b and
+// the length of its anchor's gather window [r0, r1) (v's in-edges in
+// [t - delta, t]) in pr_n.  Lanes are flattened over (pair, gather entry);
+// an entry is the intermediate m's last edge into v at or before t (its
+// next same-pair time is past t), so each distinct m is tried once, and m
+// counts when the sender's first edge to m inside the window, found by a
+// search in m's neighbour-sorted in-row, comes before that edge (ordered) or
+// before t (unordered).  A pair stops once k - 1 intermediates besides u
+// have qualified.
+__device__ void sg_join_rev(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, uint32_t need) {
+  const GraphView &g = mp.g;
+  const uint32_t lane = lane_id();
+  const bool mine = (rev >> lane) & 1ull;
+  const uint32_t nr = mine ? L.pr_n[lane] : 0u;
+  const uint32_t incl = wave_incl_scan(nr);
+  const uint32_t T = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
+  L.pr_off[lane] = incl - nr;
+  for (uint32_t f0 = 0; f0 < T; f0 += AMLM_WAVE) {
+    const uint32_t f = f0 + lane;
+    if (f < T) {
+      const uint32_t a = owner_of(L.pr_off, np, f);
+      if (L.pr_cnt[a] < need) {
+        const uint32_t it = L.pr_item[a];
+        const uint32_t j = L.i_r0[it] + (f - L.pr_off[a]);
+        const uint32_t m = g.in_nbr[j];
+        const int32_t t = L.i_t[it];
+        if (m != L.i_u[it] && g.in_nxt[j] > t) {
+          const uint32_t s = L.pr_b[a];
+          const int32_t lo = L.i_lo[it] < 0 ? 0 : L.i_lo[it];
+          const uint64_t key = nbr_key(s, lo);
+          const uint32_t ms = g.in_ptr[m], me = g.in_ptr[m + 1];
+          // first (s, time >= lo) key of m's row: after every key <= key - 1
+          const uint32_t qa = key ? upper_bound_u64_interp(g.inn_key, ms, me, key - 1) : ms;
+          if (qa < me) {
+            const uint64_t kk = g.inn_key[qa];
+            const int32_t ta = (int32_t)(uint32_t)kk;
+            if ((uint32_t)(kk >> 32) == s && ta < (mp.sg_unordered ? t : g.in_t[j])) atomicAdd(&L.pr_cnt[a], 1u);
+          }
+        }
+      }
+    }
+    // every pair done: stop early
+    if (__ballot(lane < np && ((rev >> lane) & 1ull) && L.pr_cnt[lane] < need) == 0) break;
+  }
+}
+
 // Join one batch of np (anchor, sender) pairs: pair `slot` (= lane) holds
 // its slice [pr_b, pr_b + pr_n) of the sender's out-row.  Long slices are
 // scanned one pair at a time by the whole wave with the pair's fields in
 // scalar registers; short ones are flattened over the lanes.
-__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre,
-                        uint32_t k) {
+__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, int shift, uint32_t vrs,
+                        uint32_t vre, uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint32_t need = k - 1;  // intermediates needed besides u
   uint32_t cq = 0;
   constexpr int U = kJoinUnroll;  // independent 256-byte loads in flight per wave
-  const uint32_t my_n = lane < np ? L.pr_n[lane] : 0u;
+  const bool my_rev = (rev >> lane) & 1ull;
+  const uint32_t my_n = lane < np && !my_rev ? L.pr_n[lane] : 0u;
   uint64_t longs = __ballot(my_n >= kLongPair);
   while (longs) {
     uint32_t a = __ffsll((long long)longs) - 1;
@@ -393,6 +442,11 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, 
         for (int r = 0; r < U; r++) h[r] = f0 + r * AMLM_WAVE + lane < n ? src[r * AMLM_WAVE] : hu;
         step();
       }
+      if (need <= kEagerNeed && cq > 0) {
+        // few intermediates needed: confirm now, so the scan can stop
+        sg_verify(mp, L, cq, cq, vrs, vre);
+        cq = 0;
+      }
     }
   }
   // short pairs, flattened
@@ -413,12 +467,17 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, int shift, 
       }
     }
     sg_push(mp, L, cq, cand, a, pos, vrs, vre);
+    if (need <= kEagerNeed && cq > 0) {
+      sg_verify(mp, L, cq, cq, vrs, vre);
+      cq = 0;
+    }
   }
   while (cq > 0) {
     uint32_t take = min(cq, (uint32_t)AMLM_WAVE);
     sg_verify(mp, L, cq, take, vrs, vre);
     cq -= take;
   }
+  if (rev) sg_join_rev(mp, L, np, rev, need);
 }
 
 // Anchors [s0, s1) of the chunk, all into vertex v.
@@ -487,23 +546,36 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     if (!bs) continue;
     // this lane's pair: slice of s's out-row inside [lo, t)
     uint32_t b = 0, n = 0;
+    bool rv = false;
     if (pair) {
       // s's out-window [lo, t) contains the s -> u edge: search outwards from it
       const uint32_t rs = g.out_ptr[nb], re = g.out_ptr[nb + 1];
       const uint4 m = g.out_tm[nb];
       b = tix_lower_bound(g.out_t, g.out_tix, m, rs, re, L.i_lo[it]);
       n = tix_lower_bound(g.out_t, g.out_tix, m, rs, re, L.i_t[it]) - b;
-      if (mp.work) atomicAdd(&L.i_work[it], kBytesJoinEntry * n);
+      // the smaller side: v's gather window when it is much shorter than
+      // the sender's out-window (a gather entry costs a search, a scanned
+      // out-entry one load and a filter test)
+      const uint32_t r = L.i_r1[it] - L.i_r0[it];
+      rv = (uint64_t)r * kRevRatio < n;
+      if (rv) {
+        b = nb;
+        n = r;
+      }
+      if (mp.work) atomicAdd(&L.i_work[it], rv ? kBytesRevEntry * n : kBytesJoinEntry * n);
     }
     uint32_t np = __popcll(bs);
     if (pair) {
       uint32_t slot = __popcll(bs & lt);
       L.pr_item[slot] = (uint8_t)it;
+      L.pr_rev[slot] = rv ? 1 : 0;
       L.pr_b[slot] = b;
       L.pr_n[slot] = n;
       L.pr_cnt[slot] = 0;
     }
-    sg_join(mp, L, np, shift, vrs, vre, k);
+    // reverse pairs by slot
+    const uint64_t rev = __ballot(lane < np && L.pr_rev[lane] != 0);
+    sg_join(mp, L, np, rev, shift, vrs, vre, k);
     if (lane < np && L.pr_cnt[lane] >= k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
   }
 }
@@ -971,10 +1043,8 @@ __global__ void k_flag_scatter(const uint8_t *flags, uint32_t n, const uint32_t 
 
 // ====================================================================== host
 
-hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &cfg, hipStream_t s,
-                       StageTimer *tm) {
-  StageTimer none;
-  if (!tm) tm = &none;
+static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineLaunch &cfg, hipStream_t s,
+                              StageTimer *tm) {
   hipError_t e;
 #define CK(x)                       \
   do {                              \
@@ -1105,6 +1175,18 @@ hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &
   if (cfg.aux && want_cyc && !want_sg) CK(hipStreamWaitEvent(s, cfg.ev_join, 0));
 #undef CK
   return hipSuccess;
+}
+
+hipError_t mine_launch(const MineParams &mp, MineScratch &ms, const MineLaunch &cfg, hipStream_t s,
+                       StageTimer *tm) {
+  StageTimer none;
+  if (!tm) tm = &none;
+  // the whole mining, first kernel to last, on the mining stream (the
+  // auxiliary stream is joined back before the end)
+  hipError_t e = tm->begin(kStMine, s);
+  if (e == hipSuccess) e = mine_stages(mp, ms, cfg, s, tm);
+  if (e == hipSuccess) e = tm->end(kStMine, s);
+  return e;
 }
 
 const void *k_sg_ptr() { return (const void *)k_sg; }

@@ -353,6 +353,21 @@ def test_anchor_ranges_add_up(mid_small):
     np.testing.assert_array_equal(acc, full)
 
 
+@pytest.mark.parametrize("pats,ceiling", [(oracle.ALL, 0), (oracle.SG | oracle.CYC, 0), (oracle.ALL, 3)])
+def test_parallel_driver_equals_one_process(mid_small, pats, ceiling):
+    """The multi-process driver (disjoint anchor ranges, cycle credits summed
+    then saturated) gives the single-process result, uneven ranges included."""
+    from oracle.parallel import mine_parallel
+    g = mid_small
+    full, _, _ = oracle.mine_ex(g.src, g.dst, g.ts, g.n_vertices, pats, 86400, 5, 2, ceiling=ceiling)
+    got, info = mine_parallel(g.src, g.dst, g.ts, g.n_vertices, pats, 86400, 5, 2, procs=3, ceiling=ceiling)
+    np.testing.assert_array_equal(got, full)
+    assert sorted(info["ranges"])[0][0] == 0 and sorted(info["ranges"])[-1][1] == g.n_edges
+    got, _ = mine_parallel(g.src, g.dst, g.ts, g.n_vertices, pats, 86400, 5, 2, procs=2, ceiling=ceiling,
+                           ranges=[(0, 7), (7, 7), (7, 12000), (12000, g.n_edges)])
+    np.testing.assert_array_equal(got, full)
+
+
 # ---------------------------------------------------------------- algorithmic bytes
 
 from tests.brute import brute_work  # noqa: E402
