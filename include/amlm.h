@@ -320,41 +320,58 @@ amlm_status amlm_mlp_grad(const float *weights, const float *x, const float *y, 
 typedef struct amlm_server amlm_server;
 
 /*
- * A server keeps the edges of `resident` plus every submitted batch in HBM
- * and mines each submitted batch incrementally (Section 5, streaming): the
- * new edges' own columns come from instances that end at them; cycles closed
- * by a new edge also credit older edges, which are reported as sparse
- * deltas.  Batches must be strictly later in time than everything before
- * them (AMLM_E_ORDER otherwise).  hbm_budget_bytes bounds the device memory
- * the in-flight batches may hold (0 = no bound); max_slots bounds how many
- * batches are mined concurrently, each on its own HIP stream.
+ * A server mines each submitted batch incrementally against a sliding
+ * window of the graph (Section 5, streaming): the new edges' own columns
+ * come from instances that end at them; cycles closed by a new edge also
+ * credit older edges, which are reported as sparse deltas.  Every search is
+ * bounded above by its anchor's time, so a batch needs only the edges of the
+ * last delta before it: the server keeps those (from `resident` and earlier
+ * batches) in one window store, appends queued batches to it in groups and
+ * drops edges that left the window, so its memory follows the window, not
+ * the stream's length.  Batches must be strictly later in time than
+ * everything before them (AMLM_E_ORDER otherwise), `resident` included.
+ * hbm_budget_bytes bounds the device memory the batches being mined may
+ * hold for their counts (0 = no bound; one batch is always admitted);
+ * max_slots (1..16) bounds how many batches are mined concurrently, each on
+ * its own HIP stream.  `resident` is read during this call only.
  */
 amlm_status amlm_server_create(amlm_graph *resident, const amlm_params *p, uint64_t hbm_budget_bytes,
                                uint32_t max_slots, amlm_server **out);
 
-/* Copy a batch of n host edges, order it after the previous batches, and
- * start mining it as soon as a slot and budget are free (Section 5,
- * streaming; blocking when wait != 0, else AMLM_E_BUSY).  *ticket
- * identifies the batch. */
+/* Copy a batch of n host edges, order it after the previous batches
+ * (Section 5, streaming) and queue it; it is mined once it is in the window
+ * store and a slot and budget are free.  With 64 * max_slots batches
+ * queued, blocks when wait != 0, else returns AMLM_E_BUSY.  *ticket
+ * identifies the batch.  AMLM_E_INVALID for an endpoint >= n_vertices,
+ * AMLM_E_RANGE for a batch spanning >= 2^31 - 1 - delta time units. */
 amlm_status amlm_server_submit(amlm_server *s, const uint32_t *src, const uint32_t *dst,
                                const int64_t *ts, uint64_t n, int wait, uint64_t *ticket);
 
 /*
  * Wait for a batch (Section 5, streaming).  new_counts_host: [ncols][n] for
- * the batch's own edges (host memory, may be NULL).  Deltas for older edges:
- * up to cap entries of (edge id, column, increment); *n_deltas gets the
- * total number (entries past cap are dropped; size cap generously).  Edge
- * ids of stream edges continue after the resident graph's: n_edges +
- * running index.  The batch's results are released by this call.
+ * the batch's own edges in submitted order (host memory, may be NULL).
+ * Deltas for older edges: up to cap entries of (edge id, column,
+ * increment), sorted by (edge id, column); *n_deltas gets the total number
+ * (entries past cap are dropped; size cap generously).  Edge ids of stream
+ * edges continue after the resident graph's: n_edges + running index in
+ * submission order.  The batch's results are released by this call (a
+ * second wait on the ticket is AMLM_E_INVALID); its timing record stays for
+ * the 65536 most recently waited tickets.
  */
 amlm_status amlm_server_wait(amlm_server *s, uint64_t ticket, uint32_t *new_counts_host,
                              uint64_t *n_deltas, uint64_t *delta_eid, uint32_t *delta_col,
                              uint32_t *delta_val, uint64_t cap);
 
-/* Per-ticket timing (host wall clock, seconds): submit -> admitted ->
- * finished (no paper passage; for latency measurements). */
+/* Per-ticket timing (host wall clock, seconds): submit -> admitted to a
+ * slot -> finished (no paper passage; for latency measurements). */
 amlm_status amlm_server_ticket_times(amlm_server *s, uint64_t ticket, double *t_submit,
                                      double *t_admit, double *t_done);
+
+/* Window store figures (no paper passage): edges in the current window
+ * store, the most it has held, group commits and batches mined so far.
+ * Pointers may be NULL. */
+amlm_status amlm_server_stats(amlm_server *s, uint64_t *window_edges, uint64_t *max_window_edges,
+                              uint64_t *commits, uint64_t *batches_done);
 
 /* Stop the server's slots and free everything it holds. */
 void amlm_server_destroy(amlm_server *s);

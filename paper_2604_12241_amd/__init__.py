@@ -32,6 +32,7 @@ EXPORTS = [
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
     "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy", "amlm_mlp_predict",
     "amlm_tune_set", "amlm_graph_status", "amlm_graph_set_ceiling", "amlm_graph_inject_device_error",
+    "amlm_server_stats",
 ]
 
 
@@ -84,6 +85,8 @@ def lib():
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double)]),
             "amlm_server_destroy": (None, [p]),
+            "amlm_server_stats": (st, [p, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                       ctypes.POINTER(u64)]),
             "amlm_last_error": (ctypes.c_char_p, []),
             "amlm_set_timing": (st, [p, ctypes.c_int]),
             "amlm_tune_set": (st, [p, u32, u32, u32, u32]),
@@ -325,16 +328,25 @@ class Server:
         return t.value
 
     def wait(self, ticket: int, cap: int = 1 << 22):
-        n = self.sizes[ticket]
-        counts = np.zeros((self.ncols, n), np.uint32)
+        n = self.sizes.pop(ticket)
+        counts = np.empty((self.ncols, n), np.uint32)   # every entry is written
         nd = ctypes.c_uint64()
-        de = np.zeros(cap, np.uint64)
-        dc = np.zeros(cap, np.uint32)
-        dv = np.zeros(cap, np.uint32)
+        # only the first n_deltas entries are written (untouched pages of the
+        # rest are never committed)
+        de = np.empty(cap, np.uint64)
+        dc = np.empty(cap, np.uint32)
+        dv = np.empty(cap, np.uint32)
         _check(lib().amlm_server_wait(self.handle, ticket, _ptr(counts), ctypes.byref(nd), _ptr(de), _ptr(dc),
                                       _ptr(dv), cap))
         m = min(nd.value, cap)
         return counts, (de[:m], dc[:m], dv[:m]), nd.value
+
+    def stats(self) -> dict:
+        """Edges in the current window store, the most it held, group commits
+        and batches mined so far."""
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().amlm_server_stats(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("window_edges", "max_window_edges", "commits", "batches_done"), (x.value for x in v)))
 
     def times(self, ticket: int):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

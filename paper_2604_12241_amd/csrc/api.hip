@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 
@@ -126,30 +127,35 @@ static amlm_status alloc_graph(amlm_graph *g, uint64_t E, uint32_t V) {
 
 // Mining scratch, sized for the graph's edge capacity (so allocated once per
 // graph allocation).
-amlm_status alloc_mine_scratch(amlm_graph *g) {
-  MineScratch &ms = g->ms;
-  if (ms.flags && ms.cap_ev >= std::max<uint64_t>(g->Ev, 1) && ms.cap_e >= g->E) return AMLM_OK;
-  const uint64_t ev = std::max<uint64_t>(g->cap_e, 1);
+amlm_status alloc_scratch(MineScratch &ms, uint64_t cap,
+                          const std::function<amlm_status(void **, size_t)> &alloc) {
+  const uint64_t ev = std::max<uint64_t>(cap, 1);
   uint32_t nb = (uint32_t)((ev + kFlagTile - 1) / kFlagTile);
-  A_TRY(dalloc(g, (void **)&ms.flags, 2 * ((ev + 3) & ~3ull)));
-  A_TRY(dalloc(g, (void **)&ms.sg_win, 16 * ev));
-  A_TRY(dalloc(g, (void **)&ms.feat, 4 * kMlpRaw * ev));
-  A_TRY(dalloc(g, (void **)&ms.pred, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.list_sg, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.list_cy, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.bcnt_sg, 4 * (size_t)nb));
-  A_TRY(dalloc(g, (void **)&ms.bcnt_cy, 4 * (size_t)nb));
-  A_TRY(dalloc(g, (void **)&ms.boff_sg, 4 * (size_t)nb));
-  A_TRY(dalloc(g, (void **)&ms.boff_cy, 4 * (size_t)nb));
-  A_TRY(dalloc(g, (void **)&ms.scan_tmp, 4 * std::max(scan_tmp_words(nb), scan_tmp_words(ev))));
-  A_TRY(dalloc(g, (void **)&ms.ctr, 4 * kCtrWords));
-  A_TRY(dalloc(g, (void **)&ms.nsub, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.ucnt, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.uoff, 4 * ev));
-  A_TRY(dalloc(g, (void **)&ms.units, 8 * max_units(ev, kMinBlock)));
+  A_TRY(alloc((void **)&ms.flags, 2 * ((ev + 3) & ~3ull)));
+  A_TRY(alloc((void **)&ms.sg_win, 16 * ev));
+  A_TRY(alloc((void **)&ms.feat, 4 * kMlpRaw * ev));
+  A_TRY(alloc((void **)&ms.pred, 4 * ev));
+  A_TRY(alloc((void **)&ms.list_sg, 4 * ev));
+  A_TRY(alloc((void **)&ms.list_cy, 4 * ev));
+  A_TRY(alloc((void **)&ms.bcnt_sg, 4 * (size_t)nb));
+  A_TRY(alloc((void **)&ms.bcnt_cy, 4 * (size_t)nb));
+  A_TRY(alloc((void **)&ms.boff_sg, 4 * (size_t)nb));
+  A_TRY(alloc((void **)&ms.boff_cy, 4 * (size_t)nb));
+  A_TRY(alloc((void **)&ms.scan_tmp, 4 * std::max(scan_tmp_words(nb), scan_tmp_words(ev))));
+  A_TRY(alloc((void **)&ms.ctr, 4 * kCtrWords));
+  A_TRY(alloc((void **)&ms.nsub, 4 * ev));
+  A_TRY(alloc((void **)&ms.ucnt, 4 * ev));
+  A_TRY(alloc((void **)&ms.uoff, 4 * ev));
+  A_TRY(alloc((void **)&ms.units, 8 * max_units(ev, kMinBlock)));
   ms.cap_ev = ev;
   ms.cap_e = ev;
   return AMLM_OK;
+}
+
+amlm_status alloc_mine_scratch(amlm_graph *g) {
+  MineScratch &ms = g->ms;
+  if (ms.flags && ms.cap_ev >= std::max<uint64_t>(g->Ev, 1) && ms.cap_e >= g->E) return AMLM_OK;
+  return alloc_scratch(ms, g->cap_e, [g](void **p, size_t bytes) { return dalloc(g, p, bytes); });
 }
 
 GraphView graph_view(const amlm_graph *g) {
@@ -368,6 +374,7 @@ MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *coun
   mp.vgraph = nullptr;
   mp.sub = nullptr;
   mp.anchor_lo = 0;
+  mp.anchor_hi = 0xffffffffu;
   int c = 0;
   mp.col_fo = (p->patterns & AMLM_FAN_OUT) ? c++ : -1;
   mp.col_fi = (p->patterns & AMLM_FAN_IN) ? c++ : -1;
@@ -434,6 +441,43 @@ static amlm_status mine_impl(amlm_graph *g, const amlm_params *p, uint32_t *coun
   }
   HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
   return AMLM_OK;
+}
+
+amlm_status mine_with_scratch(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, MineScratch &ms,
+                              hipStream_t s, uint32_t anchor_lo, uint32_t anchor_hi) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  A_TRY(check_params(p));
+  if (g->E && !counts_dev) {
+    set_error("null counts");
+    return AMLM_E_INVALID;
+  }
+  A_TRY(sticky_check(g));
+  if (ms.cap_e < g->E || ms.cap_ev < std::max<uint64_t>(g->Ev, 1)) {
+    set_error("mining scratch too small for the graph");
+    return AMLM_E_INVALID;
+  }
+  const uint32_t ncols = amlm_num_columns(p);
+  auto run = [&]() -> amlm_status {
+    HIP_TRY(launch_fill_u32(counts_dev, 0, (uint64_t)ncols * g->E, s));
+    MineParams mp = make_params(g, p, counts_dev, nullptr);
+    mp.anchor_lo = anchor_lo;
+    mp.anchor_hi = anchor_hi;
+    MineLaunch cfg = default_launch(g);
+    if (p->schedule == AMLM_SCHED_LEARNED) {
+      if (!global_model().loaded) {
+        set_error("the learned schedule needs a cost model (amlm_costmodel_train or _load)");
+        return AMLM_E_INVALID;
+      }
+      cfg.learned = true;
+      cfg.delta_hours = (float)p->delta / 3600.f;
+    }
+    HIP_TRY(mine_launch(mp, ms, cfg, s, nullptr));
+    return AMLM_OK;
+  };
+  return sticky_note(g, run());
 }
 
 amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,

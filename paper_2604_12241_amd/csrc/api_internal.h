@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,13 @@ GraphView graph_view(const amlm_graph *g);
 MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, unsigned long long *work);
 MineLaunch default_launch(const amlm_graph *g);
 amlm_status alloc_mine_scratch(amlm_graph *g);
+// Mining scratch for graphs of up to cap edges, each buffer from `alloc`.
+amlm_status alloc_scratch(MineScratch &ms, uint64_t cap, const std::function<amlm_status(void **, size_t)> &alloc);
+// Mining of the anchors with ids in [anchor_lo, anchor_hi) with the caller's
+// scratch (sized for g by alloc_scratch) on stream s only: several calls may
+// run concurrently on one graph, each with its own scratch and counts.
+amlm_status mine_with_scratch(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, MineScratch &ms,
+                              hipStream_t s, uint32_t anchor_lo, uint32_t anchor_hi);
 // Mining with the edges of id >= anchor_lo as the only anchors (0 = all).
 amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,
                         hipStream_t s, uint32_t anchor_lo = 0);

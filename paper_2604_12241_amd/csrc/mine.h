@@ -48,11 +48,24 @@ constexpr uint32_t kLongPair = 64;                      // slices scanned by the
 // more than this many times longer
 constexpr uint32_t kRevRatio = AMLM_REV_RATIO;
 #ifndef AMLM_EAGER_NEED
-#define AMLM_EAGER_NEED 1
+#define AMLM_EAGER_NEED 0
 #endif
 // pairs that need at most this many intermediates besides u confirm their
-// filter hits after every scan step (early exit), the others in batches of 64
+// filter hits after every scan step (early exit), the others in batches of
+// 64; 0 (batches only) was measured fastest: a check after every step puts
+// a dependent search on each step's critical path (k_sg 11.0 -> 19.8 ms
+// static on the 32M-edge graph)
 constexpr uint32_t kEagerNeed = AMLM_EAGER_NEED;
+#ifndef AMLM_EAGER_SHORT
+#define AMLM_EAGER_SHORT 1
+#endif
+// eager checks also in the flattened short-pair loop (else long pairs only)
+constexpr bool kEagerShort = AMLM_EAGER_SHORT != 0;
+#ifndef AMLM_CLAIM
+#define AMLM_CLAIM 1
+#endif
+// work units taken per atomic claim of the work-stealing counter
+constexpr uint32_t kClaim = AMLM_CLAIM;
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
 constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
@@ -80,7 +93,7 @@ struct MineParams {
   uint32_t L, k;          // L: the largest cycle length over all sub-graphs
   const uint32_t *vgraph; // batched store: sub-graph of each vertex (else NULL)
   const SubParams *sub;   // batched store: parameters per sub-graph
-  uint32_t anchor_lo;     // only edges with id >= anchor_lo are anchors (0 = all)
+  uint32_t anchor_lo, anchor_hi;  // only edges with ids in [anchor_lo, anchor_hi) are anchors
   int col_fo, col_fi, col_sg, col_gs, col_cyc;  // -1 when not requested
   uint32_t sg_unordered;  // 1: an intermediate's two legs in either order
   uint32_t *counts;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.Ev) return;
   uint32_t eid = g.out_eid[p];
-  if (eid < mp.anchor_lo) return;  // context edge (incremental mining)
+  if (eid < mp.anchor_lo || eid >= mp.anchor_hi) return;  // context edge (incremental mining)
   uint32_t u = g.out_src[p], v = g.out_nbr[p];
   int32_t t = g.out_t[p];
   int32_t lo = window_lo(t, delta_of(mp, u));
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
   uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.Ev) return;
   uint32_t eid = g.in_eid[q];
-  if (eid < mp.anchor_lo) return;
+  if (eid < mp.anchor_lo || eid >= mp.anchor_hi) return;
   uint32_t v = g.in_dst[q], u = g.in_nbr[q];
   int32_t t = g.in_t[q];
   int32_t lo = window_lo(t, delta_of(mp, u));
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
 // edge, each lane scanning its sender's window serially.
 __global__ __launch_bounds__(256) void k_alg_io(MineParams mp, uint32_t ncols) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= mp.g.E || i < mp.anchor_lo) return;
+  if (i >= mp.g.E || i < mp.anchor_lo || i >= mp.anchor_hi) return;
   mp.work[kWorkIo * mp.stride + i] = kAlgEdgeRow + (unsigned long long)kAlgCount * ncols;
 }
 
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_alg_sg(MineParams mp) {
   const uint32_t nw = gridDim.x * (blockDim.x / AMLM_WAVE);
   for (uint32_t q = blockIdx.x * (blockDim.x / AMLM_WAVE) + threadIdx.x / AMLM_WAVE; q < g.Ev; q += nw) {
     const uint32_t eid = g.in_eid[q];
-    if (eid < mp.anchor_lo) continue;
+    if (eid < mp.anchor_lo || eid >= mp.anchor_hi) continue;
     const uint32_t v = g.in_dst[q], u = g.in_nbr[q];
     const int32_t t = g.in_t[q];
     const int32_t lo = window_lo(t, delta_of(mp, u));
@@ -467,7 +467,7 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
       }
     }
     sg_push(mp, L, cq, cand, a, pos, vrs, vre);
-    if (need <= kEagerNeed && cq > 0) {
+    if (kEagerShort && need <= kEagerNeed && cq > 0) {
       sg_verify(mp, L, cq, cq, vrs, vre);
       cq = 0;
     }
@@ -727,10 +727,17 @@ __global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t 
   const uint32_t lane = lane_id();
   const uint32_t n_count = *n_count_p;
   const uint32_t n_units = units ? n_count : (n_count + block - 1) / block;
+  uint32_t c = 0, left = 0;
   for (;;) {
-    uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(ctr, 1u);
-    c = rfl((uint32_t)__shfl(c, 0, AMLM_WAVE));
+    if (left == 0) {
+      // claim kClaim consecutive units
+      if (lane == 0) c = atomicAdd(ctr, kClaim);
+      c = rfl((uint32_t)__shfl(c, 0, AMLM_WAVE));
+      left = kClaim;
+    } else {
+      c++;
+    }
+    left--;
     if (c >= n_units) break;
     const uint2 un = units ? units[c] : make_uint2(c * block, min(block, n_count - c * block));
     const bool heavy = (un.y & kUnitHeavy) != 0;

@@ -117,3 +117,78 @@ def test_stream_errors():
     assert a <= bb <= cc
     S.close()
     R.close()
+
+
+def _accumulate(base, batches, results, r_counts):
+    src = np.concatenate([base.src] + [b.src for b in batches])
+    dst = np.concatenate([base.dst] + [b.dst for b in batches])
+    ts = np.concatenate([base.ts] + [b.ts for b in batches])
+    acc = np.zeros((r_counts.shape[0], src.shape[0]), np.uint64)
+    acc[:, :base.n_edges] = r_counts
+    pos = base.n_edges
+    for (c, (de, dc, dv), nd), b in zip(results, batches):
+        assert nd == de.shape[0]
+        acc[:, pos:pos + b.n_edges] += c
+        np.add.at(acc, (dc.astype(np.int64), de.astype(np.int64)), dv)
+        assert (de < pos).all()
+        pos += b.n_edges
+    return src, dst, ts, acc
+
+
+def test_long_stream_window_store_stays_bounded():
+    """A stream many windows long (delta = 1 h, ~80 000 s of stream time):
+    the window store keeps only the last delta of edges (plus the batches of
+    one group), and the incremental results still add up to the oracle's
+    mining of the union graph.  Includes an empty batch and a batch with
+    self-loops."""
+    delta, L, k = 3600, 5, 2
+    base = W.mid(323, scale=0.002)
+    batches = W.stream_batches(base, seed=78, n_batches=60, b_min=50, b_max=800, rate_per_s=0.25,
+                               zipf_a=2.1, max_degree=40)
+    t1 = int(batches[-1].ts.max())
+    extra = [W.EdgeList(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.int64),
+                        np.zeros(0, np.float32), base.n_vertices),
+             W.EdgeList(np.array([3, 5, 5, 7, 9], np.uint32), np.array([3, 5, 7, 9, 5], np.uint32),
+                        np.array([t1 + 1, t1 + 2, t1 + 3, t1 + 4, t1 + 5], np.int64),
+                        np.zeros(5, np.float32), base.n_vertices)]
+    batches = batches + extra
+    p = A.params(A.AMLM_ALL, delta, L, k)
+    R = A.Graph(base.src, base.dst, base.ts, base.n_vertices)
+    r_counts = A.to_u32(A.amlm_mine(R, p)).astype(np.uint64)
+    S = A.Server(R, p, max_slots=3)
+    res = []
+    for i in range(0, len(batches), 6):          # groups of six in flight
+        tk = [S.submit(b.src, b.dst, b.ts) for b in batches[i:i + 6]]
+        res += [S.wait(t) for t in tk]
+    st = S.stats()
+    S.close()
+    src, dst, ts, acc = _accumulate(base, batches, res, r_counts)
+    full = oracle.mine(src, dst, ts, base.n_vertices, oracle.ALL, delta, L, k)
+    np.testing.assert_array_equal(acc, full.astype(np.uint64))
+    # bounded by the window (plus one group of batches), not by the stream
+    n_stream = sum(b.n_edges for b in batches)
+    per_window = int(np.max([np.sum((ts > t - delta) & (ts <= t)) for t in ts[::97]]))
+    assert st["batches_done"] == len(batches)
+    assert st["max_window_edges"] <= per_window + 6 * 800 + 64
+    assert st["max_window_edges"] < n_stream // 3
+    assert st["commits"] >= 1
+    R.close()
+
+
+def test_server_with_learned_schedule_equals_static():
+    """The learned schedule in the server's slots (own scratch per slot)
+    gives the static schedule's results."""
+    base, batches = _setup()
+    R = A.Graph(base.src, base.dst, base.ts, base.n_vertices)
+    A.amlm_costmodel_train([R], [A.params(A.AMLM_ALL, D, L, K)], epochs=1, batch=256, seed=5)
+    outs = []
+    for sched in (A.AMLM_SCHED_STATIC, A.AMLM_SCHED_LEARNED):
+        S = A.Server(R, A.params(A.AMLM_ALL, D, L, K, sched), max_slots=2)
+        outs.append(_run(S, batches, sequential=False))
+        S.close()
+    for (c1, d1, n1), (c2, d2, n2) in zip(*outs):
+        np.testing.assert_array_equal(c1, c2)
+        assert n1 == n2
+        for x, y in zip(d1, d2):
+            np.testing.assert_array_equal(x, y)
+    R.close()
