@@ -18,6 +18,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 FAN_OUT, FAN_IN, SG, GS, CYC = 1, 2, 4, 8, 16
 ALL = FAN_OUT | FAN_IN | SG | GS | CYC
 SG_UNORDERED = 32  # modifier of SG: the two legs of an intermediate in either order
+DEG_OUT, DEG_IN = 64, 128   # distinct counterparties in the FAN windows (columns after the cycles)
+SG_PHASE = 256     # modifier of SG: every scatter leg before every gather leg
+CYC_ANY_ORDER = 512  # modifier of CYC: the cycle's edges in any order within delta
 
 
 def build_oracle() -> str:

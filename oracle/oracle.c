@@ -31,11 +31,27 @@
  *                tau = earliest ts of an edge into u from s != v in [t-delta, t)
  *                and D(e) = distinct d with u -> d, tau < ts <= t
  *                ("integration occurs after placement", Section 4)
+ *   with OR_SG_PHASE, the legs are ordered by phase instead: every scatter
+ *                leg of the chosen intermediates (u's included) comes before
+ *                every gather leg (the anchor is u's), i.e. SG_k counts the s
+ *                for which some split time tau in (t - delta, t] has u's
+ *                scatter leg before tau and at least k - 1 other m with a
+ *                scatter leg in [t - delta, tau) and a gather leg in
+ *                [tau, t] ("integration occurs after placement", Section 4)
  *   CYC_l(e)   = number of l-cycles containing e, 2 <= l <= L: l edges
  *                c_1..c_l with dst(c_i) = src(c_{i+1}) cyclically, strictly
  *                increasing timestamps, ts(c_l) - ts(c_1) <= delta and
  *                pairwise distinct vertices (the classical temporal motif
  *                special case, Section 6; cycle decomposition, Section 5)
+ *   with OR_CYC_ANY_ORDER, the cycle's edges may occur in any order (the
+ *                anticipatory / out-of-order edges of Section 4): l edges
+ *                forming a directed cycle through l distinct vertices whose
+ *                timestamps span at most delta; each cycle is counted once,
+ *                from its edge of greatest (ts, edge id)
+ *   DEG_OUT(e) = distinct destinations of u's out-edges with ts in W, and
+ *   DEG_IN(e)  = distinct sources of v's in-edges with ts in W (the
+ *                counterparty counts beside the transaction counts FAN_OUT
+ *                and FAN_IN; Section 8's Degree features)
  *
  * Stage outputs are vertex sets (Algorithm 1: the output of a stage is nodes,
  * not edges), so S, M and D count distinct vertices; FAN counts edges; cycles
@@ -69,7 +85,10 @@
  * Only SG / GS and CYC stages that are asked for are charged.
  *
  * Columns, in this order, for the requested patterns only:
- *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.   Layout [ncols][n_edges].
+ *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L, DEG_OUT, DEG_IN.
+ * Layout [ncols][n_edges].  DEG_OUT / DEG_IN charge 8 bytes per window
+ * element to B_io; the phase-ordered SG scans each sender's out-slice until
+ * its condition first holds (the same min with the gather side).
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
@@ -83,6 +102,10 @@
 #define OR_GS 8u
 #define OR_CYC 16u
 #define OR_SG_UNORDERED 32u /* modifies OR_SG; adds no column */
+#define OR_DEG_OUT 64u
+#define OR_DEG_IN 128u
+#define OR_SG_PHASE 256u     /* modifies OR_SG; adds no column */
+#define OR_CYC_ANY_ORDER 512u /* modifies OR_CYC; adds no column */
 
 typedef struct {
     uint64_t n;
@@ -172,6 +195,8 @@ uint32_t oracle_num_columns(uint32_t patterns, uint32_t L) {
     if (patterns & OR_SG) c++;
     if (patterns & OR_GS) c++;
     if (patterns & OR_CYC) c += L - 1;
+    if (patterns & OR_DEG_OUT) c++;
+    if (patterns & OR_DEG_IN) c++;
     return c;
 }
 
@@ -180,6 +205,7 @@ typedef struct {
     uint64_t *stamp_s, *stamp_b, *stamp_m, *stamp_d;
     int64_t *maxb;
     uint64_t *slist;
+    int64_t *iv_f, *iv_g;   /* phase order: (first scatter, last gather) per intermediate */
     uint64_t clock;
 } og_scratch;
 
@@ -188,21 +214,40 @@ static int scratch_init(og_scratch *s, uint32_t nv) {
     s->stamp_s = (uint64_t *)calloc(nn, 8); s->stamp_b = (uint64_t *)calloc(nn, 8);
     s->stamp_m = (uint64_t *)calloc(nn, 8); s->stamp_d = (uint64_t *)calloc(nn, 8);
     s->maxb = (int64_t *)calloc(nn, 8); s->slist = (uint64_t *)calloc(nn, 8);
+    s->iv_f = (int64_t *)calloc(nn, 8); s->iv_g = (int64_t *)calloc(nn, 8);
     s->clock = 0;
-    return (s->stamp_s && s->stamp_b && s->stamp_m && s->stamp_d && s->maxb && s->slist) ? 0 : 2;
+    return (s->stamp_s && s->stamp_b && s->stamp_m && s->stamp_d && s->maxb && s->slist && s->iv_f && s->iv_g)
+               ? 0 : 2;
 }
 static void scratch_free(og_scratch *s) {
     free(s->stamp_s); free(s->stamp_b); free(s->stamp_m); free(s->stamp_d); free(s->maxb); free(s->slist);
+    free(s->iv_f); free(s->iv_g);
+}
+
+/* Phase order: is there a split time tau with f_u < tau <= (every chosen
+ * gather) and at least `need` of the intervals (f_i, g_i] containing tau?
+ * The count only rises just after some f_i (or f_u), so those points are
+ * the only candidates (the count is checked by brute force). */
+static int phase_ok(const int64_t *f, const int64_t *g, uint64_t n, int64_t f_u, int64_t t, uint64_t need) {
+    if (need == 0) return 1;
+    for (uint64_t c = 0; c <= n; c++) {
+        int64_t tau = (c == n ? f_u : f[c]) + 1;
+        if (tau <= f_u || tau > t) continue;
+        uint64_t cnt = 0;
+        for (uint64_t i = 0; i < n; i++) cnt += f[i] < tau && tau <= g[i];
+        if (cnt >= need) return 1;
+    }
+    return 0;
 }
 
 /* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k (written to out4).
  * want_sg / want_gs: which of the scatter-gather columns are asked for (they
  * only decide what *work is charged).  work (may be NULL) receives B_sg/gs. */
 static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k, int unordered,
-                     int want_sg, int want_gs, uint64_t out4[4], uint64_t *work) {
+                     int phase, int want_sg, int want_gs, uint64_t out4[6], uint64_t *work) {
     uint32_t u = g->src[e], v = g->dst[e];
     int64_t t = g->ts[e], lo = t - delta;
-    out4[0] = out4[1] = out4[2] = out4[3] = 0;
+    out4[0] = out4[1] = out4[2] = out4[3] = out4[4] = out4[5] = 0;
     if (work) *work = 0;
     if (u == v) return;
 
@@ -211,6 +256,23 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
     uint64_t ib = g->in_ptr[v], ie = g->in_ptr[v + 1];
     out4[0] = upper_ts(g, g->out_e, ob, oe, t) - lower_ts(g, g->out_e, ob, oe, lo);
     out4[1] = upper_ts(g, g->in_e, ib, ie, t) - lower_ts(g, g->in_e, ib, ie, lo);
+
+    /* DEG: distinct counterparties inside the same slices */
+    {
+        uint64_t cd = ++sc->clock, nd = 0;
+        for (uint64_t p = lower_ts(g, g->out_e, ob, oe, lo); p < upper_ts(g, g->out_e, ob, oe, t); p++) {
+            uint32_t d = g->dst[g->out_e[p]];
+            if (sc->stamp_d[d] != cd) { sc->stamp_d[d] = cd; nd++; }
+        }
+        out4[4] = nd;
+        cd = ++sc->clock;
+        nd = 0;
+        for (uint64_t p = lower_ts(g, g->in_e, ib, ie, lo); p < upper_ts(g, g->in_e, ib, ie, t); p++) {
+            uint32_t m = g->src[g->in_e[p]];
+            if (sc->stamp_d[m] != cd) { sc->stamp_d[m] = cd; nd++; }
+        }
+        out4[5] = nd;
+    }
 
     /* S(e): distinct senders into u in [lo, t), excluding v */
     uint64_t ub_ = g->in_ptr[u], ue_ = g->in_ptr[u + 1];
@@ -247,6 +309,32 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
         /* canonical scan length: elements up to the (k-1)-th qualifying
            intermediate other than u, or the whole slice */
         uint64_t n_s = k >= 2 ? r1 - r0 : 0, found = 0;
+        if (phase) {
+            /* first scatter leg to u, then the intervals of the other
+               intermediates in scan (time) order */
+            int64_t f_u = t;
+            for (uint64_t p = r0; p < r1; p++)
+                if (g->dst[g->out_e[p]] == u) { f_u = g->ts[g->out_e[p]]; break; }
+            uint64_t ni = 0;
+            int ok = k <= 1;
+            for (uint64_t p = r0; p < r1 && !ok; p++) {
+                uint64_t a = g->out_e[p];
+                uint32_t m = g->dst[a];
+                if (m == u || sc->stamp_m[m] == cm) continue;
+                sc->stamp_m[m] = cm;           /* first s -> m edge in the window */
+                if (sc->stamp_b[m] != cb || g->ts[a] >= sc->maxb[m]) continue;
+                sc->iv_f[ni] = g->ts[a];
+                sc->iv_g[ni] = sc->maxb[m];
+                ni++;
+                if (phase_ok(sc->iv_f, sc->iv_g, ni, f_u, t, k - 1)) {
+                    ok = 1;
+                    n_s = p - r0 + 1;
+                }
+            }
+            if (ok) sg++;
+            if (want_sg) w += 8 * (n_s < r_gather ? n_s : r_gather);
+            continue;
+        }
         for (uint64_t p = r0; p < r1; p++) {
             uint64_t a = g->out_e[p];
             uint32_t m = g->dst[a];
@@ -291,6 +379,7 @@ typedef struct {
     uint64_t *acc;      /* [L-1][n] accumulators, column l-2 */
     uint64_t work;      /* B_cyc of the current anchor */
     uint64_t close_b;   /* bytes of one closing search: 8 ceil(log2 indeg(u)) */
+    int any_order;      /* edges in any order inside [lo, t], before the anchor by (ts, id) */
 } cyc_ctx;
 
 static uint64_t ceil_log2(uint64_t x) {
@@ -302,9 +391,9 @@ static uint64_t ceil_log2(uint64_t x) {
 static void cyc_dfs(cyc_ctx *c, uint32_t h, uint32_t d, int64_t tlast) {
     const og_graph *g = c->g;
     uint64_t rb = g->out_ptr[h], re = g->out_ptr[h + 1];
-    /* first hop: [lo, t); later hops: (tlast, t) */
-    uint64_t p0 = d == 0 ? lower_ts(g, g->out_e, rb, re, c->lo) : upper_ts(g, g->out_e, rb, re, tlast);
-    uint64_t p1 = lower_ts(g, g->out_e, rb, re, c->t);
+    /* first hop: [lo, t); later hops: (tlast, t); any order: [lo, t] */
+    uint64_t p0 = d == 0 || c->any_order ? lower_ts(g, g->out_e, rb, re, c->lo) : upper_ts(g, g->out_e, rb, re, tlast);
+    uint64_t p1 = c->any_order ? upper_ts(g, g->out_e, rb, re, c->t) : lower_ts(g, g->out_e, rb, re, c->t);
     /* canonical bytes: scan the slice at depths 0 .. L-3, one closing search
        at depth L-2 (the loop below still walks it, to count the cycles) */
     if (d + 3 <= c->L) c->work += 12 * (p1 - p0);
@@ -312,6 +401,8 @@ static void cyc_dfs(cyc_ctx *c, uint32_t h, uint32_t d, int64_t tlast) {
     for (uint64_t p = p0; p < p1; p++) {
         uint64_t j = g->out_e[p];
         uint32_t w = g->dst[j];
+        /* any order: the anchor is the cycle's edge of greatest (ts, id) */
+        if (c->any_order && g->ts[j] == c->t && j >= c->anchor) continue;
         if (w == c->u) {
             uint32_t l = d + 2; /* d path edges + closing edge j + anchor */
             uint64_t *col = c->acc + (uint64_t)(l - 2) * g->n;
@@ -336,7 +427,12 @@ static int check_params(uint32_t patterns, int64_t delta, uint32_t L, uint32_t k
     if ((patterns & (OR_SG | OR_GS)) && k == 0) return 3;
     if ((patterns & OR_CYC) && (L < 2 || L > 8)) return 3;
     if ((patterns & OR_SG_UNORDERED) && !(patterns & OR_SG)) return 3;
-    if (patterns & ~(OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_CYC | OR_SG_UNORDERED)) return 3;
+    if ((patterns & OR_SG_PHASE) && (!(patterns & OR_SG) || (patterns & OR_SG_UNORDERED))) return 3;
+    if ((patterns & OR_CYC_ANY_ORDER) && !(patterns & OR_CYC)) return 3;
+    if (patterns & ~(OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_CYC | OR_SG_UNORDERED | OR_DEG_OUT | OR_DEG_IN |
+                     OR_SG_PHASE | OR_CYC_ANY_ORDER))
+        return 3;
+    if (!(patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_CYC | OR_DEG_OUT | OR_DEG_IN))) return 3;
     return 0;
 }
 
@@ -374,12 +470,14 @@ int oracle_mine_ex(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t 
     memset(counts, 0, sizeof(uint32_t) * (size_t)ncols * n);
     if (work) memset(work, 0, sizeof(uint64_t) * 3 * (size_t)n);
     uint32_t col = 0;
-    int c_fo = -1, c_fi = -1, c_sg = -1, c_gs = -1, c_cy = -1;
+    int c_fo = -1, c_fi = -1, c_sg = -1, c_gs = -1, c_cy = -1, c_do = -1, c_di = -1;
     if (patterns & OR_FAN_OUT) c_fo = col++;
     if (patterns & OR_FAN_IN) c_fi = col++;
     if (patterns & OR_SG) c_sg = col++;
     if (patterns & OR_GS) c_gs = col++;
-    if (patterns & OR_CYC) c_cy = col;
+    if (patterns & OR_CYC) { c_cy = col; col += L - 1; }
+    if (patterns & OR_DEG_OUT) c_do = col++;
+    if (patterns & OR_DEG_IN) c_di = col++;
     uint64_t *acc = NULL;
     if (c_cy >= 0) {
         acc = (uint64_t *)calloc((size_t)(L - 1) * (n ? n : 1), sizeof(uint64_t));
@@ -388,21 +486,28 @@ int oracle_mine_ex(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t 
     double t0 = now_s();
     if (work)
         for (uint64_t e = a_lo; e < a_hi; e++) work[e] = 12 + 4 * (uint64_t)ncols;
-    if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS)) {
+    if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_DEG_OUT | OR_DEG_IN)) {
         for (uint64_t e = a_lo; e < a_hi; e++) {
-            uint64_t r[4];
-            anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, (patterns & OR_SG) != 0,
-                     (patterns & OR_GS) != 0, r, work ? work + n + e : NULL);
+            uint64_t r[6];
+            anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, (patterns & OR_SG_PHASE) != 0,
+                     (patterns & OR_SG) != 0, (patterns & OR_GS) != 0, r, work ? work + n + e : NULL);
             if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = sat(r[0], ceiling);
             if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = sat(r[1], ceiling);
             if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = sat(r[2], ceiling);
             if (c_gs >= 0) counts[(uint64_t)c_gs * n + e] = sat(r[3], ceiling);
+            if (c_do >= 0) counts[(uint64_t)c_do * n + e] = sat(r[4], ceiling);
+            if (c_di >= 0) counts[(uint64_t)c_di * n + e] = sat(r[5], ceiling);
+            if (work && src[e] != dst[e]) {
+                /* the distinct-counterparty scans read the FAN slices */
+                if (c_do >= 0) work[e] += 8 * r[0];
+                if (c_di >= 0) work[e] += 8 * r[1];
+            }
         }
     }
     if (c_cy >= 0) {
         cyc_ctx c;
         memset(&c, 0, sizeof(c));
-        c.g = &g; c.L = L; c.acc = acc;
+        c.g = &g; c.L = L; c.acc = acc; c.any_order = (patterns & OR_CYC_ANY_ORDER) != 0;
         for (uint64_t e = a_lo; e < a_hi; e++) {
             if (src[e] == dst[e]) continue;
             c.u = src[e]; c.t = ts[e]; c.lo = ts[e] - delta; c.anchor = e;
@@ -507,6 +612,8 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
                          const uint64_t *sel, uint64_t n_sel, uint32_t *out) {
     int rc = check_params(patterns, delta, L, k);
     if (rc) return rc;
+    /* the time-ordered patterns only (the through-edge enumeration is theirs) */
+    if (patterns & (OR_SG_PHASE | OR_CYC_ANY_ORDER | OR_DEG_OUT | OR_DEG_IN)) return 3;
     og_graph g;
     og_scratch sc;
     if ((rc = og_build(&g, n, nv, src, dst, ts))) return rc;
@@ -517,8 +624,8 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
         uint64_t e = sel[i];
         if (e >= n) { og_free(&g); scratch_free(&sc); return 3; }
         uint32_t col = 0;
-        uint64_t r[4];
-        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, r, NULL);
+        uint64_t r[6];
+        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, 0, r, NULL);
         if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = sat(r[0], 0xffffffffu);
         if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = sat(r[1], 0xffffffffu);
         if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = sat(r[2], 0xffffffffu);

@@ -9,24 +9,49 @@ from __future__ import annotations
 import numpy as np
 
 
-def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = False) -> np.ndarray:
-    """Columns FAN_OUT, FAN_IN, SG_k, GS_k, CYC_2..CYC_L; uint64 [4+L-1, n].
+def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = False,
+                 sg_phase: bool = False, cyc_any_order: bool = False, deg: bool = False) -> np.ndarray:
+    """Columns FAN_OUT, FAN_IN, SG_k, GS_k, CYC_2..CYC_L (then DEG_OUT,
+    DEG_IN when deg); uint64 [4+L-1(+2), n].
     sg_unordered: an intermediate's gather leg may come before its scatter
-    leg (both inside the window)."""
+    leg (both inside the window).  sg_phase: some split time tau has every
+    chosen scatter leg (u's among them) in [t - delta, tau) and every gather
+    leg in [tau, t].
+    cyc_any_order: cycles are edge sets forming a directed cycle on distinct
+    vertices whose times span at most delta, in any order."""
     src = [int(x) for x in src]
     dst = [int(x) for x in dst]
     ts = [int(x) for x in ts]
     n = len(src)
     E = [i for i in range(n) if src[i] != dst[i]]
-    out = np.zeros((4 + L - 1, n), dtype=np.uint64)
+    out = np.zeros((4 + L - 1 + (2 if deg else 0), n), dtype=np.uint64)
     for e in E:
         u, v, t = src[e], dst[e], ts[e]
         lo = t - delta
         out[0, e] = sum(1 for f in E if src[f] == u and lo <= ts[f] <= t)
         out[1, e] = sum(1 for f in E if dst[f] == v and lo <= ts[f] <= t)
+        if deg:
+            out[4 + L - 1, e] = len({dst[f] for f in E if src[f] == u and lo <= ts[f] <= t})
+            out[4 + L, e] = len({src[f] for f in E if dst[f] == v and lo <= ts[f] <= t})
         S = {src[a] for a in E if dst[a] == u and src[a] != v and lo <= ts[a] < t}
         sg = 0
         for s in S:
+            if sg_phase:
+                # some split time tau: scatter legs in [lo, tau), gather legs
+                # in [tau, t]; u is one of the intermediates (its gather leg is
+                # the anchor e itself, the instance's latest edge)
+                for tau in range(lo + 1, t + 1):
+                    M = set()
+                    for a in E:
+                        if src[a] != s or not (lo <= ts[a] < tau):
+                            continue
+                        m = dst[a]
+                        if any(src[b] == m and dst[b] == v and tau <= ts[b] <= t for b in E):
+                            M.add(m)
+                    if len(M) >= k and u in M:
+                        sg += 1
+                        break
+                continue
             M = set()
             for a in E:
                 if src[a] != s or not (lo <= ts[a] < t):
@@ -67,6 +92,30 @@ def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = 
             if ts[f] > ts[last] and ts[f] - ts[first] <= delta:
                 extend(seq + [f])
 
+    if cyc_any_order:
+        # every set of l edges that forms one directed cycle through l
+        # distinct vertices, its times spanning at most delta
+        import itertools
+        for l in range(2, L + 1):
+            for comb in itertools.combinations(E, l):
+                outs = [src[c] for c in comb]
+                ins = [dst[c] for c in comb]
+                if len(set(outs)) != l or set(outs) != set(ins):
+                    continue
+                nxt = {src[c]: dst[c] for c in comb}
+                x, steps = outs[0], 0
+                while True:
+                    x = nxt[x]
+                    steps += 1
+                    if x == outs[0]:
+                        break
+                if steps != l:
+                    continue
+                tt = [ts[c] for c in comb]
+                if max(tt) - min(tt) <= delta:
+                    for c in comb:
+                        out[4 + l - 2, c] += 1
+        return out
     for c1 in E:
         extend([c1])
     return out

@@ -5,6 +5,7 @@ brute-force enumeration, closed forms for isolated motifs, the 6! = 720
 ordering count of Section 4, and invariants that hold by construction.
 """
 import itertools
+import math
 import os
 
 import numpy as np
@@ -193,23 +194,98 @@ def _read_golden(name):
 def test_t720_scatter_gather_orderings():
     gold = _read_golden("t720.txt")
     edges = [(0, 1), (0, 2), (0, 3), (1, 4), (2, 4), (3, 4)]   # s=0, m=1..3, d=4
-    hits, hits_u, total = 0, 0, 0
+    hits, hits_u, hits_p, total = 0, 0, 0, 0
     for perm in itertools.permutations(range(6)):
         total += 1
         src = np.array([a for a, _ in edges], dtype=np.uint32)
         dst = np.array([b for _, b in edges], dtype=np.uint32)
         ts = T0 + np.array(perm, dtype=np.int64)
         latest_gather = 3 + int(np.argmax(ts[3:]))
-        for pats in (oracle.SG, oracle.SG | oracle.SG_UNORDERED):
+        for pats in (oracle.SG, oracle.SG | oracle.SG_UNORDERED, oracle.SG | oracle.SG_PHASE):
             o = mine(src, dst, ts, 5, 100, 2, 3, pats)
             assert o[0].sum() == o[0, latest_gather]
             if pats == oracle.SG:
                 hits += int(o[0, latest_gather])
-            else:
+            elif pats & oracle.SG_UNORDERED:
                 hits_u += int(o[0, latest_gather])
+            else:
+                hits_p += int(o[0, latest_gather])
+                # phase order: all three scatter legs before all three gathers
+                assert int(o[0, latest_gather]) == int(max(perm[:3]) < min(perm[3:]))
     assert total == gold["orderings"]
     assert hits == gold["per_intermediate_instances"]
     assert hits_u == gold["unordered_instances"]
+    assert hits_p == gold["phase_order_instances"]
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_variants_match_brute_force(seed):
+    """Phase-ordered scatter-gather and the distinct-counterparty columns
+    against the literal enumeration."""
+    rng = np.random.default_rng(3000 + seed)
+    nv = int(rng.integers(4, 12))
+    g = W.random_small(seed + 500, n_edges=int(rng.integers(20, 90)), n_vertices=nv,
+                       t_range=int(rng.integers(5, 40)))
+    delta, L, k = int(rng.integers(0, 30)), int(rng.integers(2, 5)), int(rng.integers(1, 4))
+    pats = oracle.ALL | oracle.SG_PHASE | oracle.DEG_OUT | oracle.DEG_IN
+    o = mine(g.src, g.dst, g.ts, g.n_vertices, delta, L, k, pats)
+    b = brute_counts(g.src, g.dst, g.ts, delta, L, k, sg_phase=True, deg=True)
+    np.testing.assert_array_equal(o.astype(np.uint64), b)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_any_order_cycles_match_edge_subsets(seed):
+    """Any-order cycles against an enumeration of every edge subset that
+    forms one directed cycle (a different procedure from the oracle's search
+    from the latest edge)."""
+    rng = np.random.default_rng(4000 + seed)
+    g = W.random_small(seed + 700, n_edges=int(rng.integers(10, 26)), n_vertices=int(rng.integers(3, 7)),
+                       t_range=int(rng.integers(3, 30)))
+    delta, L = int(rng.integers(0, 25)), int(rng.integers(2, 5))
+    o = mine(g.src, g.dst, g.ts, g.n_vertices, delta, L, 2, oracle.CYC | oracle.CYC_ANY_ORDER)
+    b = brute_counts(g.src, g.dst, g.ts, delta, L, 2, cyc_any_order=True)
+    np.testing.assert_array_equal(o.astype(np.uint64), b[4:4 + L - 1])
+
+
+@pytest.mark.parametrize("l", [2, 3, 4, 5])
+def test_cycle_orderings_closed_form(l):
+    """One l-cycle on fresh vertices, over all l! orderings of its distinct
+    edge times: exactly l of them are time-respecting (start at any edge,
+    times rising around the cycle), and every one is an any-order cycle."""
+    src = np.arange(l, dtype=np.uint32)
+    dst = np.roll(src, -1)
+    tr = ao = 0
+    for perm in itertools.permutations(range(l)):
+        ts = T0 + 10 * np.array(perm, dtype=np.int64)
+        o = mine(src, dst, ts, l, 10 * l, max(l, 2), 2, oracle.CYC)
+        a = mine(src, dst, ts, l, 10 * l, max(l, 2), 2, oracle.CYC | oracle.CYC_ANY_ORDER)
+        col = l - 2
+        assert set(o[col].tolist()) <= {0, 1} and len(set(o[col].tolist())) == 1
+        assert a[col].tolist() == [1] * l
+        assert o.sum() == o[col].sum() and a.sum() == a[col].sum()   # no other length
+        tr += int(o[col, 0])
+        ao += int(a[col, 0])
+        # a time span wider than delta: no cycle either way
+        a2 = mine(src, dst, ts, l, 10 * (l - 1) - 1, max(l, 2), 2, oracle.CYC | oracle.CYC_ANY_ORDER)
+        assert a2.sum() == 0 or l == 1
+    assert tr == l
+    assert ao == math.factorial(l)
+
+
+@pytest.mark.parametrize("K,R", [(5, 1), (6, 2), (6, 3), (8, 8)])
+def test_distinct_counterparty_closed_form(K, R):
+    """A fan-out of K edges to R destinations used round-robin, and the
+    matching fan-in: DEG counts the destinations (sources) seen so far, FAN
+    the edges."""
+    src = np.array([0] * K + [10 + j % R for j in range(K)], dtype=np.uint32)
+    dst = np.array([1 + j % R for j in range(K)] + [9] * K, dtype=np.uint32)
+    ts = T0 + np.array(list(range(K)) + list(range(K)), dtype=np.int64) * 10
+    o = mine(src, dst, ts, 10 + R, 1000, 4, 2, oracle.FAN_OUT | oracle.FAN_IN | oracle.DEG_OUT | oracle.DEG_IN)
+    j = np.arange(K)
+    np.testing.assert_array_equal(o[0, :K], j + 1)
+    np.testing.assert_array_equal(o[2, :K], np.minimum(j + 1, R))
+    np.testing.assert_array_equal(o[1, K:], j + 1)
+    np.testing.assert_array_equal(o[3, K:], np.minimum(j + 1, R))
 
 
 # ---------------------------------------------------------------- invariants
@@ -335,7 +411,14 @@ def test_parameter_errors():
     with pytest.raises(ValueError):
         mine(s, d, t, 2, 10, 4, 2, patterns=oracle.FAN_OUT | oracle.SG_UNORDERED)  # modifier without SG
     with pytest.raises(ValueError):
-        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | 64)                       # unknown bit
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | 1024)                     # unknown bit
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.FAN_OUT | oracle.SG_PHASE)      # modifier without SG
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | oracle.SG_PHASE | oracle.SG_UNORDERED)
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.SG | oracle.CYC_ANY_ORDER)      # modifier without CYC
+    assert mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | oracle.DEG_OUT | oracle.DEG_IN).shape == (9, 2)
     assert mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | oracle.SG_UNORDERED).shape == (7, 2)
 
 
