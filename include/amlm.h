@@ -200,6 +200,21 @@ amlm_status amlm_tune_set(amlm_graph *g, uint32_t block, uint32_t sg_blocks, uin
 amlm_status amlm_graph_sync(amlm_graph *g, void *hip_stream);
 
 /*
+ * amlm_mine for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same mining and the same counts, with the mining scratch taken from a
+ * static device array of 64 MiB held by every GPU the library runs on,
+ * instead of the handle's own buffers.  Calls no hipMalloc, hipFree or other
+ * allocating routine, creates no stream or event, and runs on hip_stream
+ * only.  The graph's device must be current.  Graphs whose scratch does not
+ * fit (above about 850,000 edges) are rejected with AMLM_E_NOMEM before any
+ * device work.  All calls on one GPU share the array: calls that overlap on
+ * one GPU (concurrent streams, or threads) race and give wrong counts; run
+ * them one after another.  Asynchronous like amlm_mine.
+ */
+amlm_status amlm_mine_static(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, void *hip_stream);
+
+/*
  * Mining as amlm_mine, plus per-anchor byte counters in work_dev: device
  * uint64 [4][n_edges], rows
  *   0  B_io: the edge row read (src, dst, ts: 12 bytes) and its counts written

@@ -32,7 +32,7 @@ EXPORTS = [
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
     "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy", "amlm_mlp_predict",
     "amlm_tune_set", "amlm_graph_status", "amlm_graph_set_ceiling", "amlm_graph_inject_device_error",
-    "amlm_server_stats",
+    "amlm_server_stats", "amlm_mine_static",
 ]
 
 
@@ -70,6 +70,7 @@ def lib():
             "amlm_mine": (st, [p, pp, p, p]),
             "amlm_graph_sync": (st, [p, p]),
             "amlm_mine_work": (st, [p, pp, p, p, p]),
+            "amlm_mine_static": (st, [p, pp, p, p]),
             "amlm_mine_batch": (st, [p, pp, p, p]),
             "amlm_batch_create": (st, [p, p, p, p, p, u32, ctypes.c_int, p, ctypes.POINTER(p)]),
             "amlm_batch_info": (st, [p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
@@ -200,6 +201,21 @@ def amlm_mine(g: Graph, p: amlm_params, counts=None, stream=None):
         counts = torch.empty((ncols, g.n_edges), dtype=torch.int32, device="cuda")
     assert counts.is_contiguous() and counts.numel() >= ncols * g.n_edges
     _check(lib().amlm_mine(g.handle, ctypes.byref(p), _ptr(counts), _stream_handle(stream)))
+    return counts
+
+
+def amlm_mine_static(g: Graph, p: amlm_params, counts=None, stream=None):
+    """amlm_mine with the mining scratch in the library's static device array
+    (no device allocation inside the call); the counts tensor, if not given,
+    is allocated here by torch before the call."""
+    import torch
+    ncols = amlm_num_columns(p)
+    if ncols == 0:
+        _check(lib().amlm_mine_static(g.handle, ctypes.byref(p), None, _stream_handle(stream)))
+    if counts is None:
+        counts = torch.empty((ncols, g.n_edges), dtype=torch.int32, device="cuda")
+    assert counts.is_contiguous() and counts.numel() >= ncols * g.n_edges
+    _check(lib().amlm_mine_static(g.handle, ctypes.byref(p), _ptr(counts), _stream_handle(stream)))
     return counts
 
 

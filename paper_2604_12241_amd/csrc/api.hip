@@ -493,6 +493,84 @@ extern "C" amlm_status amlm_mine(amlm_graph *g, const amlm_params *p, uint32_t *
   return mine_common(g, p, counts_dev, nullptr, (hipStream_t)hip_stream);
 }
 
+// ------------------------------------------------------------------ mining without allocation
+// amlm_mine_static's mining scratch: one array per device (each GPU the
+// library runs on holds it until the process ends).  Its device address is
+// taken with hipGetSymbolAddress once per device, with that device current,
+// and only that address is used from the host.
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static amlm_status static_scratch(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device ordinal out of range for the static scratch");
+    return AMLM_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      set_error(std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(e));
+      return AMLM_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return AMLM_OK;
+}
+
+// Bytes of mining scratch a graph of `cap` edges needs, carved as in
+// alloc_scratch with 256-byte alignment.
+static uint64_t static_scratch_need(uint64_t cap) {
+  MineScratch ms;
+  uint64_t off = 0;
+  (void)alloc_scratch(ms, cap, [&](void **p, size_t bytes) {
+    *p = (void *)(uintptr_t)(off + 256);  // placeholder, never dereferenced
+    off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return AMLM_OK;
+  });
+  return off;
+}
+
+extern "C" amlm_status amlm_mine_static(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
+                                        void *hip_stream) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  A_TRY(check_params(p));
+  A_TRY(sticky_check(g));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device) {
+    set_error("amlm_mine_static: the graph's device must be the current device");
+    return AMLM_E_INVALID;
+  }
+  const uint64_t cap = std::max<uint64_t>(g->E, 1);
+  const uint64_t need = static_scratch_need(cap);
+  if (need > kStaticScratchBytes) {
+    set_error("amlm_mine_static: the graph needs " + std::to_string(need) +
+              " bytes of mining scratch; the static scratch holds " + std::to_string(kStaticScratchBytes) +
+              " (about 850,000 edges): use amlm_mine");
+    return AMLM_E_NOMEM;
+  }
+  void *base = nullptr;
+  A_TRY(sticky_note(g, static_scratch(dev, &base)));
+  MineScratch ms;
+  uint64_t off = 0;
+  A_TRY(alloc_scratch(ms, cap, [&](void **q, size_t bytes) {
+    *q = (unsigned char *)base + off;
+    off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return AMLM_OK;
+  }));
+  return mine_with_scratch(g, p, counts_dev, ms, (hipStream_t)hip_stream, 0, 0xffffffffu);
+}
+
 extern "C" amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
                                       uint64_t *work_dev, void *hip_stream) {
   if (g && g->E && !work_dev) {
