@@ -244,7 +244,7 @@ static int phase_ok(const int64_t *f, const int64_t *g, uint64_t n, int64_t f_u,
  * want_sg / want_gs: which of the scatter-gather columns are asked for (they
  * only decide what *work is charged).  work (may be NULL) receives B_sg/gs. */
 static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k, int unordered,
-                     int phase, int want_sg, int want_gs, uint64_t out4[6], uint64_t *work) {
+                     int phase, int want_sg, int want_gs, int want_deg, uint64_t out4[6], uint64_t *work) {
     uint32_t u = g->src[e], v = g->dst[e];
     int64_t t = g->ts[e], lo = t - delta;
     out4[0] = out4[1] = out4[2] = out4[3] = out4[4] = out4[5] = 0;
@@ -257,8 +257,9 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
     out4[0] = upper_ts(g, g->out_e, ob, oe, t) - lower_ts(g, g->out_e, ob, oe, lo);
     out4[1] = upper_ts(g, g->in_e, ib, ie, t) - lower_ts(g, g->in_e, ib, ie, lo);
 
-    /* DEG: distinct counterparties inside the same slices */
-    {
+    /* DEG: distinct counterparties inside the same slices (only when asked:
+       a hub's slices are long) */
+    if (want_deg) {
         uint64_t cd = ++sc->clock, nd = 0;
         for (uint64_t p = lower_ts(g, g->out_e, ob, oe, lo); p < upper_ts(g, g->out_e, ob, oe, t); p++) {
             uint32_t d = g->dst[g->out_e[p]];
@@ -490,7 +491,8 @@ int oracle_mine_ex(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t 
         for (uint64_t e = a_lo; e < a_hi; e++) {
             uint64_t r[6];
             anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, (patterns & OR_SG_PHASE) != 0,
-                     (patterns & OR_SG) != 0, (patterns & OR_GS) != 0, r, work ? work + n + e : NULL);
+                     (patterns & OR_SG) != 0, (patterns & OR_GS) != 0, (patterns & (OR_DEG_OUT | OR_DEG_IN)) != 0, r,
+                     work ? work + n + e : NULL);
             if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = sat(r[0], ceiling);
             if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = sat(r[1], ceiling);
             if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = sat(r[2], ceiling);
@@ -625,7 +627,7 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
         if (e >= n) { og_free(&g); scratch_free(&sc); return 3; }
         uint32_t col = 0;
         uint64_t r[6];
-        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, 0, r, NULL);
+        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, 0, 0, r, NULL);
         if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = sat(r[0], 0xffffffffu);
         if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = sat(r[1], 0xffffffffu);
         if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = sat(r[2], 0xffffffffu);

@@ -52,7 +52,8 @@ def default_procs():
     return max(1, min(16, n))
 
 
-def mine_parallel(src, dst, ts, n_vertices, patterns, delta, L, k, procs=None, ranges=None, ceiling=0):
+def mine_parallel(src, dst, ts, n_vertices, patterns, delta, L, k, procs=None, ranges=None, ceiling=0,
+                  progress=None):
     """All columns of every edge by ``procs`` workers over disjoint anchor
     ranges (default: ``procs`` equal ranges of edge ids).  Returns (counts
     uint32 [ncols, n], info) where info holds the ranges, each worker's
@@ -82,8 +83,67 @@ def mine_parallel(src, dst, ts, n_vertices, patterns, delta, L, k, procs=None, r
                 info["ranges"].append((lo, hi))
                 info["loop_s"].append(sec)
                 info["wall_s"].append(wall)
+                if progress:
+                    progress(lo, hi, sec)
     finally:
         _ARGS = None
     if acc is not None:
         counts[na:] = np.minimum(acc, np.uint64(cap)).astype(np.uint32)
     return counts, info
+
+
+def _worker_full(rng):
+    src, dst, ts, nv, patterns, delta, L, k, ceiling = _ARGS
+    lo, hi = rng
+    out, _, sec = mine_ex(src, dst, ts, nv, patterns, delta, L, k, a_lo=lo, a_hi=hi, ceiling=ceiling)
+    na = _anchored_columns(patterns)
+    cyc = []
+    for c in range(na, out.shape[0]):
+        idx = np.flatnonzero(out[c]).astype(np.uint32)
+        cyc.append((idx, out[c, idx]))
+    return lo, hi, np.ascontiguousarray(out[:, lo:hi]), cyc
+
+
+def mine_ranges(src, dst, ts, n_vertices, patterns, delta, L, k, ranges, procs=None, ceiling=0):
+    """Each anchor range mined on its own (one process per range, at most
+    `procs` at a time): returns, per range in the given order, (counts of
+    the range's own edges [ncols, hi - lo], and per cycle column the nonzero
+    credits (edge ids, values) of the cycles whose last edge is in the
+    range, to any edge).  This is what a stream batch adds when the graph
+    holds everything up to it: anchors only look back in time."""
+    global _ARGS
+    procs = procs or default_procs()
+    _ARGS = (np.ascontiguousarray(src, np.uint32), np.ascontiguousarray(dst, np.uint32),
+             np.ascontiguousarray(ts, np.int64), int(n_vertices), int(patterns), int(delta), int(L), int(k),
+             int(ceiling))
+    res = {}
+    try:
+        with mp.get_context("fork").Pool(min(procs, max(1, len(ranges)))) as pool:
+            for lo, hi, own, cyc in pool.imap_unordered(_worker_full, ranges):
+                res[(lo, hi)] = (own, cyc)
+    finally:
+        _ARGS = None
+    return [res[(int(a), int(b))] for a, b in ranges]
+
+
+def _worker_one(i):
+    graphs, params = _ARGS
+    g, (patterns, delta, L, k) = graphs[i], params[i]
+    return i, mine_ex(g[0], g[1], g[2], g[3], patterns, delta, L, k)[0]
+
+
+def mine_many(graphs, params, procs=None):
+    """Independent graphs (src, dst, ts, n_vertices) with their own
+    (patterns, delta, L, k), mined by a pool of processes; returns the
+    counts in the given order."""
+    global _ARGS
+    procs = procs or default_procs()
+    _ARGS = (graphs, params)
+    out = [None] * len(graphs)
+    try:
+        with mp.get_context("fork").Pool(min(procs, max(1, len(graphs)))) as pool:
+            for i, c in pool.imap_unordered(_worker_one, range(len(graphs))):
+                out[i] = c
+    finally:
+        _ARGS = None
+    return out

@@ -451,6 +451,29 @@ def test_parallel_driver_equals_one_process(mid_small, pats, ceiling):
     np.testing.assert_array_equal(got, full)
 
 
+def test_range_and_many_drivers(mid_small):
+    """Per-range results (own rows + sparse cycle credits) add up to the
+    full mining; independent graphs in a pool equal one-by-one mining."""
+    from oracle.parallel import mine_many, mine_ranges
+    g = mid_small
+    full = mine(g.src, g.dst, g.ts, g.n_vertices, 86400, 5, 2).astype(np.uint64)
+    ranges = [(0, 4000), (4000, 4001), (4001, 17000), (17000, g.n_edges)]
+    acc = np.zeros_like(full)
+    for (lo, hi), (own, cyc) in zip(ranges, mine_ranges(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL, 86400, 5, 2,
+                                                         ranges, procs=3)):
+        acc[:4, lo:hi] = own[:4]
+        np.testing.assert_array_equal(own[4:].astype(np.uint64) * 0, 0)
+        for c, (idx, val) in enumerate(cyc):
+            assert (idx < hi).all()          # a cycle's edges are no later than its last
+            acc[4 + c, idx] += val
+    np.testing.assert_array_equal(acc, full)
+    gs = [W.random_small(s, n_edges=60, n_vertices=8, t_range=30) for s in range(5)]
+    ps = [(oracle.ALL, 10 + s, 2 + s % 4, 1 + s % 3) for s in range(5)]
+    got = mine_many([(x.src, x.dst, x.ts, x.n_vertices) for x in gs], ps, procs=2)
+    for x, (pat, d, L, k), c in zip(gs, ps, got):
+        np.testing.assert_array_equal(c, mine(x.src, x.dst, x.ts, x.n_vertices, d, L, k, pat))
+
+
 # ---------------------------------------------------------------- algorithmic bytes
 
 from tests.brute import brute_work  # noqa: E402
