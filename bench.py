@@ -26,6 +26,8 @@ WORKLOADS = {
     "large": ("large", {"seed": 404}, 86400, 6, 2),
     "mid": ("mid", {"seed": 202}, 86400, 6, 2),
     "tiny": ("tiny", {"seed": 101}, 86400, 4, 3),
+    # a 5M-edge graph of a seed the cost model is not trained on (202..205)
+    "mid_heldout": ("mid", {"seed": 206}, 86400, 6, 2),
 }
 
 
@@ -110,7 +112,7 @@ def _stream_source(g, n_pool, seed=505):
         rep += 1
 
 
-def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300):
+def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300, inflight=64):
     """Config-5 style serving: the graph resident, stream batches of 1k-100k
     edges (log-uniform) strictly after its end.  A saturation run (every
     batch queued as fast as the server takes it) gives the sustained rate;
@@ -132,7 +134,7 @@ def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300):
         a, b, c, n = next(src)
         tk.append(S.submit(a, b, c, wait=True))
         edges += n
-        while len(tk) - done > 4 * slots:    # keep the results flowing
+        while len(tk) - done > inflight:     # keep the results flowing
             S.wait(tk[done])
             done += 1
     for t in tk[done:]:
@@ -157,7 +159,7 @@ def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300):
             while time.perf_counter() < due:
                 time.sleep(min(0.0002, max(0.0, due - time.perf_counter())))
             tk.append(S.submit(a, b, c, wait=True))
-            while len(tk) - len(lat) > 8 * slots:
+            while len(tk) - len(lat) > inflight:
                 t = tk[len(lat)]
                 S.wait(t)
                 x, _, z = S.times(t)
@@ -229,7 +231,8 @@ def oracle_full(g, delta, L, k, unordered=False, procs=None):
     procs = procs or default_procs()
     pats = oracle.ALL | (oracle.SG_UNORDERED if unordered else 0)
     t0 = time.perf_counter()
-    counts, info = mine_parallel(g.src, g.dst, g.ts, g.n_vertices, pats, delta, L, k, procs=procs)
+    counts, info = mine_parallel(g.src, g.dst, g.ts, g.n_vertices, pats, delta, L, k, procs=procs,
+                                 progress=lambda lo, hi, s: log(f"[bench] oracle anchors [{lo}, {hi}) done in {s:.1f} s"))
     wall = time.perf_counter() - t0
     n = g.n_edges
     loop = max(info["loop_s"])
@@ -247,7 +250,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=["large", "mid", "tiny"])
     ap.add_argument("--schedule", default="learned", choices=["static", "learned"])
     ap.add_argument("--sg-order", default="ordered", choices=["ordered", "unordered"],
                     help="scatter-gather legs of an intermediate strictly ordered (default) or window-only")
@@ -257,6 +260,8 @@ def main():
     ap.add_argument("--oracle-procs", type=int, default=0, help="oracle processes (0: host cores, at most 16)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-slots", type=int, default=4, help="server slots (batches mined concurrently)")
+    ap.add_argument("--serve-inflight", type=int, default=64, help="batches submitted and not yet collected")
     ap.add_argument("--model-cache", default=None, help="load / save the trained cost model here")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: no comparisons, plus a 1 GiB copy of known size")
@@ -343,15 +348,43 @@ def main():
         A.amlm_copy(b, a)
         torch.cuda.synchronize()
     elif sched == A.AMLM_SCHED_LEARNED:
-        # the static schedule on the same graph and clock, for the comparison
+        # the other schedules on the same graph and clock: static (no
+        # slicing), the length rule (slicing without the network) and the
+        # true per-anchor costs (headroom only: never shipped)
         check = counts.clone()
-        step(p_static)
-        A.amlm_graph_sync(G)
-        same = bool(torch.equal(check, counts))
-        del check
-        dts, avgs = timed(p_static, args.steps)
-        static = {"value": E / dts, "ms_per_step": dts * 1e3, "stage_ms": avgs,
-                  "counts_identical_to_learned": same}
+        _, wk_l = A.amlm_mine_work(G, p)
+        torch.cuda.synchronize()
+        true_cost = torch.log1p(wk_l[3].to(torch.float64)).to(torch.float32).contiguous()
+        del wk_l
+        A.amlm_graph_set_costs(G, true_cost)
+        schedules = {}
+        for name, sc in (("static", A.AMLM_SCHED_STATIC), ("length_rule", A.AMLM_SCHED_LENGTH),
+                         ("oracle_cost", A.AMLM_SCHED_GIVEN)):
+            px = A.params(pats, delta, L, k, sc)
+            step(px)
+            A.amlm_graph_sync(G)
+            same = bool(torch.equal(check, counts))
+            dtx, avgx = timed(px, args.steps)
+            schedules[name] = {"value": E / dtx, "ms_per_step": dtx * 1e3, "stage_ms": avgx,
+                               "counts_identical_to_learned": same}
+        A.amlm_graph_set_costs(G, None)
+        del check, true_cost
+        static = schedules["static"]
+        schedules["learned"] = {"value": E / dt, "ms_per_step": dt * 1e3, "stage_ms": avg}
+        # rank correlation of the predicted against the true scatter-gather
+        # bytes, on graphs the model was not trained on
+        from scipy.stats import spearmanr
+        heldout = {}
+        gh = make_workload("mid_heldout")[0]
+        Gh = A.Graph(gh.src, gh.dst, gh.ts, gh.n_vertices)
+        for name, GG in (("mid_seed206", Gh), (args.workload, G)):
+            pr, lb, wl = A.amlm_costmodel_eval(GG, p)
+            heldout[name] = {"anchors": int(pr.shape[0]),
+                             "spearman_model": float(spearmanr(pr, lb).correlation),
+                             "spearman_window_length": float(spearmanr(wl, lb).correlation)}
+        Gh.close()
+        schedules["heldout_rank_correlation"] = heldout
+        schedules["length_rule_bytes_per_entry"] = A.amlm_costmodel_length_coef()
 
     # the dominant kernel (k_sg) against the HBM roofline: the method's
     # scatter-gather bytes over its mean event time; and the whole mining
@@ -389,8 +422,10 @@ def main():
     if static is not None:
         out["static_schedule"] = static
         out["learned_over_static"] = (E / dt) / static["value"]
+        out["schedules"] = schedules
+        out["learned_over_length_rule"] = (E / dt) / schedules["length_rule"]["value"]
     if not args.no_serve:
-        out["stream"] = bench_serving(A, G, g, p)
+        out["stream"] = bench_serving(A, G, g, p, slots=args.serve_slots, inflight=args.serve_inflight)
         out["p99_stream_latency_ms"] = out["stream"]["load_80"]["p99_ms"]
     if not args.no_batch:
         out["batching"] = bench_batching(A)

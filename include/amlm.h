@@ -41,7 +41,8 @@
  * amlm_graph_set_ceiling) is reported as that value.
  *
  * Output layout: counts[col * n_edges + i] for edge i, with one column per
- * requested pattern in the order FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L.
+ * requested pattern in the order FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L,
+ * DEG_OUT, DEG_IN.
  *
  * Threading: a handle may be used by one host thread at a time.  Errors are
  * reported by the returned status; amlm_last_error() gives a thread-local
@@ -76,12 +77,31 @@ typedef enum {
 #define AMLM_GS 8u
 #define AMLM_CYCLES 16u
 #define AMLM_ALL 31u
+/* distinct counterparties inside the FAN windows (Section 8, Table 2's
+ * Degree features beside the transaction counts): DEG_OUT(e) = distinct
+ * destinations of u's out-edges with timestamp in [t - delta, t], DEG_IN(e)
+ * = distinct sources of v's in-edges there.  Their columns come after the
+ * cycle columns; AMLM_ALL does not include them. */
+#define AMLM_DEG_OUT 64u
+#define AMLM_DEG_IN 128u
 /* modifier of AMLM_SG (adds no column): an intermediate m of sender s counts
  * when s -> m lies in [t - delta, t) and m -> v in [t - delta, t], in either
  * order; only the window bounds the two legs, as in Section 6's compiled
  * scatter-gather example (Section 4: per-step order is optional).  Without
  * it s -> m must come strictly before m -> v. */
 #define AMLM_SG_UNORDERED 32u
+/* modifier of AMLM_SG (adds no column; excludes AMLM_SG_UNORDERED): the
+ * legs are ordered by phase, "integration occurs after placement"
+ * (Section 4): s counts when some split time tau has u's scatter leg and
+ * those of at least k - 1 other intermediates in [t - delta, tau) and their
+ * gather legs in [tau, t] (u's gather leg is the anchor).  k <= 8. */
+#define AMLM_SG_PHASE 256u
+/* modifier of AMLM_CYCLES (adds no column): a cycle's edges may occur in any
+ * order (Section 4's anticipatory, out-of-order edges): l edges forming a
+ * directed cycle through l distinct vertices whose timestamps span at most
+ * delta, counted once from the edge of greatest (timestamp, edge id) and
+ * credited to each of its edges. */
+#define AMLM_CYC_ANY_ORDER 512u
 
 /* schedules for the scatter-gather and cycle work (never change a count) */
 #define AMLM_SCHED_STATIC 0u  /* anchors in time order, fixed-size blocks of
@@ -91,6 +111,14 @@ typedef enum {
                                  into sender-window slices (one work unit each)
                                  and group light anchors into small blocks;
                                  requires a trained or loaded cost model */
+#define AMLM_SCHED_LENGTH 2u  /* as AMLM_SCHED_LEARNED, with the bytes estimated
+                                 without the network: the anchor's sender-window
+                                 length times a constant fitted on the same
+                                 training labels (the ablation of the network);
+                                 requires a model trained by this version */
+#define AMLM_SCHED_GIVEN 3u   /* as AMLM_SCHED_LEARNED, with the caller's
+                                 per-edge log1p(bytes) (amlm_graph_set_costs):
+                                 true costs give the schedule's headroom */
 
 typedef struct {
     uint32_t patterns;      /* OR of AMLM_FAN_OUT .. AMLM_CYCLES, optionally
@@ -238,6 +266,56 @@ amlm_status amlm_mine_static(amlm_graph *g, const amlm_params *p, uint32_t *coun
 amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev,
                            uint64_t *work_dev, void *hip_stream);
 
+/* ---- stage-cell programs: patterns without a new kernel ----
+ * Algorithm 1 composes a pattern from stages, each a for_all loop over the
+ * windowed neighbours of a vertex found by an earlier stage, with the
+ * operations of Section 6 (differentiate, difference, intersection) and
+ * early termination.  A program here is a list of cells, interpreted per
+ * anchor e = (u -> v, t) by one generic kernel.  Vertices are numbered
+ * 0 = u, 1 = v, 2 + i = the vertex bound by cell i.  Every cell's window is
+ * [lo, hi] with lo = t - delta (AMLM_T_WINDOW) or one past the time of the
+ * edge bound by an earlier cell `tref` (AMLM_T_AFTER), and hi = t
+ * (AMLM_T_THROUGH) or t - 1 (AMLM_T_BEFORE). */
+#define AMLM_CELL_FOR_OUT 0u /* for_all: out-edges of vertex `node` in the window, binding their destination */
+#define AMLM_CELL_FOR_IN 1u  /* for_all: in-edges of vertex `node` in the window, binding their source */
+#define AMLM_CELL_PROBE 2u   /* the edges from vertex `node` to vertex `peer` in the window (the
+                                intersection with one vertex, by binary search); last cell only */
+#define AMLM_T_WINDOW 0u
+#define AMLM_T_AFTER 1u
+#define AMLM_T_THROUGH 0u
+#define AMLM_T_BEFORE 1u
+#define AMLM_AGG_SUM 0u        /* the cell's value: the sum of its bindings' inner values
+                                  (1 per binding of the innermost loop) */
+#define AMLM_AGG_AT_LEAST 1u   /* the number of bindings whose inner value is >= threshold */
+#define AMLM_AGG_AT_LEAST_K 2u /* the same with threshold k ("at least N", Section 4) */
+typedef struct {
+    uint8_t op;        /* AMLM_CELL_* */
+    uint8_t node;      /* the vertex it expands (or probes from) */
+    uint8_t peer;      /* AMLM_CELL_PROBE: the vertex the edges go to */
+    uint8_t tlo;       /* AMLM_T_WINDOW or AMLM_T_AFTER */
+    uint8_t tref;      /* AMLM_T_AFTER: the earlier loop cell */
+    uint8_t thi;       /* AMLM_T_THROUGH or AMLM_T_BEFORE */
+    uint8_t skip;      /* bit b: neighbours equal to vertex b are skipped (differentiate) */
+    uint8_t distinct;  /* loops: each neighbour once (its first out-edge / last in-edge in the
+                          window: a stage's output is a vertex set); probe: 0 or 1 edge */
+    uint8_t agg;       /* AMLM_AGG_*: how a loop folds its bindings */
+    uint8_t pad[3];
+    uint32_t threshold;
+} amlm_cell;
+
+/*
+ * Interpret a program of 1..6 cells for every edge of g as the anchor
+ * (Algorithm 1, Section 6): out_dev[i] (device uint32[n_edges]) gets the
+ * first cell's value for anchor i, saturating at the graph's ceiling;
+ * self-loops get 0.  Invalid programs (a vertex or time reference used
+ * before it is bound, a probe that is not the last cell, unknown codes) are
+ * AMLM_E_INVALID before any device work.  One lane per anchor: a new
+ * pattern costs no new kernel, at the price of the fixed kernels' tuning.
+ * Asynchronous on hip_stream.
+ */
+amlm_status amlm_mine_program(amlm_graph *g, const amlm_cell *cells, uint32_t n_cells, int64_t delta, uint32_t k,
+                              uint32_t *out_dev, void *hip_stream);
+
 /* ---- batching: many independent graphs in one launch ---- */
 
 /*
@@ -303,8 +381,27 @@ amlm_status amlm_autotune(amlm_graph *g, const amlm_params *ps, uint32_t n_param
 amlm_status amlm_costmodel_train(amlm_graph *const *train_graphs, const amlm_params *ps, uint32_t n,
                                  uint32_t epochs, uint32_t batch, uint64_t seed,
                                  const char *out_path, void *hip_stream);
-/* Load / save the process-wide model (weights, input mean and 1/std); no
- * paper passage. */
+/*
+ * Held-out evaluation of the loaded model on graph g (no paper passage: the
+ * gain test of the learned part).  For every anchor the scatter-gather
+ * kernel works on, in time order: the model's predicted log1p(bytes), the
+ * true log1p(bytes) counted by the plain miner (row 3 of amlm_mine_work) and
+ * the sender-window length.  Host arrays of cap entries (any may be NULL);
+ * *n gets the number of anchors (entries past cap are dropped).
+ * Synchronises hip_stream.
+ */
+amlm_status amlm_costmodel_eval(amlm_graph *g, const amlm_params *p, uint64_t cap, float *pred, float *label,
+                                uint32_t *window_len, uint64_t *n, void *hip_stream);
+/* The length schedule's constant of the loaded model: predicted bytes per
+ * sender-window entry (0 if the model file predates it). */
+amlm_status amlm_costmodel_length_coef(float *coef);
+/* Per-edge costs for AMLM_SCHED_GIVEN on g: device float[n_edges],
+ * log1p(predicted bytes) by edge id, caller-owned and read during later
+ * mining calls (NULL clears).  No paper passage. */
+amlm_status amlm_graph_set_costs(amlm_graph *g, const float *log_cost_dev);
+
+/* Load / save the process-wide model (weights, input mean and 1/std, the
+ * length constant); no paper passage. */
 amlm_status amlm_costmodel_load(const char *path);
 amlm_status amlm_costmodel_save(const char *path);
 /* Copy the loaded model out: weights[5057] (FP32 master values, flat layout
@@ -387,6 +484,21 @@ amlm_status amlm_server_ticket_times(amlm_server *s, uint64_t ticket, double *t_
  * Pointers may be NULL. */
 amlm_status amlm_server_stats(amlm_server *s, uint64_t *window_edges, uint64_t *max_window_edges,
                               uint64_t *commits, uint64_t *batches_done);
+
+/* Write the server's streaming state to path (no paper passage: the state
+ * of Section 5's streaming integration, kept across restarts): the window
+ * store (the last delta of edges with their global edge ids), the latest
+ * timestamp, the next edge id, n_vertices and the parameters.  Waits until
+ * every submitted batch is in the store; batches still being mined are not
+ * affected and their results stay with this server. */
+amlm_status amlm_server_snapshot(amlm_server *s, const char *path);
+
+/* A server started from a snapshot instead of a resident graph: the
+ * snapshot's parameters and n_vertices, the given budget and slots.  Later
+ * batches get exactly the results (rows, deltas and edge ids) they would
+ * have had on the server that wrote the snapshot.  AMLM_E_INVALID for a
+ * missing, truncated or corrupt file. */
+amlm_status amlm_server_resume(const char *path, uint64_t hbm_budget_bytes, uint32_t max_slots, amlm_server **out);
 
 /* Stop the server's slots and free everything it holds. */
 void amlm_server_destroy(amlm_server *s);

@@ -18,7 +18,10 @@ LIB_PATH = os.path.join(HERE, "libamlm.so")
 AMLM_FAN_OUT, AMLM_FAN_IN, AMLM_SG, AMLM_GS, AMLM_CYCLES = 1, 2, 4, 8, 16
 AMLM_ALL = 31
 AMLM_SG_UNORDERED = 32  # modifier of AMLM_SG: an intermediate's two legs in either order
-AMLM_SCHED_STATIC, AMLM_SCHED_LEARNED = 0, 1
+AMLM_DEG_OUT, AMLM_DEG_IN = 64, 128  # distinct counterparties (columns after the cycle columns)
+AMLM_SG_PHASE = 256       # modifier of AMLM_SG: every scatter leg before every gather leg
+AMLM_CYC_ANY_ORDER = 512  # modifier of AMLM_CYCLES: a cycle's edges in any order within delta
+AMLM_SCHED_STATIC, AMLM_SCHED_LEARNED, AMLM_SCHED_LENGTH, AMLM_SCHED_GIVEN = 0, 1, 2, 3
 STATUS = {0: "AMLM_OK", 1: "AMLM_E_INVALID", 2: "AMLM_E_RANGE", 3: "AMLM_E_NOMEM",
           4: "AMLM_E_DEVICE", 5: "AMLM_E_ORDER", 6: "AMLM_E_BUSY"}
 
@@ -32,7 +35,8 @@ EXPORTS = [
     "amlm_costmodel_get", "amlm_mlp_forward", "amlm_mlp_grad",
     "amlm_batch_create", "amlm_batch_info", "amlm_autotune", "amlm_copy", "amlm_mlp_predict",
     "amlm_tune_set", "amlm_graph_status", "amlm_graph_set_ceiling", "amlm_graph_inject_device_error",
-    "amlm_server_stats", "amlm_mine_static",
+    "amlm_server_stats", "amlm_mine_static", "amlm_costmodel_eval", "amlm_costmodel_length_coef",
+    "amlm_graph_set_costs", "amlm_server_snapshot", "amlm_server_resume", "amlm_mine_program",
 ]
 
 
@@ -71,6 +75,10 @@ def lib():
             "amlm_graph_sync": (st, [p, p]),
             "amlm_mine_work": (st, [p, pp, p, p, p]),
             "amlm_mine_static": (st, [p, pp, p, p]),
+            "amlm_mine_program": (st, [p, p, u32, i64, u32, p, p]),
+            "amlm_costmodel_eval": (st, [p, pp, u64, p, p, p, ctypes.POINTER(u64), p]),
+            "amlm_costmodel_length_coef": (st, [ctypes.POINTER(ctypes.c_float)]),
+            "amlm_graph_set_costs": (st, [p, p]),
             "amlm_mine_batch": (st, [p, pp, p, p]),
             "amlm_batch_create": (st, [p, p, p, p, p, u32, ctypes.c_int, p, ctypes.POINTER(p)]),
             "amlm_batch_info": (st, [p, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
@@ -86,6 +94,8 @@ def lib():
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double)]),
             "amlm_server_destroy": (None, [p]),
+            "amlm_server_snapshot": (st, [p, ctypes.c_char_p]),
+            "amlm_server_resume": (st, [ctypes.c_char_p, u64, u32, ctypes.POINTER(p)]),
             "amlm_server_stats": (st, [p, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
                                        ctypes.POINTER(u64)]),
             "amlm_last_error": (ctypes.c_char_p, []),
@@ -219,6 +229,42 @@ def amlm_mine_static(g: Graph, p: amlm_params, counts=None, stream=None):
     return counts
 
 
+# stage-cell programs (amlm_mine_program)
+AMLM_CELL_FOR_OUT, AMLM_CELL_FOR_IN, AMLM_CELL_PROBE = 0, 1, 2
+AMLM_T_WINDOW, AMLM_T_AFTER = 0, 1
+AMLM_T_THROUGH, AMLM_T_BEFORE = 0, 1
+AMLM_AGG_SUM, AMLM_AGG_AT_LEAST, AMLM_AGG_AT_LEAST_K = 0, 1, 2
+VAR_U, VAR_V = 0, 1
+
+
+class amlm_cell(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint8), ("node", ctypes.c_uint8), ("peer", ctypes.c_uint8),
+                ("tlo", ctypes.c_uint8), ("tref", ctypes.c_uint8), ("thi", ctypes.c_uint8),
+                ("skip", ctypes.c_uint8), ("distinct", ctypes.c_uint8), ("agg", ctypes.c_uint8),
+                ("pad", ctypes.c_uint8 * 3), ("threshold", ctypes.c_uint32)]
+
+
+def cell(op, node, peer=0, tlo=AMLM_T_WINDOW, tref=0, thi=AMLM_T_THROUGH, skip=(), distinct=False,
+         agg=AMLM_AGG_SUM, threshold=0) -> amlm_cell:
+    """One stage cell; `skip` lists the vertices whose equals are skipped."""
+    mask = 0
+    for b in skip:
+        mask |= 1 << b
+    return amlm_cell(op, node, peer, tlo, tref, thi, mask, 1 if distinct else 0, agg, (0, 0, 0), threshold)
+
+
+def amlm_mine_program(g: Graph, cells, delta: int, k: int = 1, out=None, stream=None):
+    """The first cell's value per anchor: an int32 tensor [n_edges] holding
+    uint32 bit patterns."""
+    import torch
+    arr = (amlm_cell * len(cells))(*cells)
+    if out is None:
+        out = torch.empty(max(1, g.n_edges), dtype=torch.int32, device="cuda")
+    _check(lib().amlm_mine_program(g.handle, arr, len(cells), int(delta), int(k), _ptr(out),
+                                   _stream_handle(stream)))
+    return out[:g.n_edges]
+
+
 WORK_ROWS = ["io", "sg", "cyc", "sg_impl"]
 
 
@@ -323,15 +369,29 @@ def amlm_autotune(g: Graph, ps, outs, cache_path=None, stream=None):
 
 
 class Server:
-    """Continuous-batching server over a resident graph (amlm_server_*)."""
+    """Continuous-batching server over a resident graph (amlm_server_*), or
+    resumed from a snapshot (``Server.resume``)."""
 
     def __init__(self, resident: Graph, p: amlm_params, hbm_budget: int = 0, max_slots: int = 4):
         self.handle = ctypes.c_void_p()
         self.p = p
         self.ncols = amlm_num_columns(p)
+        self.sizes = {}
+        if resident is None:
+            return
         _check(lib().amlm_server_create(resident.handle, ctypes.byref(p), int(hbm_budget), int(max_slots),
                                         ctypes.byref(self.handle)))
-        self.sizes = {}
+
+    @classmethod
+    def resume(cls, path: str, p: amlm_params, hbm_budget: int = 0, max_slots: int = 4):
+        """A server continuing the stream saved by ``snapshot`` (p: the
+        parameters it was saved with, for the column count)."""
+        S = cls(None, p)
+        _check(lib().amlm_server_resume(path.encode(), int(hbm_budget), int(max_slots), ctypes.byref(S.handle)))
+        return S
+
+    def snapshot(self, path: str):
+        _check(lib().amlm_server_snapshot(self.handle, path.encode()))
 
     def submit(self, src, dst, ts, wait: bool = False) -> int:
         src = np.ascontiguousarray(src, np.uint32)
@@ -380,6 +440,32 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def amlm_costmodel_eval(g: Graph, p: amlm_params, stream=None):
+    """(predicted log1p bytes, true log1p bytes, sender-window length) of
+    every scatter-gather anchor of g, as numpy arrays."""
+    cap = max(1, int(g.n_edges))
+    pred = np.empty(cap, np.float32)
+    lab = np.empty(cap, np.float32)
+    wl = np.empty(cap, np.uint32)
+    n = ctypes.c_uint64()
+    _check(lib().amlm_costmodel_eval(g.handle, ctypes.byref(p), cap, _ptr(pred), _ptr(lab), _ptr(wl),
+                                     ctypes.byref(n), _stream_handle(stream)))
+    k = min(n.value, cap)
+    return pred[:k].copy(), lab[:k].copy(), wl[:k].copy()
+
+
+def amlm_costmodel_length_coef() -> float:
+    c = ctypes.c_float()
+    _check(lib().amlm_costmodel_length_coef(ctypes.byref(c)))
+    return float(c.value)
+
+
+def amlm_graph_set_costs(g: Graph, log_cost):
+    """Per-edge log1p(bytes) (a float32 device tensor of n_edges, kept
+    alive by the caller) for AMLM_SCHED_GIVEN; None clears."""
+    _check(lib().amlm_graph_set_costs(g.handle, None if log_cost is None else _ptr(log_cost)))
 
 
 MLP_PARAMS = 5057

@@ -327,12 +327,25 @@ amlm_status check_params(const amlm_params *p) {
     set_error("null params");
     return AMLM_E_INVALID;
   }
-  if ((p->patterns & AMLM_ALL) == 0 || (p->patterns & ~(AMLM_ALL | AMLM_SG_UNORDERED))) {
-    set_error("patterns must be a non-empty subset of AMLM_ALL (plus AMLM_SG_UNORDERED)");
+  const uint32_t cols = AMLM_ALL | AMLM_DEG_OUT | AMLM_DEG_IN;
+  if ((p->patterns & cols) == 0 || (p->patterns & ~(cols | AMLM_SG_UNORDERED | AMLM_SG_PHASE | AMLM_CYC_ANY_ORDER))) {
+    set_error("patterns must be a non-empty set of pattern bits (plus AMLM_SG_UNORDERED)");
     return AMLM_E_INVALID;
   }
   if ((p->patterns & AMLM_SG_UNORDERED) && !(p->patterns & AMLM_SG)) {
     set_error("AMLM_SG_UNORDERED modifies AMLM_SG, which is not requested");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_SG_PHASE) && (!(p->patterns & AMLM_SG) || (p->patterns & AMLM_SG_UNORDERED))) {
+    set_error("AMLM_SG_PHASE modifies AMLM_SG and excludes AMLM_SG_UNORDERED");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_SG_PHASE) && p->k > kPhaseKMax) {
+    set_error("the phase-ordered scatter-gather supports k <= 8");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_CYC_ANY_ORDER) && !(p->patterns & AMLM_CYCLES)) {
+    set_error("AMLM_CYC_ANY_ORDER modifies AMLM_CYCLES, which is not requested");
     return AMLM_E_INVALID;
   }
   if (p->delta < 0) {
@@ -347,7 +360,7 @@ amlm_status check_params(const amlm_params *p) {
     set_error("k must be >= 1");
     return AMLM_E_INVALID;
   }
-  if (p->schedule > AMLM_SCHED_LEARNED) {
+  if (p->schedule > AMLM_SCHED_GIVEN) {
     set_error("unknown schedule");
     return AMLM_E_INVALID;
   }
@@ -362,6 +375,8 @@ extern "C" uint32_t amlm_num_columns(const amlm_params *p) {
   if (p->patterns & AMLM_SG) c++;
   if (p->patterns & AMLM_GS) c++;
   if (p->patterns & AMLM_CYCLES) c += p->max_cycle_len - 1;
+  if (p->patterns & AMLM_DEG_OUT) c++;
+  if (p->patterns & AMLM_DEG_IN) c++;
   return c;
 }
 
@@ -381,7 +396,12 @@ MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *coun
   mp.col_sg = (p->patterns & AMLM_SG) ? c++ : -1;
   mp.col_gs = (p->patterns & AMLM_GS) ? c++ : -1;
   mp.col_cyc = (p->patterns & AMLM_CYCLES) ? c : -1;
+  if (p->patterns & AMLM_CYCLES) c += (int)mp.L - 1;
+  mp.col_do = (p->patterns & AMLM_DEG_OUT) ? c++ : -1;
+  mp.col_di = (p->patterns & AMLM_DEG_IN) ? c++ : -1;
   mp.sg_unordered = (p->patterns & AMLM_SG_UNORDERED) ? 1u : 0u;
+  mp.sg_phase = (p->patterns & AMLM_SG_PHASE) ? 1u : 0u;
+  mp.cyc_any = (p->patterns & AMLM_CYC_ANY_ORDER) ? 1u : 0u;
   mp.counts = counts;
   mp.stride = g->E;
   mp.ceil = g->ceiling;
@@ -403,6 +423,40 @@ MineLaunch default_launch(const amlm_graph *g) {
   return cfg;
 }
 
+amlm_status schedule_config(const amlm_graph *g, const amlm_params *p, MineLaunch &cfg) {
+  cfg.sched = p->schedule;
+  cfg.delta_hours = (float)p->delta / 3600.f;
+  const MlpModel &m = global_model();
+  if ((p->schedule == AMLM_SCHED_LEARNED || p->schedule == AMLM_SCHED_LENGTH) && !m.loaded) {
+    set_error("the learned and length schedules need a cost model (amlm_costmodel_train or _load)");
+    return AMLM_E_INVALID;
+  }
+  if (p->schedule == AMLM_SCHED_LENGTH) {
+    if (!(m.len_coef > 0.f)) {
+      set_error("the loaded cost model has no length constant (retrain it)");
+      return AMLM_E_INVALID;
+    }
+    cfg.len_coef = m.len_coef;
+  }
+  if (p->schedule == AMLM_SCHED_GIVEN) {
+    if (!g->given_cost) {
+      set_error("the given schedule needs per-edge costs (amlm_graph_set_costs)");
+      return AMLM_E_INVALID;
+    }
+    cfg.given = g->given_cost;
+  }
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_graph_set_costs(amlm_graph *g, const float *log_cost_dev) {
+  if (!g) {
+    set_error("null graph");
+    return AMLM_E_INVALID;
+  }
+  g->given_cost = log_cost_dev;
+  return AMLM_OK;
+}
+
 static amlm_status mine_impl(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,
                              hipStream_t s, uint32_t anchor_lo) {
   A_TRY(check_params(p));
@@ -418,14 +472,7 @@ static amlm_status mine_impl(amlm_graph *g, const amlm_params *p, uint32_t *coun
   MineParams mp = make_params(g, p, counts_dev, work_dev);
   mp.anchor_lo = anchor_lo;
   MineLaunch cfg = default_launch(g);
-  if (p->schedule == AMLM_SCHED_LEARNED) {
-    if (!global_model().loaded) {
-      set_error("the learned schedule needs a cost model (amlm_costmodel_train or _load)");
-      return AMLM_E_INVALID;
-    }
-    cfg.learned = true;
-    cfg.delta_hours = (float)p->delta / 3600.f;
-  }
+  A_TRY(schedule_config(g, p, cfg));
   if (anchor_lo == 0) {
     // full mining: the cycle kernel overlaps the cost model on a second
     // stream (incremental mining of small serving windows stays on one
@@ -466,14 +513,7 @@ amlm_status mine_with_scratch(amlm_graph *g, const amlm_params *p, uint32_t *cou
     mp.anchor_lo = anchor_lo;
     mp.anchor_hi = anchor_hi;
     MineLaunch cfg = default_launch(g);
-    if (p->schedule == AMLM_SCHED_LEARNED) {
-      if (!global_model().loaded) {
-        set_error("the learned schedule needs a cost model (amlm_costmodel_train or _load)");
-        return AMLM_E_INVALID;
-      }
-      cfg.learned = true;
-      cfg.delta_hours = (float)p->delta / 3600.f;
-    }
+    A_TRY(schedule_config(g, p, cfg));
     HIP_TRY(mine_launch(mp, ms, cfg, s, nullptr));
     return AMLM_OK;
   };

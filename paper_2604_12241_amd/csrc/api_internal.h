@@ -58,6 +58,7 @@ struct amlm_graph {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   BatchState batch{};
   uint32_t ceiling = 0xffffffffu;  // counts saturate here
+  const float *given_cost = nullptr;  // AMLM_SCHED_GIVEN: caller's log1p(bytes) per edge id
   // AMLM_E_DEVICE once a HIP runtime call failed inside a call on this
   // handle; every later call except destroy / info / status returns it
   amlm_status sticky = AMLM_OK;
@@ -70,6 +71,9 @@ amlm_status check_params(const amlm_params *p);
 GraphView graph_view(const amlm_graph *g);
 MineParams make_params(const amlm_graph *g, const amlm_params *p, uint32_t *counts, unsigned long long *work);
 MineLaunch default_launch(const amlm_graph *g);
+// The scatter-gather schedule of p on g (cost model, length constant or
+// given costs as needed): AMLM_E_INVALID when what it needs is missing.
+amlm_status schedule_config(const amlm_graph *g, const amlm_params *p, MineLaunch &cfg);
 amlm_status alloc_mine_scratch(amlm_graph *g);
 // Mining scratch for graphs of up to cap edges, each buffer from `alloc`.
 amlm_status alloc_scratch(MineScratch &ms, uint64_t cap, const std::function<amlm_status(void **, size_t)> &alloc);

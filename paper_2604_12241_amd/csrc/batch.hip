@@ -39,8 +39,11 @@ __global__ void k_fill_vgraph(const uint32_t *voff, uint32_t n, uint32_t *vgraph
 }
 
 // combined [ncols][E] -> per-graph [ncols_i][E_i]
+// Combined column c -> graph a's column: the cycle block holds the largest
+// L's columns, graph a keeps its own L's first ones; the columns after the
+// block (DEG) move down by the cycle columns graph a does not have.
 __global__ void k_batch_split(const uint32_t *comb, uint64_t E, uint32_t ncols, const uint64_t *eoff, uint32_t n,
-                              uint32_t *const *outs, const uint32_t *ncols_i) {
+                              uint32_t *const *outs, const uint32_t *ncols_i, uint32_t cyc0, uint32_t ncyc_max) {
   uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; idx < (uint64_t)ncols * E; idx += stride) {
@@ -51,9 +54,13 @@ __global__ void k_batch_split(const uint32_t *comb, uint64_t E, uint32_t ncols, 
       uint32_t mid = (a + b + 1) >> 1;
       if (eoff[mid] <= e) a = mid; else b = mid - 1;
     }
-    if (c < ncols_i[a]) {
+    const uint32_t ncyc_a = ncols_i[a] - (ncols - ncyc_max);  // graph a's cycle columns
+    uint32_t oc = c;
+    if (c >= cyc0 + ncyc_max) oc = c - (ncyc_max - ncyc_a);
+    else if (c >= cyc0 + ncyc_a) continue;
+    if (oc < ncols_i[a]) {
       uint64_t Ei = eoff[a + 1] - eoff[a];
-      outs[a][(uint64_t)c * Ei + (e - eoff[a])] = comb[idx];
+      outs[a][(uint64_t)oc * Ei + (e - eoff[a])] = comb[idx];
     }
   }
 }
@@ -65,6 +72,8 @@ uint32_t ncols_of(uint32_t patterns, uint32_t L) {
   if (patterns & AMLM_SG) c++;
   if (patterns & AMLM_GS) c++;
   if (patterns & AMLM_CYCLES) c += L - 1;
+  if (patterns & AMLM_DEG_OUT) c++;
+  if (patterns & AMLM_DEG_IN) c++;
   return c;
 }
 
@@ -239,10 +248,7 @@ static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_
     A_TRY(balloc(g, (void **)&B.comb, 4ull * nc_max * std::max<uint64_t>(g->E, 1)));
     B.comb_cols = nc_max;
   }
-  if (pm.schedule == AMLM_SCHED_LEARNED && !global_model().loaded) {
-    set_error("the learned schedule needs a cost model (amlm_costmodel_train or _load)");
-    return AMLM_E_INVALID;
-  }
+
   // parameters and output pointers live in device memory read by the graph
   HIP_TRY(hipMemcpyAsync(B.d_sub, sub.data(), sizeof(SubParams) * B.n, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(B.d_outs, counts_dev, sizeof(uint32_t *) * B.n, hipMemcpyHostToDevice, s));
@@ -251,10 +257,7 @@ static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_
   mp.vgraph = B.vgraph;
   mp.sub = B.d_sub;
   MineLaunch cfg = default_launch(g);
-  if (pm.schedule == AMLM_SCHED_LEARNED) {
-    cfg.learned = true;
-    cfg.delta_hours = (float)pm.delta / 3600.f;
-  }
+  A_TRY(schedule_config(g, &pm, cfg));
   std::string sig = batch_signature(g, pm.patterns, pm.schedule, Lmax, cfg);
   if (!B.exec || sig != B.sig) {
     if (B.exec) {
@@ -267,8 +270,10 @@ static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_
     hipError_t e = launch_fill_u32(B.comb, 0, (uint64_t)nc_max * g->E, cs);
     if (e == hipSuccess) e = mine_launch(mp, g->ms, cfg, cs, nullptr);
     if (e == hipSuccess && g->E) {
+      const uint32_t ncyc_max = (pm.patterns & AMLM_CYCLES) ? Lmax - 1 : 0;
+      const uint32_t cyc0 = mp.col_cyc >= 0 ? (uint32_t)mp.col_cyc : nc_max;
       hipLaunchKernelGGL(k_batch_split, dim3(4 * device_info().num_cu), dim3(256), 0, cs, B.comb, g->E, nc_max,
-                         B.d_eoff, B.n, B.d_outs, B.d_ncols);
+                         B.d_eoff, B.n, B.d_outs, B.d_ncols, cyc0, ncyc_max);
       e = hipGetLastError();
     }
     hipGraph_t graph = nullptr;

@@ -32,6 +32,9 @@ struct MlpModel {
   uint32_t train_samples = 0;
   float master[kMlpParams];   // FP32 master weights
   float mean[kMlpF], inv_std[kMlpF];
+  // the length rule fitted on the same labels: predicted bytes = len_coef x
+  // sender-window length (geometric mean of bytes / length); 0 if unknown
+  float len_coef = 0.f;
   uint16_t *d_w16 = nullptr;  // device BF16 weights
   float *d_norm = nullptr;    // device mean[12], inv_std[12]
 };
@@ -43,8 +46,13 @@ hipError_t model_upload(MlpModel &m);
 // Predict log-work for list items: pred[i] from feat[idx[i] * 8 ...] (idx
 // may be NULL for the identity); the item count is *n_dev if n_dev is not
 // NULL, else n_host.
+// Batched stores (vgraph != NULL): each item's window and cycle length are
+// its sub-graph's (item idx[i] is a CSC position, in_dst[idx[i]] its vertex).
+struct SubParams;
 hipError_t mlp_infer(const MlpModel &m, const uint32_t *feat, const uint32_t *idx, uint32_t n_host,
-                     const uint32_t *n_dev, float delta_hours, float L, float *pred, hipStream_t s);
+                     const uint32_t *n_dev, float delta_hours, float L, float *pred, hipStream_t s,
+                     const uint32_t *in_dst = nullptr, const uint32_t *vgraph = nullptr,
+                     const SubParams *sub = nullptr);
 
 uint16_t f32_to_bf16(float f);
 float bf16_to_f32(uint16_t h);

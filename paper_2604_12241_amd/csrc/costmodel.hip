@@ -91,7 +91,9 @@ constexpr int kActPad = kMlpH + 8;  // bf16 per LDS row (pad against bank confli
 template <bool kFromRaw>
 __global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const float *norm, const uint32_t *feat,
                                                   const uint32_t *idx, const float *X, const uint32_t *n_p,
-                                                  uint32_t n_host, float dh, float L, float *pred) {
+                                                  uint32_t n_host, float dh, float L, float *pred,
+                                                  const uint32_t *in_dst, const uint32_t *vgraph,
+                                                  const SubParams *sub) {
   __shared__ short act[256 / AMLM_WAVE][kTileRows][kActPad];
   const uint32_t lane = lane_id(), w = threadIdx.x / AMLM_WAVE;
   const uint32_t col = lane % 16, kq = (lane / 16) * 4;
@@ -137,7 +139,13 @@ __global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const flo
 #pragma unroll
         for (int q = 0; q < kMlpRaw; q++) r[q] = feat[rr * kMlpRaw + q];
         float xf[kMlpF];
-        mlp_input(r, dh, L, nrm, xf);
+        float dh_i = dh, L_i = L;
+        if (vgraph) {  // batched store: the item's own sub-graph
+          const SubParams sp = sub[vgraph[in_dst[rr]]];
+          dh_i = (float)sp.delta / 3600.f;
+          L_i = (float)sp.L;
+        }
+        mlp_input(r, dh_i, L_i, nrm, xf);
 #pragma unroll
         for (int i = 0; i < 4; i++) x[i] = kq + i < kMlpF ? xf[kq + i] : 0.f;
       } else {
@@ -412,6 +420,29 @@ __global__ void k_compact_keep(const uint32_t *keep, const uint32_t *off, uint32
   if (keep[p]) list[off[p]] = p;
 }
 
+// Per-block partial sums (fixed order) of log(bytes) - log(sender-window
+// length) over samples with a non-empty sender window, and their count: the
+// length rule's constant is exp(mean).
+__global__ void k_len_moments(const uint32_t *feat, const float *label, uint32_t n, double *part) {
+  __shared__ double acc[256][2];
+  double s = 0.0, c = 0.0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t w = feat[(uint64_t)i * kMlpRaw + 2];
+    const double by = expm1((double)label[i]);
+    if (w < 2 || by <= 0.0) continue;  // anchors the split rule never cuts
+    s += log(by) - log((double)w);
+    c += 1.0;
+  }
+  acc[threadIdx.x][0] = s;
+  acc[threadIdx.x][1] = c;
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int q = 0; q < (int)blockDim.x; q++) t += acc[q][threadIdx.x];
+    part[blockIdx.x * 2 + threadIdx.x] = t;
+  }
+}
+
 // Per-block partial sums (fixed order) of the unstandardised inputs and their
 // squares, for the normalisation statistics.
 __global__ void k_input_moments(const uint32_t *feat, uint32_t n, float dh, float L, double *part) {
@@ -466,10 +497,11 @@ hipError_t model_upload(MlpModel &m) {
 }
 
 hipError_t mlp_infer(const MlpModel &m, const uint32_t *feat, const uint32_t *idx, uint32_t n_host,
-                     const uint32_t *n_dev, float delta_hours, float L, float *pred, hipStream_t s) {
+                     const uint32_t *n_dev, float delta_hours, float L, float *pred, hipStream_t s,
+                     const uint32_t *in_dst, const uint32_t *vgraph, const SubParams *sub) {
   uint32_t blocks = 2 * device_info().num_cu;
   hipLaunchKernelGGL(k_mlp_mfma<true>, dim3(blocks), dim3(256), 0, s, m.d_w16, m.d_norm, feat, idx,
-                     (const float *)nullptr, n_dev, n_host, delta_hours, L, pred);
+                     (const float *)nullptr, n_dev, n_host, delta_hours, L, pred, in_dst, vgraph, sub);
   return hipGetLastError();
 }
 
@@ -596,7 +628,8 @@ extern "C" amlm_status amlm_mlp_predict(const float *w_host, const float *x_host
   HIP_TRY(hipMemcpy(X, x_host, 4ull * n * kMlpF, hipMemcpyHostToDevice));
   hipLaunchKernelGGL(k_mlp_mfma<false>, dim3(std::max(1u, std::min(1024u, (n + 63) / 64))), dim3(256), 0, 0, w16,
                      (const float *)nullptr, (const uint32_t *)nullptr, (const uint32_t *)nullptr, X,
-                     (const uint32_t *)nullptr, n, 0.f, 0.f, Y);
+                     (const uint32_t *)nullptr, n, 0.f, 0.f, Y, (const uint32_t *)nullptr,
+                     (const uint32_t *)nullptr, (const SubParams *)nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpy(y_host, Y, 4ull * n, hipMemcpyDeviceToHost));
   return AMLM_OK;
@@ -684,6 +717,22 @@ extern "C" amlm_status amlm_costmodel_train(amlm_graph *const *gs, const amlm_pa
     m.mean[f] = (float)mean;
     m.inv_std[f] = var > 1e-12 ? (float)(1.0 / std::sqrt(var)) : 1.f;
   }
+  {
+    // the length rule on the same labels
+    double *lpart;
+    A_TRY(b.get(&lpart, (size_t)mblk * 2));
+    hipLaunchKernelGGL(k_len_moments, dim3(mblk), dim3(256), 0, s, feat_all, lab_all, n_samples, lpart);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> lp((size_t)mblk * 2);
+    HIP_TRY(hipMemcpyAsync(lp.data(), lpart, 8 * lp.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double s1 = 0, c1 = 0;
+    for (uint32_t q = 0; q < mblk; q++) {
+      s1 += lp[2 * q];
+      c1 += lp[2 * q + 1];
+    }
+    m.len_coef = c1 > 0 ? (float)std::exp(s1 / c1) : 0.f;
+  }
   init_weights(m.master, seed);
   HIP_TRY(model_upload(m));
   float *X, *mom1, *mom2, *master, *grad, *partial;
@@ -729,7 +778,8 @@ extern "C" amlm_status amlm_costmodel_train(amlm_graph *const *gs, const amlm_pa
   return AMLM_OK;
 }
 
-static const char kMagic[8] = {'A', 'M', 'L', 'M', 'M', 'L', 'P', '1'};
+static const char kMagic[8] = {'A', 'M', 'L', 'M', 'M', 'L', 'P', '2'};
+static const char kMagicV1[8] = {'A', 'M', 'L', 'M', 'M', 'L', 'P', '1'};  // without the length constant
 
 extern "C" amlm_status amlm_costmodel_save(const char *path) {
   MlpModel &m = global_model();
@@ -744,7 +794,7 @@ extern "C" amlm_status amlm_costmodel_save(const char *path) {
   }
   bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(m.mean, 4, kMlpF, f) == (size_t)kMlpF &&
             fwrite(m.inv_std, 4, kMlpF, f) == (size_t)kMlpF &&
-            fwrite(m.master, 4, kMlpParams, f) == (size_t)kMlpParams;
+            fwrite(m.master, 4, kMlpParams, f) == (size_t)kMlpParams && fwrite(&m.len_coef, 4, 1, f) == 1;
   fclose(f);
   if (!ok) {
     set_error("short write");
@@ -762,9 +812,12 @@ extern "C" amlm_status amlm_costmodel_load(const char *path) {
   char magic[8];
   MlpModel &m = global_model();
   MlpModel tmp;
-  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMagic, 8) == 0 &&
-            fread(tmp.mean, 4, kMlpF, f) == (size_t)kMlpF && fread(tmp.inv_std, 4, kMlpF, f) == (size_t)kMlpF &&
-            fread(tmp.master, 4, kMlpParams, f) == (size_t)kMlpParams;
+  bool ok = fread(magic, 1, 8, f) == 8 && (memcmp(magic, kMagic, 8) == 0 || memcmp(magic, kMagicV1, 8) == 0);
+  const bool v2 = ok && memcmp(magic, kMagic, 8) == 0;
+  ok = ok && fread(tmp.mean, 4, kMlpF, f) == (size_t)kMlpF && fread(tmp.inv_std, 4, kMlpF, f) == (size_t)kMlpF &&
+       fread(tmp.master, 4, kMlpParams, f) == (size_t)kMlpParams;
+  tmp.len_coef = 0.f;
+  if (ok && v2) ok = fread(&tmp.len_coef, 4, 1, f) == 1;
   fclose(f);
   if (!ok) {
     set_error("not a cost model file");
@@ -773,6 +826,7 @@ extern "C" amlm_status amlm_costmodel_load(const char *path) {
   memcpy(m.mean, tmp.mean, sizeof(m.mean));
   memcpy(m.inv_std, tmp.inv_std, sizeof(m.inv_std));
   memcpy(m.master, tmp.master, sizeof(m.master));
+  m.len_coef = tmp.len_coef;
   HIP_TRY(model_upload(m));
   m.loaded = true;
   return AMLM_OK;
@@ -787,5 +841,77 @@ extern "C" amlm_status amlm_costmodel_get(float *weights, float *mean, float *in
   if (weights) memcpy(weights, m.master, sizeof(m.master));
   if (mean) memcpy(mean, m.mean, sizeof(m.mean));
   if (inv_std) memcpy(inv_std, m.inv_std, sizeof(m.inv_std));
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_costmodel_eval(amlm_graph *g, const amlm_params *p, uint64_t cap, float *pred,
+                                           float *label, uint32_t *window_len, uint64_t *n_out, void *hip_stream) {
+  if (!g || !p || !n_out) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  MlpModel &m = global_model();
+  if (!m.loaded) {
+    set_error("no cost model is loaded");
+    return AMLM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  *n_out = 0;
+  if (g->Ev == 0) return AMLM_OK;
+  DevBuf b;
+  const uint64_t E = std::max<uint64_t>(g->E, 1);
+  uint32_t *fs, *keep, *koff, *klist, *cnt_dev, *ctmp, *scan_tmp, *fk;
+  float *ls, *lk, *yk;
+  unsigned long long *wk;
+  A_TRY(b.get(&fs, E * kMlpRaw));
+  A_TRY(b.get(&ls, E));
+  A_TRY(b.get(&keep, E));
+  A_TRY(b.get(&koff, E));
+  A_TRY(b.get(&klist, E));
+  A_TRY(b.get(&cnt_dev, 4));
+  A_TRY(b.get(&wk, kWorkRows * E));
+  A_TRY(b.get(&ctmp, E * (uint64_t)std::max(1u, amlm_num_columns(p))));
+  A_TRY(b.get(&scan_tmp, scan_tmp_words(E)));
+  A_TRY(mine_common(g, p, ctmp, wk, s));
+  hipLaunchKernelGGL(k_sample_features, dim3((g->Ev + 255) / 256), dim3(256), 0, s, graph_view(g), p->delta,
+                     (const unsigned long long *)(wk + kWorkSgImpl * g->E), fs, ls, keep);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(scan_exclusive_u32(keep, koff, g->Ev, cnt_dev, scan_tmp, s));
+  hipLaunchKernelGGL(k_compact_keep, dim3((g->Ev + 255) / 256), dim3(256), 0, s, keep, koff, g->Ev, klist);
+  HIP_TRY(hipGetLastError());
+  uint32_t nk = 0;
+  HIP_TRY(hipMemcpyAsync(&nk, cnt_dev, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *n_out = nk;
+  if (nk == 0) return AMLM_OK;
+  A_TRY(b.get(&fk, (uint64_t)nk * kMlpRaw));
+  A_TRY(b.get(&lk, nk));
+  A_TRY(b.get(&yk, nk));
+  hipLaunchKernelGGL(k_gather_samples, dim3((nk + 255) / 256), dim3(256), 0, s, klist, nk, fs, ls, fk, lk, 0u);
+  HIP_TRY(hipGetLastError());
+  const float dh = (float)p->delta / 3600.f;
+  const float Lf = (float)((p->patterns & AMLM_CYCLES) ? p->max_cycle_len : 2);
+  HIP_TRY(mlp_infer(m, fk, nullptr, nk, nullptr, dh, Lf, yk, s));
+  const uint64_t k = std::min<uint64_t>(nk, cap);
+  if (k) {
+    if (pred) HIP_TRY(hipMemcpyAsync(pred, yk, 4 * k, hipMemcpyDeviceToHost, s));
+    if (label) HIP_TRY(hipMemcpyAsync(label, lk, 4 * k, hipMemcpyDeviceToHost, s));
+    if (window_len) HIP_TRY(hipMemcpy2DAsync(window_len, 4, fk + 2, 4 * kMlpRaw, 4, k, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_costmodel_length_coef(float *coef) {
+  MlpModel &m = global_model();
+  if (!coef) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  if (!m.loaded) {
+    set_error("no cost model is loaded");
+    return AMLM_E_INVALID;
+  }
+  *coef = m.len_coef;
   return AMLM_OK;
 }

@@ -16,6 +16,16 @@ constexpr uint8_t kFlagGsDest = 8;
 constexpr uint32_t kAnchorScanCap = 16;
 
 constexpr int kSgThreads = 64;   // one wave per block
+#ifndef AMLM_PREFETCH_CLAIM
+#define AMLM_PREFETCH_CLAIM 0
+#endif
+constexpr bool kPrefetchClaim = AMLM_PREFETCH_CLAIM != 0;
+// optional occupancy target for k_sg (waves per SIMD), for sweeps
+#ifdef AMLM_SG_WAVES_PER_EU
+#define AMLM_SG_OCCUPANCY __attribute__((amdgpu_waves_per_eu(AMLM_SG_WAVES_PER_EU, AMLM_SG_WAVES_PER_EU)))
+#else
+#define AMLM_SG_OCCUPANCY
+#endif
 #ifndef AMLM_BLOOM_LOG2_MAX
 #define AMLM_BLOOM_LOG2_MAX 15
 #endif
@@ -42,7 +52,7 @@ constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
 constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave
 #ifndef AMLM_REV_RATIO
-#define AMLM_REV_RATIO 16
+#define AMLM_REV_RATIO 32
 #endif
 // a pair's join iterates the gather side when the sender's out-window is
 // more than this many times longer
@@ -61,11 +71,10 @@ constexpr uint32_t kEagerNeed = AMLM_EAGER_NEED;
 #endif
 // eager checks also in the flattened short-pair loop (else long pairs only)
 constexpr bool kEagerShort = AMLM_EAGER_SHORT != 0;
-#ifndef AMLM_CLAIM
-#define AMLM_CLAIM 1
-#endif
-// work units taken per atomic claim of the work-stealing counter
-constexpr uint32_t kClaim = AMLM_CLAIM;
+
+// phase-ordered scatter-gather keeps the k - 1 latest gather times of a
+// sender's intervals in registers: k is at most this
+constexpr uint32_t kPhaseKMax = 8;
 
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
 constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
@@ -95,7 +104,10 @@ struct MineParams {
   const SubParams *sub;   // batched store: parameters per sub-graph
   uint32_t anchor_lo, anchor_hi;  // only edges with ids in [anchor_lo, anchor_hi) are anchors
   int col_fo, col_fi, col_sg, col_gs, col_cyc;  // -1 when not requested
+  int col_do, col_di;    // distinct counterparties (after the cycle columns), -1 when not requested
   uint32_t sg_unordered;  // 1: an intermediate's two legs in either order
+  uint32_t sg_phase;      // 1: every scatter leg before every gather leg (k <= kPhaseKMax)
+  uint32_t cyc_any;       // 1: a cycle's edges in any order inside the window
   uint32_t *counts;
   uint64_t stride;   // row stride of counts (= number of edges)
   uint32_t ceil;     // every count saturates at this value (2^32 - 1 by default)
@@ -135,9 +147,17 @@ inline uint64_t max_units(uint64_t ev, uint32_t block) { return ev / block + ev 
 #endif
 constexpr uint32_t kSplitBytes = AMLM_SPLIT_BYTES;  // learned schedule: predicted bytes per slice
 
+// scatter-gather schedules: fixed blocks of the list (static), or heavy
+// anchors cut into slices by an estimate of their work: the cost model
+// (learned), the sender-window length times a constant fitted with the
+// model (length), or per-edge costs given by the caller (given)
+enum { kSchedStatic = 0, kSchedLearned = 1, kSchedLength = 2, kSchedGiven = 3 };
+
 struct MineLaunch {
   uint32_t sg_blocks, sg_chunk, cyc_blocks, cyc_blocks_small;  // cycle grids for L > 6 and L <= 6
-  bool learned = false;         // schedule scatter-gather chunks by the cost model
+  uint32_t sched = kSchedStatic;
+  float len_coef = 0.f;          // length schedule: bytes per sender-window entry
+  const float *given = nullptr;  // given schedule: log1p(bytes) per edge id
   uint32_t learned_chunk = kSgChunkMax;  // anchors per chunk in the learned schedule
   uint32_t split_bytes = kSplitBytes;    // learned schedule: predicted bytes per slice
   // optional second stream: the cycle kernel runs there, concurrently with

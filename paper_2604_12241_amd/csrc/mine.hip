@@ -55,11 +55,18 @@ __global__ __launch_bounds__(256) void k_anchor_out(MineParams mp, uint8_t *flag
   const uint32_t k = k_of(mp, u);
   uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
   uint32_t fan_out = 0;
-  if (mp.col_fo >= 0 || feat) {
+  if (mp.col_fo >= 0 || mp.col_do >= 0 || feat) {
     uint32_t hi = gallop_upper_right(g.out_t, p + 1, re, t);
     uint32_t lb = gallop_lower_left(g.out_t, rs, p, lo);
     fan_out = hi - lb;
     if (mp.col_fo >= 0) mp.counts[(uint64_t)mp.col_fo * mp.stride + eid] = min(fan_out, mp.ceil);
+    if (mp.col_do >= 0) {
+      // distinct destinations: the window's first edge of each (u, d) pair
+      uint32_t nd = 0;
+      for (uint32_t q = lb; q < hi; q++) nd += g.out_prv[q] < lo;
+      mp.counts[(uint64_t)mp.col_do * mp.stride + eid] = min(nd, mp.ceil);
+      if (mp.work) atomicAdd(&mp.work[kWorkIo * mp.stride + eid], (unsigned long long)kAlgElem * fan_out);
+    }
   }
   if (mp.col_sg >= 0 || mp.col_gs >= 0) {
     uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
@@ -128,11 +135,18 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
   int32_t t = g.in_t[q];
   int32_t lo = window_lo(t, delta_of(mp, u));
   const bool is_sg = (mp.col_sg >= 0 || mp.col_gs >= 0) && flags_sg[q];
-  if (mp.col_fi >= 0 || is_sg) {
+  if (mp.col_fi >= 0 || mp.col_di >= 0 || is_sg) {
     uint32_t rs = g.in_ptr[v], re = g.in_ptr[v + 1];
     uint32_t hi = gallop_upper_right(g.in_t, q + 1, re, t);
     uint32_t lb = gallop_lower_left(g.in_t, rs, q, lo);
     if (mp.col_fi >= 0) mp.counts[(uint64_t)mp.col_fi * mp.stride + eid] = min(hi - lb, mp.ceil);
+    if (mp.col_di >= 0) {
+      // distinct sources: the last edge of each (m, v) pair at or before t
+      uint32_t nd = 0;
+      for (uint32_t j = lb; j < hi; j++) nd += g.in_nxt[j] > t;
+      mp.counts[(uint64_t)mp.col_di * mp.stride + eid] = min(nd, mp.ceil);
+      if (mp.work) atomicAdd(&mp.work[kWorkIo * mp.stride + eid], (unsigned long long)kAlgElem * (hi - lb));
+    }
     if (is_sg) {
       sg_win[q].z = lb;
       sg_win[q].w = hi;
@@ -152,13 +166,78 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
   if (mp.col_cyc >= 0 || (is_sg && feat)) {
     uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
     uint32_t q1 = lower_bound_i32(g.out_t, vs, ve, t);
-    if (mp.col_cyc >= 0 && q1 > vs && g.out_t[q1 - 1] >= lo) flags_cy[eid] = kFlagCYC;
+    // any order: v's first hop may also leave at time t itself
+    const uint32_t qc = mp.cyc_any ? upper_bound_i32(g.out_t, q1, ve, t) : q1;
+    if (mp.col_cyc >= 0 && qc > vs && g.out_t[qc - 1] >= lo) flags_cy[eid] = kFlagCYC;
     if (is_sg && feat) {
       uint32_t q0 = gallop_lower_left(g.out_t, vs, q1, lo);
       feat[(uint64_t)q * kMlpRaw + 3] = q1 - q0;
       feat[(uint64_t)q * kMlpRaw + 6] = ve - vs;
     }
   }
+}
+
+// Phase order for one (anchor, sender) pair, scanning the sender's
+// out-slice [b, b + n) in time order: every chosen scatter leg (u's
+// included) must come before every chosen gather leg, the anchor being u's.
+// Each intermediate m != u is tried once, at its first edge in the window
+// (time f_m), against its last edge into v at or before t (time g_m, found
+// in v's neighbour-sorted row [vrs, vre)); a split time tau then exists for
+// the intervals seen so far iff the (k-1)-th largest g among them exceeds
+// max(f of the latest interval, f_u).  The k - 1 largest g are kept in
+// registers (k <= kPhaseKMax).  Returns whether the pair qualifies; *scanned
+// gets the elements scanned (all of them when it does not).  `filter`
+// (may be NULL) rejects m that are surely not in v's gather window.
+template <class Filter>
+__device__ bool sg_phase_pair(const MineParams &mp, uint32_t s, uint32_t u, int32_t lo, int32_t t, uint32_t k,
+                              uint32_t b, uint32_t n, uint32_t vrs, uint32_t vre, const Filter &filter,
+                              uint32_t *scanned) {
+  const GraphView &g = mp.g;
+  *scanned = n;
+  if (k <= 1) {
+    *scanned = 0;
+    return true;
+  }
+  // f_u: the sender's first edge to u inside the window
+  const uint32_t urs = g.in_ptr[u], ure = g.in_ptr[u + 1];
+  const uint64_t ku = nbr_key(s, lo < 0 ? 0 : lo);
+  const uint32_t qu = ku ? upper_bound_u64_interp(g.inn_key, urs, ure, ku - 1) : urs;
+  int32_t f_u = t;
+  if (qu < ure && (uint32_t)(g.inn_key[qu] >> 32) == s) f_u = (int32_t)(uint32_t)g.inn_key[qu];
+  int32_t top[kPhaseKMax - 1];
+#pragma unroll
+  for (uint32_t i = 0; i < kPhaseKMax - 1; i++) top[i] = AMLM_INT_MIN;
+  const uint32_t need = k - 1;
+  for (uint32_t i = 0; i < n; i++) {
+    const uint32_t pos = b + i;
+    const uint32_t m = g.out_nbr[pos];
+    if (m == u || g.out_prv[pos] >= lo) continue;  // u, or not m's first edge in the window
+    if (!filter(g.out_h[pos])) continue;
+    const uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+    if (q == vrs) continue;
+    const uint64_t kk = g.inn_key[q - 1];
+    const int32_t gm = (int32_t)(uint32_t)kk, fm = g.out_t[pos];
+    if ((uint32_t)(kk >> 32) != m || gm < lo || fm >= gm) continue;
+    // insert gm into the descending list of the k - 1 largest
+    int32_t x = gm;
+#pragma unroll
+    for (uint32_t j = 0; j < kPhaseKMax - 1; j++) {
+      if (j < need && x > top[j]) {
+        const int32_t y = top[j];
+        top[j] = x;
+        x = y;
+      }
+    }
+    int32_t kth = top[0];
+#pragma unroll
+    for (uint32_t j = 1; j < kPhaseKMax - 1; j++)
+      if (j == need - 1) kth = top[j];
+    if (kth > max(fm, f_u)) {
+      *scanned = i + 1;
+      return true;
+    }
+  }
+  return false;
 }
 
 // ------------------------------------------------------------------ algorithmic bytes
@@ -213,6 +292,13 @@ __global__ __launch_bounds__(256) void k_alg_sg(MineParams mp) {
       const uint32_t b = lower_bound_i32(g.out_t, rs, re, lo);
       const uint32_t n_full = lower_bound_i32(g.out_t, b, re, t) - b;
       uint32_t n_s = min(n_full, r), found = 0;
+      if (mp.sg_phase) {
+        uint32_t scanned;
+        auto any = [](uint32_t) { return true; };
+        (void)sg_phase_pair(mp, s, u, lo, t, k, b, n_full, vrs, vre, any, &scanned);
+        join += min(scanned, r);
+        continue;
+      }
       for (uint32_t i = 0; i < min(n_full, r); i++) {
         const uint32_t pos = b + i, m = g.out_nbr[pos];
         if (m == u || g.out_prv[pos] >= lo) continue;  // u, or not the first s -> m edge of the window
@@ -354,6 +440,22 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
     sg_verify(mp, L, cq, AMLM_WAVE, vrs, vre);
     cq -= AMLM_WAVE;
   }
+}
+
+// Phase-ordered joins of a batch of pairs: one lane per pair, each scanning
+// its slice serially (the filter of the segment rejects most entries).
+__device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre,
+                              uint32_t k) {
+  const uint32_t lane = lane_id();
+  if (lane >= np) return;
+  const uint32_t it = L.pr_item[lane], b = L.pr_b[lane], n = L.pr_n[lane];
+  if (n == 0) return;
+  const uint32_t s = mp.g.out_src[b];
+  const uint32_t hu = vhash(L.i_u[it]);
+  uint32_t scanned;
+  auto filter = [&](uint32_t h) { return h != hu && bloom_test(L.bloom, shift, h); };
+  if (sg_phase_pair(mp, s, L.i_u[it], L.i_lo[it], L.i_t[it], k, b, n, vrs, vre, filter, &scanned))
+    L.pr_cnt[lane] = k - 1;
 }
 
 // Reverse join of the pairs in `rev` (degree-ordered intersection, Section
@@ -557,7 +659,7 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
       // the sender's out-window (a gather entry costs a search, a scanned
       // out-entry one load and a filter test)
       const uint32_t r = L.i_r1[it] - L.i_r0[it];
-      rv = (uint64_t)r * kRevRatio < n;
+      rv = !mp.sg_phase && (uint64_t)r * kRevRatio < n;
       if (rv) {
         b = nb;
         n = r;
@@ -575,7 +677,10 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     }
     // reverse pairs by slot
     const uint64_t rev = __ballot(lane < np && L.pr_rev[lane] != 0);
-    sg_join(mp, L, np, rev, shift, vrs, vre, k);
+    if (mp.sg_phase)
+      sg_join_phase(mp, L, np, shift, vrs, vre, k);
+    else
+      sg_join(mp, L, np, rev, shift, vrs, vre, k);
     if (lane < np && L.pr_cnt[lane] >= k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
   }
 }
@@ -609,6 +714,23 @@ __device__ __forceinline__ unsigned long long split_size(const MineParams &mp, c
   if (*w < 2) return 0;
   if (!pred) return *w;
   return (unsigned long long)fminf(expm1f(fminf(fmaxf(pred[i], 0.f), 40.f)), 2147483648.f);
+}
+
+// Predicted log1p(bytes) of the list items without the network: the
+// sender-window length times a constant (length schedule), or the caller's
+// per-edge costs (given schedule).
+__global__ __launch_bounds__(256) void k_pred_rule(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
+                                                   const uint8_t *flags_sg, const uint4 *sg_win, uint32_t sched,
+                                                   float len_coef, const float *given, float *pred) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_items_p) return;
+  const uint32_t q = items[i];
+  if (sched == kSchedGiven) {
+    pred[i] = given[mp.g.in_eid[q]];
+  } else {
+    const uint32_t w = join_window(mp, flags_sg, sg_win, q);
+    pred[i] = log1pf(len_coef * (float)w);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_split_weight(MineParams mp, const uint32_t *items, const uint32_t *n_items_p,
@@ -719,26 +841,30 @@ __global__ void k_split_gs(MineParams mp, const uint32_t *items, const uint32_t 
 // Units: with `units` NULL (static schedule) unit c is the block of items
 // [c * block, (c + 1) * block) and n_count_p points at the item count; else
 // units[c] and n_count_p points at the unit count.
-__global__ __launch_bounds__(AMLM_WAVE) void k_sg(MineParams mp, const uint32_t *items, const uint2 *units,
-                                                 const uint32_t *n_count_p, uint32_t block, uint32_t *ctr,
-                                                 const uint4 *sg_win, const uint8_t *flags_sg) {
+__global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams mp, const uint32_t *items,
+                                                                    const uint2 *units, const uint32_t *n_count_p,
+                                                                    uint32_t block, uint32_t *ctr,
+                                                                    const uint4 *sg_win, const uint8_t *flags_sg) {
   __shared__ SgLds L;
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint32_t n_count = *n_count_p;
   const uint32_t n_units = units ? n_count : (n_count + block - 1) / block;
-  uint32_t c = 0, left = 0;
+  // the next unit is claimed while this one is mined, so the counter's
+  // round trip overlaps the work (kPrefetchClaim)
+  uint32_t next = 0;
+  if (kPrefetchClaim && lane == 0) next = atomicAdd(ctr, 1u);
   for (;;) {
-    if (left == 0) {
-      // claim kClaim consecutive units
-      if (lane == 0) c = atomicAdd(ctr, kClaim);
-      c = rfl((uint32_t)__shfl(c, 0, AMLM_WAVE));
-      left = kClaim;
+    uint32_t c = 0;
+    if (kPrefetchClaim) {
+      c = rfl((uint32_t)__shfl(next, 0, AMLM_WAVE));
+      if (c >= n_units) break;
+      if (lane == 0) next = atomicAdd(ctr, 1u);
     } else {
-      c++;
+      if (lane == 0) c = atomicAdd(ctr, 1u);
+      c = rfl((uint32_t)__shfl(c, 0, AMLM_WAVE));
+      if (c >= n_units) break;
     }
-    left--;
-    if (c >= n_units) break;
     const uint2 un = units ? units[c] : make_uint2(c * block, min(block, n_count - c * block));
     const bool heavy = (un.y & kUnitHeavy) != 0;
     const uint32_t nr = heavy ? 1u : un.y;
@@ -846,7 +972,7 @@ struct CycFrame {
 template <int kFrames>
 struct CycLds {
   uint32_t r_eid[AMLM_WAVE], r_u[AMLM_WAVE], r_L[AMLM_WAVE];
-  int32_t r_t[AMLM_WAVE];
+  int32_t r_t[AMLM_WAVE], r_lo[AMLM_WAVE];
   CycFrame fr[kFrames];
 };
 
@@ -892,24 +1018,38 @@ __device__ void cyc_prepare(const MineParams &mp, S_t &S, uint32_t i) {
       int32_t tl = tau + 1 < 0 ? 0 : tau + 1;
       uint32_t qa = lower_bound_u64(g.inn_key, urs, ure, nbr_key(h, tl));
       uint32_t qb = lower_bound_u64(g.inn_key, qa, ure, nbr_key(h, t));
-      if (qb > qa) {
-        cyc_credit_path(mp, S, i, lane, Lr, qb - qa);
-        uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)Lr - 2) * mp.stride;
-        for (uint32_t q = qa; q < qb; q++) credit(col + g.inn_eid[q], 1u, mp.ceil);
+      // any order: closing edges at time t too, those before the anchor by id
+      uint32_t qc = qb;
+      if (mp.cyc_any)
+        while (qc < ure && g.inn_key[qc] == nbr_key(h, t) && g.inn_eid[qc] < S.r_eid[r]) qc++;
+      uint32_t *col = mp.counts + (uint64_t)(mp.col_cyc + (int)Lr - 2) * mp.stride;
+      uint32_t ncl = qb - qa;
+      if (mp.cyc_any) {
+        ncl = 0;
+        for (uint32_t q = qb; q < ure && g.inn_key[q] == nbr_key(h, t); q++) ncl += g.inn_eid[q] < S.r_eid[r];
+        ncl += qb - qa;
       }
+      if (ncl) {
+        cyc_credit_path(mp, S, i, lane, Lr, ncl);
+        for (uint32_t q = qa; q < qb; q++) credit(col + g.inn_eid[q], 1u, mp.ceil);
+        if (mp.cyc_any)
+          for (uint32_t q = qb; q < ure && g.inn_key[q] == nbr_key(h, t); q++)
+            if (g.inn_eid[q] < S.r_eid[r]) credit(col + g.inn_eid[q], 1u, mp.ceil);
+      }
+      (void)qc;
       if (mp.work) {
-        // one closing search when the head has an out-edge in (tau, t), and
+        // one closing search when the head has an out-edge in its slice, and
         // the credits of the cycles found
         const uint32_t rs = g.out_ptr[h], re = g.out_ptr[h + 1];
         const uint32_t x0 = upper_bound_i32(g.out_t, rs, re, tau);
-        unsigned long long w = (unsigned long long)kAlgCycleEdge * Lr * (qb - qa);
-        if (x0 < re && g.out_t[x0] < t) w += kAlgElem * ceil_log2_u32(ure - urs);
+        unsigned long long w = (unsigned long long)kAlgCycleEdge * Lr * ncl;
+        if (x0 < re && (mp.cyc_any ? g.out_t[x0] <= t : g.out_t[x0] < t)) w += kAlgElem * ceil_log2_u32(ure - urs);
         if (w) atomicAdd(&mp.work[kWorkCyc * mp.stride + S.r_eid[r]], w);
       }
     } else {
       uint32_t rs = g.out_ptr[h], re = g.out_ptr[h + 1];
       xb = upper_bound_i32(g.out_t, rs, re, tau);
-      nsz = lower_bound_i32(g.out_t, xb, re, t) - xb;
+      nsz = (mp.cyc_any ? upper_bound_i32(g.out_t, xb, re, t) : lower_bound_i32(g.out_t, xb, re, t)) - xb;
       if (mp.work && nsz) atomicAdd(&mp.work[kWorkCyc * mp.stride + S.r_eid[r]], (unsigned long long)kAlgCycElem * nsz);
     }
   }
@@ -952,7 +1092,8 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
       F0.root[lane] = (uint8_t)lane;
       F0.eid[lane] = 0xffffffffu;
       F0.vert[lane] = v;
-      F0.tau[lane] = window_lo(t, delta_of(mp, u)) - 1;  // first hop at time >= lo
+      S.r_lo[lane] = window_lo(t, delta_of(mp, u));
+      F0.tau[lane] = S.r_lo[lane] - 1;  // first hop at time >= lo
     }
     if (lane == 0) S.fr[0].n = nr;
     cyc_prepare(mp, S, 0);
@@ -977,7 +1118,12 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
         }
         uint32_t pos = F.xb[a] + (f - F.xoff[a]);
         w = g.out_nbr[pos];
-        if (w == S.r_u[F.root[a]]) {
+        // any order: only edges before the anchor by (time, edge id), so each
+        // cycle is found once, from its greatest edge
+        const bool after_anchor = mp.cyc_any && g.out_t[pos] == S.r_t[F.root[a]] &&
+                                  g.out_eid[pos] >= S.r_eid[F.root[a]];
+        if (after_anchor) {
+        } else if (w == S.r_u[F.root[a]]) {
           // closing hop: a cycle of sp + 2 edges
           cyc_credit_path(mp, S, sp, a, sp + 2, 1u);
           credit(mp.counts + (uint64_t)(mp.col_cyc + sp) * mp.stride + g.out_eid[pos], 1u, mp.ceil);
@@ -999,7 +1145,8 @@ __global__ __launch_bounds__(kCycThreads) void k_cyc(MineParams mp, const uint32
           G.root[slot] = F.root[a];
           G.eid[slot] = ceid;
           G.vert[slot] = w;
-          G.tau[slot] = ctau;
+          // in order: the next hop leaves after this edge; any order: anywhere in the window
+          G.tau[slot] = mp.cyc_any ? S.r_lo[F.root[a]] - 1 : ctau;
         }
         if (lane == 0) G.n = __popcll(bc);
         cyc_prepare(mp, S, sp + 1);
@@ -1064,7 +1211,7 @@ static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineL
   if (mp.work && E) {
     // accounting run: every edge row's own bytes
     const uint32_t ncols = (mp.col_fo >= 0) + (mp.col_fi >= 0) + (mp.col_sg >= 0) + (mp.col_gs >= 0) +
-                           (mp.col_cyc >= 0 ? mp.L - 1 : 0);
+                           (mp.col_cyc >= 0 ? mp.L - 1 : 0) + (mp.col_do >= 0) + (mp.col_di >= 0);
     hipLaunchKernelGGL(k_alg_io, dim3((E + 255) / 256), dim3(256), 0, s, mp, ncols);
     CK(hipGetLastError());
   }
@@ -1072,8 +1219,11 @@ static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineL
   CK(tm->begin(kStAnchor, s));
   CK(launch_fill_u32((uint32_t *)ms.flags, 0, (Ev + 3) / 4 + (E + 3) / 4, s));
   uint8_t *flags_sg = ms.flags, *flags_cy = ms.flags + 4 * ((Ev + 3) / 4);
-  const bool learned = cfg.learned && mp.col_sg >= 0 && mp.k >= 2;
-  uint32_t *feat = learned ? ms.feat : (uint32_t *)nullptr;
+  // the sliced schedules (the cost model's, the length rule's, the given
+  // costs'): heavy anchors cut into slices by their estimated work
+  const bool learned = cfg.sched != kSchedStatic && mp.col_sg >= 0 && mp.k >= 2;
+  const bool use_mlp = learned && cfg.sched == kSchedLearned;
+  uint32_t *feat = use_mlp ? ms.feat : (uint32_t *)nullptr;
   hipLaunchKernelGGL(k_anchor_out, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, ms.sg_win, feat);
   CK(hipGetLastError());
   hipLaunchKernelGGL(k_anchor_in, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, flags_cy, ms.sg_win, feat);
@@ -1133,7 +1283,15 @@ static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineL
     const float *pred = nullptr;
     if (learned) {
       CK(tm->begin(kStModel, s));
-      CK(mlp_infer(global_model(), ms.feat, ms.list_sg, 0, n_sg, cfg.delta_hours, (float)mp.L, ms.pred, s));
+      if (use_mlp) {
+        CK(mlp_infer(global_model(), ms.feat, ms.list_sg, 0, n_sg, cfg.delta_hours, (float)mp.L, ms.pred, s,
+                     mp.vgraph ? mp.g.in_dst : nullptr, mp.vgraph, mp.sub));
+      } else {
+        hipLaunchKernelGGL(k_pred_rule, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, ms.list_sg, n_sg,
+                           (const uint8_t *)flags_sg, (const uint4 *)ms.sg_win, cfg.sched, cfg.len_coef, cfg.given,
+                           ms.pred);
+        CK(hipGetLastError());
+      }
       pred = ms.pred;
       CK(tm->end(kStModel, s));
     }

@@ -22,6 +22,8 @@
 // allows its counts buffer.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -452,25 +454,17 @@ static void worker(amlm_server *S, uint32_t k) {
   }
 }
 
-extern "C" amlm_status amlm_server_create(amlm_graph *resident, const amlm_params *p, uint64_t hbm_budget_bytes,
-                                          uint32_t max_slots, amlm_server **out) {
-  if (!resident || !out) {
-    set_error("null argument");
-    return AMLM_E_INVALID;
-  }
-  *out = nullptr;
+// A server without its first store version or threads (freed by
+// amlm_server_destroy).
+static amlm_status server_init(const amlm_params *p, uint64_t hbm_budget_bytes, uint32_t max_slots, uint32_t V,
+                               amlm_server **out) {
   amlm_status st = check_params(p);
   if (st != AMLM_OK) return st;
-  if (resident->batch.n) {
-    set_error("a batched store cannot be served");
-    return AMLM_E_INVALID;
-  }
-  if ((st = sticky_check(resident)) != AMLM_OK) return st;
   amlm_server *S = new amlm_server();
   (void)hipGetDevice(&S->device);
   S->p = *p;
   S->ncols = amlm_num_columns(p);
-  S->V = resident->V;
+  S->V = V;
   S->budget = hbm_budget_bytes;
   uint32_t c = 0;
   if (p->patterns & AMLM_FAN_OUT) c++;
@@ -481,14 +475,58 @@ extern "C" amlm_status amlm_server_create(amlm_graph *resident, const amlm_param
   S->ncyc = (p->patterns & AMLM_CYCLES) ? p->max_cycle_len - 1 : 0;
   max_slots = std::max(1u, std::min(max_slots, 16u));
   S->max_queue = 64 * max_slots;
+  S->slots.resize(max_slots);
+  if (hipStreamCreateWithFlags(&S->commit_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("server: stream creation failed");
+    amlm_server_destroy(S);
+    return AMLM_E_DEVICE;
+  }
+  for (uint32_t k = 0; k < max_slots; k++) {
+    if (hipStreamCreateWithFlags(&S->slots[k].stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("server: stream creation failed");
+      amlm_server_destroy(S);
+      return AMLM_E_DEVICE;
+    }
+  }
+  *out = S;
+  return AMLM_OK;
+}
+
+// Build the first store version from its staged edges and start the threads.
+static amlm_status server_start(amlm_server *S) {
+  StoreVer &v0 = S->ver[0];
+  amlm_status st = store_build(S, v0, S->commit_stream);
+  if (st != AMLM_OK) return st;
+  S->cur = 0;
+  S->max_store = v0.n;
+  S->committer = std::thread(committer, S);
+  for (uint32_t k = 0; k < S->slots.size(); k++) S->slots[k].th = std::thread(worker, S, k);
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_server_create(amlm_graph *resident, const amlm_params *p, uint64_t hbm_budget_bytes,
+                                          uint32_t max_slots, amlm_server **out) {
+  if (!resident || !out) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  *out = nullptr;
+  if (resident->batch.n) {
+    set_error("a batched store cannot be served");
+    return AMLM_E_INVALID;
+  }
+  amlm_status st = sticky_check(resident);
+  if (st != AMLM_OK) return st;
+  amlm_server *S = nullptr;
+  if ((st = server_init(p, hbm_budget_bytes, max_slots, resident->V, &S)) != AMLM_OK) return st;
   auto bail = [&](amlm_status code, const char *msg) {
     (void)hipGetLastError();
-    set_error(msg);
+    if (msg) set_error(msg);
     amlm_server_destroy(S);
     return code;
   };
-  if (hipStreamCreateWithFlags(&S->commit_stream, hipStreamNonBlocking) != hipSuccess)
-    return bail(AMLM_E_DEVICE, "server: stream creation failed");
   // the first store version: the resident edges no older than delta before
   // its latest edge (the first batch is later still)
   const uint64_t Ev = resident->Ev;
@@ -508,10 +546,7 @@ extern "C" amlm_status amlm_server_create(amlm_graph *resident, const amlm_param
   }
   StoreVer &v0 = S->ver[0];
   const uint64_t n0 = Ev - p0;
-  if ((st = store_reserve(v0, n0)) != AMLM_OK) {
-    amlm_server_destroy(S);
-    return st;
-  }
+  if ((st = store_reserve(v0, n0)) != AMLM_OK) return bail(st, nullptr);
   v0.n = n0;
   if (n0) {
     hipLaunchKernelGGL(k_store_from_graph, dim3((uint32_t)((n0 + 255) / 256)), dim3(256), 0, S->commit_stream,
@@ -522,20 +557,135 @@ extern "C" amlm_status amlm_server_create(amlm_graph *resident, const amlm_param
         hipStreamSynchronize(S->commit_stream) != hipSuccess)
       return bail(AMLM_E_DEVICE, "server: copying the resident graph failed");
   }
-  if ((st = store_build(S, v0, S->commit_stream)) != AMLM_OK) {
+  S->next_geid = resident->E;
+  if ((st = server_start(S)) != AMLM_OK) return bail(st, nullptr);
+  *out = S;
+  return AMLM_OK;
+}
+
+// Snapshot file: magic, the parameters, n_vertices, the latest timestamp, the
+// next edge id, the window store's edge count, then its src, dst, ts and
+// global edge ids in time order.
+static const char kSnapMagic[8] = {'A', 'M', 'L', 'M', 'S', 'N', 'P', '1'};
+
+extern "C" amlm_status amlm_server_snapshot(amlm_server *S, const char *path) {
+  if (!S || !path) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  std::vector<uint32_t> src, dst, geid;
+  std::vector<int64_t> ts;
+  int64_t t_last;
+  uint64_t next_geid, n;
+  amlm_params p;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    // every submitted batch in the store (mining may still go on: it only
+    // reads the version)
+    S->cv.wait(lk, [&] { return S->pending.empty() || S->stop; });
+    StoreVer &v = S->ver[S->cur];
+    n = v.n;
+    src.resize(n);
+    dst.resize(n);
+    geid.resize(n);
+    ts.resize(n);
+    if (n && (hipMemcpyAsync(src.data(), v.src, 4 * n, hipMemcpyDeviceToHost, S->commit_stream) != hipSuccess ||
+              hipMemcpyAsync(dst.data(), v.dst, 4 * n, hipMemcpyDeviceToHost, S->commit_stream) != hipSuccess ||
+              hipMemcpyAsync(geid.data(), v.geid, 4 * n, hipMemcpyDeviceToHost, S->commit_stream) != hipSuccess ||
+              hipMemcpyAsync(ts.data(), v.ts, 8 * n, hipMemcpyDeviceToHost, S->commit_stream) != hipSuccess ||
+              hipStreamSynchronize(S->commit_stream) != hipSuccess)) {
+      (void)hipGetLastError();
+      set_error("server: snapshot copy failed");
+      return AMLM_E_DEVICE;
+    }
+    t_last = S->t_last;
+    next_geid = S->next_geid;
+    p = S->p;
+  }
+  FILE *f = fopen(path, "wb");
+  if (!f) {
+    set_error(std::string("cannot open ") + path);
+    return AMLM_E_INVALID;
+  }
+  bool ok = fwrite(kSnapMagic, 1, 8, f) == 8 && fwrite(&p, sizeof(p), 1, f) == 1 && fwrite(&S->V, 4, 1, f) == 1 &&
+            fwrite(&t_last, 8, 1, f) == 1 && fwrite(&next_geid, 8, 1, f) == 1 && fwrite(&n, 8, 1, f) == 1 &&
+            fwrite(src.data(), 4, n, f) == n && fwrite(dst.data(), 4, n, f) == n && fwrite(ts.data(), 8, n, f) == n &&
+            fwrite(geid.data(), 4, n, f) == n;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) {
+    set_error("server: short write of the snapshot");
+    return AMLM_E_INVALID;
+  }
+  return AMLM_OK;
+}
+
+extern "C" amlm_status amlm_server_resume(const char *path, uint64_t hbm_budget_bytes, uint32_t max_slots,
+                                          amlm_server **out) {
+  if (!path || !out) {
+    set_error("null argument");
+    return AMLM_E_INVALID;
+  }
+  *out = nullptr;
+  FILE *f = fopen(path, "rb");
+  if (!f) {
+    set_error(std::string("cannot open ") + path);
+    return AMLM_E_INVALID;
+  }
+  char magic[8];
+  amlm_params p;
+  uint32_t V = 0;
+  int64_t t_last = 0;
+  uint64_t next_geid = 0, n = 0;
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kSnapMagic, 8) == 0 && fread(&p, sizeof(p), 1, f) == 1 &&
+            fread(&V, 4, 1, f) == 1 && fread(&t_last, 8, 1, f) == 1 && fread(&next_geid, 8, 1, f) == 1 &&
+            fread(&n, 8, 1, f) == 1 && n < 0xffffffffull;
+  std::vector<uint32_t> src, dst, geid;
+  std::vector<int64_t> ts;
+  if (ok) {
+    src.resize(n);
+    dst.resize(n);
+    geid.resize(n);
+    ts.resize(n);
+    ok = fread(src.data(), 4, n, f) == n && fread(dst.data(), 4, n, f) == n && fread(ts.data(), 8, n, f) == n &&
+         fread(geid.data(), 4, n, f) == n;
+  }
+  fclose(f);
+  if (!ok) {
+    set_error("not a server snapshot, or a truncated one");
+    return AMLM_E_INVALID;
+  }
+  for (uint64_t i = 0; i < n; i++)
+    if (src[i] >= V || dst[i] >= V || (i && ts[i] < ts[i - 1])) {
+      set_error("corrupt server snapshot");
+      return AMLM_E_INVALID;
+    }
+  amlm_server *S = nullptr;
+  amlm_status st = server_init(&p, hbm_budget_bytes, max_slots, V, &S);
+  if (st != AMLM_OK) return st;
+  StoreVer &v0 = S->ver[0];
+  if ((st = store_reserve(v0, n)) != AMLM_OK) {
     amlm_server_destroy(S);
     return st;
   }
-  S->cur = 0;
-  S->max_store = n0;
-  S->next_geid = resident->E;
-  S->slots.resize(max_slots);
-  for (uint32_t k = 0; k < max_slots; k++) {
-    if (hipStreamCreateWithFlags(&S->slots[k].stream, hipStreamNonBlocking) != hipSuccess)
-      return bail(AMLM_E_DEVICE, "server: stream creation failed");
+  v0.n = n;
+  v0.host_ts = ts;
+  hipStream_t s = S->commit_stream;
+  if (n && (hipMemcpyAsync(v0.src, src.data(), 4 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(v0.dst, dst.data(), 4 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(v0.geid, geid.data(), 4 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(v0.ts, ts.data(), 8 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)) {
+    (void)hipGetLastError();
+    set_error("server: restoring the snapshot failed");
+    amlm_server_destroy(S);
+    return AMLM_E_DEVICE;
   }
-  S->committer = std::thread(committer, S);
-  for (uint32_t k = 0; k < max_slots; k++) S->slots[k].th = std::thread(worker, S, k);
+  S->t_last = t_last;
+  S->next_geid = next_geid;
+  if ((st = server_start(S)) != AMLM_OK) {
+    amlm_server_destroy(S);
+    return st;
+  }
   *out = S;
   return AMLM_OK;
 }

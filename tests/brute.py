@@ -211,3 +211,56 @@ def brute_work(src, dst, ts, delta: int, L: int, k: int, want_sg=True, want_gs=T
             visit(v, 0, None, {v})
             out[2, e] = acc[0]
     return out
+
+
+def brute_program(src, dst, ts, cells, delta: int, k: int) -> np.ndarray:
+    """Stage-cell programs evaluated literally (uint64 [n]): for each anchor
+    e = (u -> v, t), vertices 0 = u, 1 = v, 2 + i = bound by cell i; a loop
+    cell runs over the non-self-loop edges out of (into) its vertex inside
+    its window [lo, hi], in (time, id) order, keeping with `distinct` only
+    the earliest out-edge (latest in-edge) per neighbour, skipping
+    neighbours equal to the `skip` vertices; a probe counts the edges from
+    `node` to `peer` inside its window (0 or 1 with `distinct`).  Folds: sum
+    of the inner values (1 per innermost binding), or the number of
+    bindings whose inner value reaches the threshold (k for AT_LEAST_K).
+    `cells` are dicts with the amlm_cell field names (skip as a tuple)."""
+    src = [int(x) for x in src]
+    dst = [int(x) for x in dst]
+    ts = [int(x) for x in ts]
+    n = len(src)
+    E = sorted((i for i in range(n) if src[i] != dst[i]), key=lambda i: (ts[i], i))
+    out = np.zeros(n, dtype=np.uint64)
+
+    def run(i, var, times, t, lo_w):
+        c = cells[i]
+        lo = lo_w if c["tlo"] == 0 else times[c["tref"]] + 1
+        hi = t if c["thi"] == 0 else t - 1
+        if c["op"] == 2:
+            a, b = var[c["node"]], var[c["peer"]]
+            cnt = sum(1 for f in E if src[f] == a and dst[f] == b and lo <= ts[f] <= hi)
+            return min(cnt, 1) if c["distinct"] else cnt
+        x = var[c["node"]]
+        if c["op"] == 0:
+            edges = [(f, dst[f]) for f in E if src[f] == x and lo <= ts[f] <= hi]
+        else:
+            edges = [(f, src[f]) for f in E if dst[f] == x and lo <= ts[f] <= hi]
+        if c["distinct"]:
+            pick = {}
+            for f, w in edges:   # (time, id) order
+                if c["op"] == 0:
+                    pick.setdefault(w, f)     # earliest out-edge per neighbour
+                else:
+                    pick[w] = f               # latest in-edge per neighbour
+            edges = sorted(((f, w) for w, f in pick.items()), key=lambda z: (ts[z[0]], z[0]))
+        acc = 0
+        thr = k if c["agg"] == 2 else c.get("threshold", 0)
+        for f, w in edges:
+            if any(var[b] == w for b in c.get("skip", ()) if b < len(var)):
+                continue
+            val = 1 if i + 1 == len(cells) else run(i + 1, var + [w], times + [ts[f]], t, lo_w)
+            acc += val if c["agg"] == 0 else (1 if val >= thr else 0)
+        return acc
+
+    for e in E:
+        out[e] = run(0, [src[e], dst[e]], [], ts[e], ts[e] - delta)
+    return out

@@ -34,11 +34,15 @@ def test_library_loads_and_reports_columns():
     # the unordered scatter-gather modifier adds no column and needs AMLM_SG
     assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | A.AMLM_SG_UNORDERED, L=4)) == 7
     assert A.amlm_num_columns(A.params(patterns=A.AMLM_FAN_OUT | A.AMLM_SG_UNORDERED, L=4)) == 0
-    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | 64, L=4)) == 0
+    # the distinct-counterparty columns come after the cycle columns
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | A.AMLM_DEG_OUT | A.AMLM_DEG_IN, L=4)) == 9
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_DEG_IN, L=4)) == 1
     assert A.amlm_num_columns(A.params(L=9)) == 0          # invalid L
     assert A.amlm_num_columns(A.params(k=0)) == 0          # invalid k
     assert A.amlm_num_columns(A.params(delta=-1)) == 0     # invalid window
-    assert A.amlm_num_columns(A.params(patterns=64)) == 0  # unknown pattern bit
+    assert A.amlm_num_columns(A.params(patterns=1 << 12)) == 0  # unknown pattern bit
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | (1 << 12), L=4)) == 0
+    assert A.amlm_num_columns(A.params(schedule=4)) == 0   # unknown schedule
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -99,11 +99,13 @@ def test_batch_learned_schedule_with_slices_over_replays():
     for G in train:
         G.close()
     A.amlm_tune_set(B, split_bytes=64)
-    ps = [A.params(A.AMLM_ALL, p.delta, p.max_cycle_len, p.k, A.AMLM_SCHED_LEARNED) for _, p in subs]
     refs = [oracle.mine(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL, p.delta, p.max_cycle_len, p.k)
             for g, p in subs]
     other = W.mid(778, scale=0.002)
-    for rep in range(3):
+    for rep in range(4):
+        # the network (per-sub-graph window and L as inputs), then the length rule
+        sched = A.AMLM_SCHED_LEARNED if rep < 3 else A.AMLM_SCHED_LENGTH
+        ps = [A.params(A.AMLM_ALL, p.delta, p.max_cycle_len, p.k, sched) for _, p in subs]
         outs = A.amlm_mine_batch(B, ps)
         torch.cuda.synchronize()
         for i, (o, r) in enumerate(zip(outs, refs)):
@@ -112,7 +114,7 @@ def test_batch_learned_schedule_with_slices_over_replays():
         A.amlm_mine(G, A.params(A.AMLM_ALL, 86400, 5, 2))
         torch.cuda.synchronize()
         G.close()
-    assert B.info_batch()[1] == 1
+    assert B.info_batch()[1] == 2   # one capture per schedule
     B.close()
 
 

@@ -74,7 +74,35 @@ def trained():
     return w, mean, inv_std
 
 
-def test_training_is_deterministic_and_predicts_work(trained):
+def _spearman(a, b):
+    from scipy.stats import spearmanr
+    return float(spearmanr(a, b).correlation)
+
+
+def test_heldout_rank_correlation(trained):
+    """On a graph the model never saw (another seed of the generator), the
+    predicted scatter-gather bytes rank the anchors by their true bytes
+    (counted by the plain miner): the deterministic training gives a fixed
+    correlation, checked against a floor and against the length rule (the
+    sender-window length alone, which is what the schedule would use without
+    the network)."""
+    g = W.mid(209, scale=0.03)
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    pred, lab, wl = A.amlm_costmodel_eval(G, A.params(A.AMLM_ALL, 86400, 6, 2))
+    G.close()
+    assert pred.shape[0] > 10000 and np.isfinite(pred).all()
+    rho_model = _spearman(pred, lab)
+    rho_len = _spearman(wl, lab)
+    print(f"held-out Spearman: model {rho_model:.4f}, window length {rho_len:.4f} over {pred.shape[0]} anchors")
+    # measured on MI355X with this training (deterministic): model 0.465,
+    # window length 0.480 -- the network ranks anchors about as well as the
+    # length rule, not better
+    assert rho_model >= 0.40
+    assert abs(rho_model - rho_len) <= 0.10
+    assert A.amlm_costmodel_length_coef() > 0
+
+
+def test_training_is_deterministic(trained):
     w, mean, inv_std = trained
     assert np.isfinite(w).all() and np.isfinite(mean).all()
     # retrain with the same seed: identical weights
@@ -101,11 +129,36 @@ def test_learned_schedule_counts_equal_static_and_oracle(trained):
     G.close()
 
 
+def test_length_and_given_schedules_equal_static(trained):
+    """The ablation schedules (sender-window length rule, caller-given true
+    costs) slice the same anchors differently and give the same counts,
+    with slices forced by a small split size too."""
+    g = W.mid(211, scale=0.03)
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    base = A.to_u32(A.amlm_mine(G, A.params(A.AMLM_ALL, 86400, 6, 2, A.AMLM_SCHED_STATIC)))
+    _, work = A.amlm_mine_work(G, A.params(A.AMLM_ALL, 86400, 6, 2, A.AMLM_SCHED_LEARNED))
+    torch.cuda.synchronize()
+    cost = torch.log1p(work[3].view(torch.int64).to(torch.float64)).to(torch.float32).contiguous()
+    A.amlm_graph_set_costs(G, cost)
+    for split in (0, 512):
+        A.amlm_tune_set(G, split_bytes=split)
+        for sched in (A.AMLM_SCHED_LEARNED, A.AMLM_SCHED_LENGTH, A.AMLM_SCHED_GIVEN):
+            c = A.to_u32(A.amlm_mine(G, A.params(A.AMLM_ALL, 86400, 6, 2, sched)))
+            A.amlm_graph_sync(G)
+            np.testing.assert_array_equal(c, base, err_msg=f"schedule {sched} split {split}")
+    A.amlm_graph_set_costs(G, None)
+    with pytest.raises(A.AmlmError):
+        A.amlm_mine(G, A.params(A.AMLM_ALL, 86400, 6, 2, A.AMLM_SCHED_GIVEN))
+    G.close()
+
+
 def test_save_load_roundtrip(trained):
     w, mean, inv_std = trained
+    coef = A.amlm_costmodel_length_coef()
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "m.bin")
         A.amlm_costmodel_save(path)
         A.amlm_costmodel_load(path)
         w2, m2, s2 = A.amlm_costmodel_get()
     assert np.array_equal(w, w2) and np.array_equal(mean, m2) and np.array_equal(inv_std, s2)
+    assert A.amlm_costmodel_length_coef() == coef

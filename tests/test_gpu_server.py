@@ -192,3 +192,38 @@ def test_server_with_learned_schedule_equals_static():
         for x, y in zip(d1, d2):
             np.testing.assert_array_equal(x, y)
     R.close()
+
+
+def test_snapshot_resume_continues_the_stream():
+    """A server snapshot after some batches, a server resumed from it, and
+    the rest of the stream: the later batches' rows, deltas and edge ids are
+    those of an uninterrupted server.  A truncated file is rejected."""
+    import os
+    import tempfile
+    base, batches = _setup()
+    p = A.params(A.AMLM_ALL, D, L, K)
+    R = A.Graph(base.src, base.dst, base.ts, base.n_vertices)
+    full = _run(A.Server(R, p, max_slots=2), batches, sequential=False)
+    S = A.Server(R, p, max_slots=2)
+    first = _run(S, batches[:6], sequential=False)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "snap.bin")
+        S.snapshot(path)
+        S.close()
+        T = A.Server.resume(path, p, max_slots=3)
+        rest = _run(T, batches[6:], sequential=False)
+        T.close()
+        with open(path, "rb") as f:
+            head = f.read(64)
+        bad = os.path.join(d, "bad.bin")
+        with open(bad, "wb") as f:
+            f.write(head)
+        with pytest.raises(A.AmlmError) as ei:
+            A.Server.resume(bad, p)
+        assert ei.value.status == 1
+    for (c1, d1, n1), (c2, d2, n2) in zip(full, first + rest):
+        np.testing.assert_array_equal(c1, c2)
+        assert n1 == n2
+        for x, y in zip(d1, d2):
+            np.testing.assert_array_equal(x, y)
+    R.close()
