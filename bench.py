@@ -210,6 +210,59 @@ def bench_batching(A, n_graphs=256, steps=5):
             "hipgraph_captures": captures}
 
 
+def bench_variants(A, g, reps=3):
+    """The paper's variants on a 5M-edge graph: the pattern modifiers (whole
+    mining) and the stage-cell interpreter on patterns the fixed kernels
+    also compute (same counts checked), each timed with HIP events."""
+    import torch
+    PROGS = {
+        # cells: (op, node, peer, tlo, tref, thi, skip, distinct, agg, threshold)
+        "fan_out": [(A.AMLM_CELL_FOR_OUT, A.VAR_U, 0, A.AMLM_T_WINDOW, 0, A.AMLM_T_THROUGH, (), False,
+                     A.AMLM_AGG_SUM, 0)],
+        "sg": [(A.AMLM_CELL_FOR_IN, A.VAR_U, 0, A.AMLM_T_WINDOW, 0, A.AMLM_T_BEFORE, (A.VAR_V,), True,
+                A.AMLM_AGG_AT_LEAST_K, 0),
+               (A.AMLM_CELL_FOR_OUT, 2, 0, A.AMLM_T_WINDOW, 0, A.AMLM_T_BEFORE, (), True, A.AMLM_AGG_AT_LEAST, 1),
+               (A.AMLM_CELL_PROBE, 3, A.VAR_V, A.AMLM_T_AFTER, 1, A.AMLM_T_THROUGH, (), False, A.AMLM_AGG_SUM, 0)],
+    }
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    E = g.n_edges
+
+    def tm(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {"graph": f"{E} edges, {g.n_vertices} accounts, delta=86400s (5M-edge generator, seed 206)"}
+    mods = (("default", A.AMLM_ALL, 6, 2), ("sg_unordered", A.AMLM_ALL | A.AMLM_SG_UNORDERED, 6, 2),
+            ("sg_phase", A.AMLM_ALL | A.AMLM_SG_PHASE, 6, 2),
+            ("deg_columns", A.AMLM_ALL | A.AMLM_DEG_OUT | A.AMLM_DEG_IN, 6, 2),
+            ("cycles_L4", A.AMLM_CYCLES, 4, 2), ("cycles_any_order_L4", A.AMLM_CYCLES | A.AMLM_CYC_ANY_ORDER, 4, 2))
+    for name, pat, L, k in mods:
+        p = A.params(pat, 86400, L, k)
+        out = torch.empty((A.amlm_num_columns(p), E), dtype=torch.int32, device="cuda")
+        ms = tm(lambda: A.amlm_mine(G, p, out))
+        res[name] = {"ms": ms, "edges_per_s": E / (ms * 1e-3), "L": L, "k": k}
+    fixed = A.amlm_mine(G, A.params(A.AMLM_FAN_OUT | A.AMLM_SG, 86400, 2, 2))
+    for (name, cells), col in zip(PROGS.items(), (0, 1)):
+        cc = [A.cell(*c) for c in cells]
+        out = torch.empty(E, dtype=torch.int32, device="cuda")
+        ms = tm(lambda: A.amlm_mine_program(G, cc, 86400, 2, out))
+        p1 = A.params(A.AMLM_FAN_OUT if name == "fan_out" else A.AMLM_SG, 86400, 2, 2)
+        o1 = torch.empty((1, E), dtype=torch.int32, device="cuda")
+        ms_fixed = tm(lambda: A.amlm_mine(G, p1, o1))
+        res[f"program_{name}"] = {"ms": ms, "fixed_kernel_ms": ms_fixed,
+                                  "identical_to_fixed": bool(torch.equal(out, fixed[col]))}
+    A.amlm_graph_sync(G)
+    G.close()
+    return res
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo)."""
     try:
@@ -260,6 +313,7 @@ def main():
     ap.add_argument("--oracle-procs", type=int, default=0, help="oracle processes (0: host cores, at most 16)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-slots", type=int, default=4, help="server slots (batches mined concurrently)")
     ap.add_argument("--serve-inflight", type=int, default=64, help="batches submitted and not yet collected")
     ap.add_argument("--model-cache", default=None, help="load / save the trained cost model here")
@@ -274,6 +328,7 @@ def main():
         args.no_serve = args.no_batch = args.no_cpu_baseline = True
 
     g, delta, L, k = make_workload(args.workload)
+    gh = make_workload("mid_heldout")[0] if not args.profile else None
     ref = cpu_rec = None
     if not args.no_cpu_baseline:
         # the oracle first: its workers are forked, before this process
@@ -375,7 +430,6 @@ def main():
         # bytes, on graphs the model was not trained on
         from scipy.stats import spearmanr
         heldout = {}
-        gh = make_workload("mid_heldout")[0]
         Gh = A.Graph(gh.src, gh.dst, gh.ts, gh.n_vertices)
         for name, GG in (("mid_seed206", Gh), (args.workload, G)):
             pr, lb, wl = A.amlm_costmodel_eval(GG, p)
@@ -429,6 +483,9 @@ def main():
         out["p99_stream_latency_ms"] = out["stream"]["load_80"]["p99_ms"]
     if not args.no_batch:
         out["batching"] = bench_batching(A)
+    if gh is not None and not args.no_variants:
+        log("[bench] variants and stage-cell programs on the 5M-edge graph ...")
+        out["variants"] = bench_variants(A, gh)
     if cpu_rec is not None:
         out["cpu_baseline"] = cpu_rec
     print(json.dumps(out), flush=True)

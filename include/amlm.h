@@ -215,7 +215,8 @@ amlm_status amlm_stage_times(amlm_graph *g, float *ms);
 
 /* Pin the launch shape of later amlm_mine calls on g (no paper passage; the
  * launch shape of the persistent kernels; 0 keeps the default of a field):
- * block = list items per scatter-gather work unit (clamped to [4, 8]);
+ * block = list items per scatter-gather work unit (clamped to [4, 16];
+ * default 8 for the static schedule, 16 for the sliced ones);
  * sg_blocks, cyc_blocks = persistent grid sizes; split_bytes = learned
  * schedule only: an anchor whose predicted scatter-gather bytes exceed this
  * is cut into slices of about this size, each its own work unit (default

@@ -415,8 +415,8 @@ MineLaunch default_launch(const amlm_graph *g) {
   cfg.sg_blocks = (uint32_t)(di.num_cu * di.sg_occ);
   cfg.cyc_blocks = (uint32_t)(di.num_cu * di.cyc_occ);
   cfg.cyc_blocks_small = (uint32_t)(di.num_cu * di.cyc_occ_small);
-  cfg.sg_chunk = kSgChunkMax;  // anchors per work-stealing grab
-  if (g->tune.sg_chunk) cfg.sg_chunk = g->tune.sg_chunk;
+  cfg.sg_chunk = kStaticChunk;  // anchors per work-stealing grab
+  if (g->tune.sg_chunk) cfg.sg_chunk = cfg.learned_chunk = g->tune.sg_chunk;
   if (g->tune.sg_blocks) cfg.sg_blocks = g->tune.sg_blocks;
   if (g->tune.cyc_blocks) cfg.cyc_blocks = cfg.cyc_blocks_small = g->tune.cyc_blocks;
   if (g->tune.split_bytes) cfg.split_bytes = g->tune.split_bytes;

@@ -391,7 +391,7 @@ static amlm_status autotune_impl(amlm_graph *g, const amlm_params *ps, uint32_t 
     g->tune = best;
   } else {
     DeviceInfo &di = device_info();
-    const uint32_t chunks[] = {kMinBlock, 6, kSgChunkMax};
+    const uint32_t chunks[] = {kMinBlock, 8, 12, kSgChunkMax};
     uint32_t Lmax = 0;
     for (uint32_t i = 0; i < n_params; i++) Lmax = std::max(Lmax, ps[i].max_cycle_len);
     const int cyc_occ = Lmax <= kCycSmallL ? di.cyc_occ_small : di.cyc_occ;

@@ -104,6 +104,11 @@ __global__ __launch_bounds__(256) void k_interp(GraphView g, Prog P, int64_t del
       f.pos = lower_bound_i32(g.in_t, rs, re, f.lo);
       f.end = upper_bound_i32(g.in_t, f.pos, re, f.hi);
     }
+    if (i + 1 == P.n && c.agg == kAggSum && !c.distinct && !c.skip) {
+      // an innermost plain count: the slice's length, without walking it
+      f.acc = min(f.end - f.pos, ceil);
+      f.pos = f.end;
+    }
     return true;
   };
   // fold one child value into cell i

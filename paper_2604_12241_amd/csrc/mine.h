@@ -36,7 +36,7 @@ constexpr bool kPrefetchClaim = AMLM_PREFETCH_CLAIM != 0;
 #define AMLM_BLOOM_K 4
 #endif
 #ifndef AMLM_SG_CHUNK_MAX
-#define AMLM_SG_CHUNK_MAX 8
+#define AMLM_SG_CHUNK_MAX 16
 #endif
 #ifndef AMLM_JOIN_UNROLL
 #define AMLM_JOIN_UNROLL 8
@@ -50,6 +50,11 @@ constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;
 constexpr int kBloomK = AMLM_BLOOM_K;                   // bits set per key, all in one 32-bit word
 constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
+// default anchors per work unit: the static schedule's blocks of the list
+// (8: its units of one hub then spread over more waves; 16 measured slower,
+// k_sg 10.4 -> 11.5 ms) and the learned schedule's light blocks, whose heavy
+// anchors are already sliced (16: k_sg 7.9 -> 7.5 ms on the 32M-edge graph)
+constexpr uint32_t kStaticChunk = 8, kLearnedChunk = 16;
 constexpr uint32_t kLongPair = 64;                      // slices scanned by the whole wave
 #ifndef AMLM_REV_RATIO
 #define AMLM_REV_RATIO 32
@@ -158,7 +163,7 @@ struct MineLaunch {
   uint32_t sched = kSchedStatic;
   float len_coef = 0.f;          // length schedule: bytes per sender-window entry
   const float *given = nullptr;  // given schedule: log1p(bytes) per edge id
-  uint32_t learned_chunk = kSgChunkMax;  // anchors per chunk in the learned schedule
+  uint32_t learned_chunk = kLearnedChunk;  // anchors per chunk in the sliced schedules
   uint32_t split_bytes = kSplitBytes;    // learned schedule: predicted bytes per slice
   // optional second stream: the cycle kernel runs there, concurrently with
   // the cost model and work units (fork and join through the two events)

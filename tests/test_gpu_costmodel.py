@@ -64,10 +64,10 @@ def test_gradient_is_deterministic():
 
 @pytest.fixture(scope="module")
 def trained():
-    gs = [W.mid(202 + i, scale=0.02) for i in range(2)]
+    gs = [W.mid(202 + i, scale=0.1) for i in range(2)]
     Gs = [A.Graph(g.src, g.dst, g.ts, g.n_vertices) for g in gs]
     ps = [A.params(A.AMLM_ALL, 86400, 6, 2)] * len(Gs)
-    A.amlm_costmodel_train(Gs, ps, epochs=3, batch=1024, seed=5)
+    A.amlm_costmodel_train(Gs, ps, epochs=4, batch=4096, seed=5)
     w, mean, inv_std = A.amlm_costmodel_get()
     for G in Gs:
         G.close()
@@ -94,11 +94,11 @@ def test_heldout_rank_correlation(trained):
     rho_model = _spearman(pred, lab)
     rho_len = _spearman(wl, lab)
     print(f"held-out Spearman: model {rho_model:.4f}, window length {rho_len:.4f} over {pred.shape[0]} anchors")
-    # measured on MI355X with this training (deterministic): model 0.465,
-    # window length 0.480 -- the network ranks anchors about as well as the
-    # length rule, not better
-    assert rho_model >= 0.40
-    assert abs(rho_model - rho_len) <= 0.10
+    # measured on MI355X with this training (deterministic): model 0.678,
+    # window length 0.480 (a smaller model, 2 x 100k-edge graphs and 3
+    # epochs, gave 0.465: no better than the length)
+    assert rho_model >= 0.60
+    assert rho_model >= rho_len + 0.10
     assert A.amlm_costmodel_length_coef() > 0
 
 
@@ -106,9 +106,9 @@ def test_training_is_deterministic(trained):
     w, mean, inv_std = trained
     assert np.isfinite(w).all() and np.isfinite(mean).all()
     # retrain with the same seed: identical weights
-    gs = [W.mid(202 + i, scale=0.02) for i in range(2)]
+    gs = [W.mid(202 + i, scale=0.1) for i in range(2)]
     Gs = [A.Graph(g.src, g.dst, g.ts, g.n_vertices) for g in gs]
-    A.amlm_costmodel_train(Gs, [A.params(A.AMLM_ALL, 86400, 6, 2)] * 2, epochs=3, batch=1024, seed=5)
+    A.amlm_costmodel_train(Gs, [A.params(A.AMLM_ALL, 86400, 6, 2)] * 2, epochs=4, batch=4096, seed=5)
     w2, _, _ = A.amlm_costmodel_get()
     assert np.array_equal(w.view(np.uint32), w2.view(np.uint32))
     for G in Gs:
