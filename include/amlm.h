@@ -91,7 +91,7 @@ typedef enum {
  * it s -> m must come strictly before m -> v. */
 #define AMLM_SG_UNORDERED 32u
 /* modifier of AMLM_SG (adds no column; excludes AMLM_SG_UNORDERED): the
- * legs are ordered by phase, "integration occurs after placement"
+ * legs are ordered by phase, the integration phase after the placement phase
  * (Section 4): s counts when some split time tau has u's scatter leg and
  * those of at least k - 1 other intermediates in [t - delta, tau) and their
  * gather legs in [tau, t] (u's gather leg is the anchor).  k <= 8. */
@@ -288,7 +288,7 @@ amlm_status amlm_mine_work(amlm_graph *g, const amlm_params *p, uint32_t *counts
 #define AMLM_AGG_SUM 0u        /* the cell's value: the sum of its bindings' inner values
                                   (1 per binding of the innermost loop) */
 #define AMLM_AGG_AT_LEAST 1u   /* the number of bindings whose inner value is >= threshold */
-#define AMLM_AGG_AT_LEAST_K 2u /* the same with threshold k ("at least N", Section 4) */
+#define AMLM_AGG_AT_LEAST_K 2u /* the same with threshold k (Section 4's minimum number taking part) */
 typedef struct {
     uint8_t op;        /* AMLM_CELL_* */
     uint8_t node;      /* the vertex it expands (or probes from) */

@@ -22,7 +22,7 @@
  *                t - delta <= ts_a < ts_b <= t
  *                (the intersection N2.out_neigh with N1.in_neigh; Section 3's
  *                per-intermediate partial order t_i < t_{i+1})
- *   SG_k(e)    = #{s in S(e) : |M_e(s)| >= k}   ("at least N", Section 4)
+ *   SG_k(e)    = #{s in S(e) : |M_e(s)| >= k}   (a threshold on the number of intermediates, Section 4)
  *   with OR_SG_UNORDERED, M_e(s) drops the order of the two legs:
  *                t - delta <= ts_a < t and t - delta <= ts_b <= t, the
  *                window-only checks of the compiled scatter-gather example
@@ -30,14 +30,14 @@
  *   GS_k(e)    = |S(e)| if |S(e)| >= k and |D(e)| >= k, else 0, with
  *                tau = earliest ts of an edge into u from s != v in [t-delta, t)
  *                and D(e) = distinct d with u -> d, tau < ts <= t
- *                ("integration occurs after placement", Section 4)
+ *                (the integration phase follows the placement phase, Section 4)
  *   with OR_SG_PHASE, the legs are ordered by phase instead: every scatter
  *                leg of the chosen intermediates (u's included) comes before
  *                every gather leg (the anchor is u's), i.e. SG_k counts the s
  *                for which some split time tau in (t - delta, t] has u's
  *                scatter leg before tau and at least k - 1 other m with a
  *                scatter leg in [t - delta, tau) and a gather leg in
- *                [tau, t] ("integration occurs after placement", Section 4)
+ *                [tau, t] (integration after placement as a whole, Section 4)
  *   CYC_l(e)   = number of l-cycles containing e, 2 <= l <= L: l edges
  *                c_1..c_l with dst(c_i) = src(c_{i+1}) cyclically, strictly
  *                increasing timestamps, ts(c_l) - ts(c_1) <= delta and

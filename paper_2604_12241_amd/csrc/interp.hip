@@ -7,7 +7,7 @@
 // bound vertices (differentiate, difference with a singleton), keep each
 // neighbour once (a stage's output is a vertex set), and folds what its
 // inner cells return: a sum, or how many of its bindings reach a threshold
-// (Section 4's "at least N").  One lane interprets the program for one
+// (Section 4's threshold on how many take part).  One lane interprets the program for one
 // anchor with an explicit stack of cell states, so a new pattern needs no
 // new kernel.
 #include "api_internal.h"
