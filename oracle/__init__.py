@@ -21,6 +21,8 @@ SG_UNORDERED = 32  # modifier of SG: the two legs of an intermediate in either o
 DEG_OUT, DEG_IN = 64, 128   # distinct counterparties in the FAN windows (columns after the cycles)
 SG_PHASE = 256     # modifier of SG: every scatter leg before every gather leg
 CYC_ANY_ORDER = 512  # modifier of CYC: the cycle's edges in any order within delta
+PART = 1024        # participation columns: the SG / GS instances each edge belongs to
+SG_SIZES = 2048    # SG_k instances binned by size: exactly k, k+1, k+2, at least k+3 intermediates
 
 
 def build_oracle() -> str:

@@ -52,6 +52,26 @@
  *   DEG_IN(e)  = distinct sources of v's in-edges with ts in W (the
  *                counterparty counts beside the transaction counts FAN_OUT
  *                and FAN_IN; Section 8's Degree features)
+ *   with OR_PART, every edge also gets the number of scatter-gather and
+ *                gather-scatter instances it belongs to (Table 2's features
+ *                count, per transaction, the instances it takes part in):
+ *                an instance is a pair (anchor e, sender s) that SG_k(e) or
+ *                GS_k(e) counts, and an edge belongs to it when it is an
+ *                edge of some realisation of it (one edge per leg, the
+ *                legs' order and window conditions met):
+ *     SG_PART    the anchor; every s -> u in [t-delta, t); for each
+ *                m in M_e(s) other than u, every s -> m in [t-delta, t)
+ *                earlier than m's latest gather leg into v (any, unordered)
+ *                and every m -> v in [t-delta, t] later than m's first
+ *                scatter leg from s (any, unordered); not with OR_SG_PHASE
+ *     GS_PART    sender s's legs s -> u in [t-delta, t), and u's
+ *                scatter legs u -> d with tau < ts <= t (the anchor among
+ *                them), which belong to all |S(e)| instances of e
+ *   with OR_SG_SIZES, the SG_k instances of e binned by their size (the
+ *                streaming passage of Section 5 counts scatter-gathers of
+ *                different sizes): the number of s in S(e) with
+ *                |M_e(s)| = k, = k + 1, = k + 2 and >= k + 3 (four columns
+ *                summing to SG_k(e)); not with OR_SG_PHASE
  *
  * Stage outputs are vertex sets (Algorithm 1: the output of a stage is nodes,
  * not edges), so S, M and D count distinct vertices; FAN counts edges; cycles
@@ -85,10 +105,14 @@
  * Only SG / GS and CYC stages that are asked for are charged.
  *
  * Columns, in this order, for the requested patterns only:
- *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L, DEG_OUT, DEG_IN.
+ *   FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L, DEG_OUT, DEG_IN, SG_PART,
+ *   GS_PART (with OR_PART, each when its pattern is asked for), then the
+ *   four SG size bins.
  * Layout [ncols][n_edges].  DEG_OUT / DEG_IN charge 8 bytes per window
  * element to B_io; the phase-ordered SG scans each sender's out-slice until
- * its condition first holds (the same min with the gather side).
+ * its condition first holds (the same min with the gather side).  The
+ * participation and size columns add only their 4 output bytes each to
+ * B_io.
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
@@ -106,6 +130,8 @@
 #define OR_DEG_IN 128u
 #define OR_SG_PHASE 256u     /* modifies OR_SG; adds no column */
 #define OR_CYC_ANY_ORDER 512u /* modifies OR_CYC; adds no column */
+#define OR_PART 1024u        /* participation columns of SG and GS */
+#define OR_SG_SIZES 2048u    /* SG instances binned by their number of intermediates */
 
 typedef struct {
     uint64_t n;
@@ -197,6 +223,9 @@ uint32_t oracle_num_columns(uint32_t patterns, uint32_t L) {
     if (patterns & OR_CYC) c += L - 1;
     if (patterns & OR_DEG_OUT) c++;
     if (patterns & OR_DEG_IN) c++;
+    if ((patterns & OR_PART) && (patterns & OR_SG)) c++;
+    if ((patterns & OR_PART) && (patterns & OR_GS)) c++;
+    if (patterns & OR_SG_SIZES) c += 4;
     return c;
 }
 
@@ -206,6 +235,7 @@ typedef struct {
     int64_t *maxb;
     uint64_t *slist;
     int64_t *iv_f, *iv_g;   /* phase order: (first scatter, last gather) per intermediate */
+    int64_t *minf;          /* first scatter time from the current sender, per intermediate */
     uint64_t clock;
 } og_scratch;
 
@@ -215,13 +245,15 @@ static int scratch_init(og_scratch *s, uint32_t nv) {
     s->stamp_m = (uint64_t *)calloc(nn, 8); s->stamp_d = (uint64_t *)calloc(nn, 8);
     s->maxb = (int64_t *)calloc(nn, 8); s->slist = (uint64_t *)calloc(nn, 8);
     s->iv_f = (int64_t *)calloc(nn, 8); s->iv_g = (int64_t *)calloc(nn, 8);
+    s->minf = (int64_t *)calloc(nn, 8);
     s->clock = 0;
-    return (s->stamp_s && s->stamp_b && s->stamp_m && s->stamp_d && s->maxb && s->slist && s->iv_f && s->iv_g)
+    return (s->stamp_s && s->stamp_b && s->stamp_m && s->stamp_d && s->maxb && s->slist && s->iv_f && s->iv_g &&
+            s->minf)
                ? 0 : 2;
 }
 static void scratch_free(og_scratch *s) {
     free(s->stamp_s); free(s->stamp_b); free(s->stamp_m); free(s->stamp_d); free(s->maxb); free(s->slist);
-    free(s->iv_f); free(s->iv_g);
+    free(s->iv_f); free(s->iv_g); free(s->minf);
 }
 
 /* Phase order: is there a split time tau with f_u < tau <= (every chosen
@@ -240,14 +272,18 @@ static int phase_ok(const int64_t *f, const int64_t *g, uint64_t n, int64_t f_u,
     return 0;
 }
 
-/* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k (written to out4).
+/* Anchored columns of edge e: FAN_OUT, FAN_IN, SG_k, GS_k, DEG_OUT, DEG_IN and
+ * the four size bins of SG_k (written to out4[0..9]).
  * want_sg / want_gs: which of the scatter-gather columns are asked for (they
- * only decide what *work is charged).  work (may be NULL) receives B_sg/gs. */
+ * only decide what *work is charged).  work (may be NULL) receives B_sg/gs.
+ * psg / pgs (may be NULL): per-edge participation counters, credited with
+ * the edges of every SG / GS instance anchored at e. */
 static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delta, uint32_t k, int unordered,
-                     int phase, int want_sg, int want_gs, int want_deg, uint64_t out4[6], uint64_t *work) {
+                     int phase, int want_sg, int want_gs, int want_deg, uint64_t out4[10], uint64_t *work,
+                     uint64_t *psg, uint64_t *pgs) {
     uint32_t u = g->src[e], v = g->dst[e];
     int64_t t = g->ts[e], lo = t - delta;
-    out4[0] = out4[1] = out4[2] = out4[3] = out4[4] = out4[5] = 0;
+    for (int i = 0; i < 10; i++) out4[i] = 0;
     if (work) *work = 0;
     if (u == v) return;
 
@@ -342,11 +378,35 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
             /* maxb >= lo always: it is a gather time inside the window */
             if (sc->stamp_b[m] == cb && (unordered || g->ts[a] < sc->maxb[m]) && sc->stamp_m[m] != cm) {
                 sc->stamp_m[m] = cm;
+                sc->minf[m] = g->ts[a]; /* slices run in time order: m's first leg from s */
                 nm++;
                 if (m != u && k >= 2 && ++found == k - 1) n_s = p - r0 + 1;
             }
         }
-        if (nm >= k) sg++;
+        if (nm >= k) {
+            sg++;
+            /* size bins: exactly k, k + 1, k + 2, at least k + 3 */
+            out4[6 + (nm - k < 3 ? nm - k : 3)]++;
+            if (psg) {
+                /* the edges of the instance (e, s): the anchor, the sender
+                   legs, and for every other intermediate m each scatter leg
+                   with a later gather leg and each gather leg with an
+                   earlier scatter leg (any, unordered) */
+                psg[e]++;
+                for (uint64_t p = p0; p < p1; p++)
+                    if (g->src[g->in_e[p]] == s) psg[g->in_e[p]]++;
+                for (uint64_t p = r0; p < r1; p++) {
+                    uint64_t a = g->out_e[p];
+                    uint32_t m = g->dst[a];
+                    if (m != u && sc->stamp_m[m] == cm && (unordered || g->ts[a] < sc->maxb[m])) psg[a]++;
+                }
+                for (uint64_t p = q0; p < q1; p++) {
+                    uint64_t b = g->in_e[p];
+                    uint32_t m = g->src[b];
+                    if (m != u && sc->stamp_m[m] == cm && (unordered || g->ts[b] > sc->minf[m])) psg[b]++;
+                }
+            }
+        }
         if (want_sg) w += 8 * (n_s < r_gather ? n_s : r_gather);
     }
     out4[2] = sg;
@@ -363,7 +423,16 @@ static void anchored(const og_graph *g, og_scratch *sc, uint64_t e, int64_t delt
                 if (++nd == k && scanned == d1 - d0) scanned = p - d0 + 1;
             }
         }
-        if (nd >= k) out4[3] = nS;
+        if (nd >= k) {
+            out4[3] = nS;
+            if (pgs) {
+                /* each of the nS instances holds all of u's scatter legs in
+                   (tau, t] and its own sender's legs into u */
+                for (uint64_t p = d0; p < d1; p++) pgs[g->out_e[p]] += nS;
+                for (uint64_t p = p0; p < p1; p++)
+                    if (g->src[g->in_e[p]] != v) pgs[g->in_e[p]]++;
+            }
+        }
         if (want_gs) w += 8 * scanned;
     }
     if (work) *work = w;
@@ -430,8 +499,10 @@ static int check_params(uint32_t patterns, int64_t delta, uint32_t L, uint32_t k
     if ((patterns & OR_SG_UNORDERED) && !(patterns & OR_SG)) return 3;
     if ((patterns & OR_SG_PHASE) && (!(patterns & OR_SG) || (patterns & OR_SG_UNORDERED))) return 3;
     if ((patterns & OR_CYC_ANY_ORDER) && !(patterns & OR_CYC)) return 3;
+    if ((patterns & OR_PART) && (!(patterns & (OR_SG | OR_GS)) || (patterns & OR_SG_PHASE))) return 3;
+    if ((patterns & OR_SG_SIZES) && (!(patterns & OR_SG) || (patterns & OR_SG_PHASE))) return 3;
     if (patterns & ~(OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_CYC | OR_SG_UNORDERED | OR_DEG_OUT | OR_DEG_IN |
-                     OR_SG_PHASE | OR_CYC_ANY_ORDER))
+                     OR_SG_PHASE | OR_CYC_ANY_ORDER | OR_PART | OR_SG_SIZES))
         return 3;
     if (!(patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_CYC | OR_DEG_OUT | OR_DEG_IN))) return 3;
     return 0;
@@ -479,26 +550,38 @@ int oracle_mine_ex(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t 
     if (patterns & OR_CYC) { c_cy = col; col += L - 1; }
     if (patterns & OR_DEG_OUT) c_do = col++;
     if (patterns & OR_DEG_IN) c_di = col++;
-    uint64_t *acc = NULL;
+    int c_ps = -1, c_pg = -1;
+    if ((patterns & OR_PART) && (patterns & OR_SG)) c_ps = col++;
+    if ((patterns & OR_PART) && (patterns & OR_GS)) c_pg = col++;
+    int c_sz = (patterns & OR_SG_SIZES) ? (int)col : -1;
+    if (c_sz >= 0) col += 4;
+    uint64_t *acc = NULL, *psg = NULL, *pgs = NULL;
     if (c_cy >= 0) {
         acc = (uint64_t *)calloc((size_t)(L - 1) * (n ? n : 1), sizeof(uint64_t));
         if (!acc) { og_free(&g); scratch_free(&sc); return 2; }
+    }
+    if (c_ps >= 0) psg = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t));
+    if (c_pg >= 0) pgs = (uint64_t *)calloc(n ? n : 1, sizeof(uint64_t));
+    if ((c_ps >= 0 && !psg) || (c_pg >= 0 && !pgs)) {
+        free(acc); free(psg); free(pgs); og_free(&g); scratch_free(&sc);
+        return 2;
     }
     double t0 = now_s();
     if (work)
         for (uint64_t e = a_lo; e < a_hi; e++) work[e] = 12 + 4 * (uint64_t)ncols;
     if (patterns & (OR_FAN_OUT | OR_FAN_IN | OR_SG | OR_GS | OR_DEG_OUT | OR_DEG_IN)) {
         for (uint64_t e = a_lo; e < a_hi; e++) {
-            uint64_t r[6];
+            uint64_t r[10];
             anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, (patterns & OR_SG_PHASE) != 0,
                      (patterns & OR_SG) != 0, (patterns & OR_GS) != 0, (patterns & (OR_DEG_OUT | OR_DEG_IN)) != 0, r,
-                     work ? work + n + e : NULL);
+                     work ? work + n + e : NULL, psg, pgs);
             if (c_fo >= 0) counts[(uint64_t)c_fo * n + e] = sat(r[0], ceiling);
             if (c_fi >= 0) counts[(uint64_t)c_fi * n + e] = sat(r[1], ceiling);
             if (c_sg >= 0) counts[(uint64_t)c_sg * n + e] = sat(r[2], ceiling);
             if (c_gs >= 0) counts[(uint64_t)c_gs * n + e] = sat(r[3], ceiling);
             if (c_do >= 0) counts[(uint64_t)c_do * n + e] = sat(r[4], ceiling);
             if (c_di >= 0) counts[(uint64_t)c_di * n + e] = sat(r[5], ceiling);
+            for (int b = 0; b < 4 && c_sz >= 0; b++) counts[(uint64_t)(c_sz + b) * n + e] = sat(r[6 + b], ceiling);
             if (work && src[e] != dst[e]) {
                 /* the distinct-counterparty scans read the FAN slices */
                 if (c_do >= 0) work[e] += 8 * r[0];
@@ -527,6 +610,11 @@ int oracle_mine_ex(uint64_t n, uint32_t nv, const uint32_t *src, const uint32_t 
                 counts[(uint64_t)(c_cy + l) * n + e] = sat(acc[(uint64_t)l * n + e], ceiling);
         free(acc);
     }
+    /* participation counts: credited to any edge by the anchors in range */
+    for (uint64_t e = 0; e < n && c_ps >= 0; e++) counts[(uint64_t)c_ps * n + e] = sat(psg[e], ceiling);
+    for (uint64_t e = 0; e < n && c_pg >= 0; e++) counts[(uint64_t)c_pg * n + e] = sat(pgs[e], ceiling);
+    free(psg);
+    free(pgs);
     if (seconds) *seconds = t1 - t0;
     og_free(&g);
     scratch_free(&sc);
@@ -615,7 +703,7 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
     int rc = check_params(patterns, delta, L, k);
     if (rc) return rc;
     /* the time-ordered patterns only (the through-edge enumeration is theirs) */
-    if (patterns & (OR_SG_PHASE | OR_CYC_ANY_ORDER | OR_DEG_OUT | OR_DEG_IN)) return 3;
+    if (patterns & (OR_SG_PHASE | OR_CYC_ANY_ORDER | OR_DEG_OUT | OR_DEG_IN | OR_PART | OR_SG_SIZES)) return 3;
     og_graph g;
     og_scratch sc;
     if ((rc = og_build(&g, n, nv, src, dst, ts))) return rc;
@@ -626,8 +714,8 @@ int oracle_mine_selected(uint64_t n, uint32_t nv, const uint32_t *src, const uin
         uint64_t e = sel[i];
         if (e >= n) { og_free(&g); scratch_free(&sc); return 3; }
         uint32_t col = 0;
-        uint64_t r[6];
-        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, 0, 0, r, NULL);
+        uint64_t r[10];
+        anchored(&g, &sc, e, delta, k, (patterns & OR_SG_UNORDERED) != 0, 0, 0, 0, 0, r, NULL, NULL, NULL);
         if (patterns & OR_FAN_OUT) out[(uint64_t)(col++) * n_sel + i] = sat(r[0], 0xffffffffu);
         if (patterns & OR_FAN_IN) out[(uint64_t)(col++) * n_sel + i] = sat(r[1], 0xffffffffu);
         if (patterns & OR_SG) out[(uint64_t)(col++) * n_sel + i] = sat(r[2], 0xffffffffu);

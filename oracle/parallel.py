@@ -5,9 +5,12 @@ Each worker mines the anchors of one contiguous edge-id range with the plain
 single-threaded oracle (``mine_ex`` with ``a_lo, a_hi``).  The anchored
 columns (FAN_OUT, FAN_IN, SG, GS) of different ranges are disjoint; cycles are
 enumerated once, from their last edge, so a cycle is found by exactly one
-worker and its credits to every one of its edges add up across workers.  The
-merge therefore sums the cycle columns in 64 bits and saturates once, which
-gives the full mining exactly.
+worker and its credits to every one of its edges add up across workers, and
+so do the participation credits of the scatter-gather and gather-scatter
+instances (each belongs to its anchor's range).  The merge therefore sums
+every column after the first four in 64 bits (the distinct-counterparty
+columns are nonzero only at a range's own anchors) and saturates once,
+which gives the full mining exactly.
 
 Workers are forked: the edge arrays are shared copy-on-write, and the caller
 must not have initialised a GPU runtime in this process.

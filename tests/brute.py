@@ -10,9 +10,12 @@ import numpy as np
 
 
 def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = False,
-                 sg_phase: bool = False, cyc_any_order: bool = False, deg: bool = False) -> np.ndarray:
+                 sg_phase: bool = False, cyc_any_order: bool = False, deg: bool = False,
+                 sizes: bool = False) -> np.ndarray:
     """Columns FAN_OUT, FAN_IN, SG_k, GS_k, CYC_2..CYC_L (then DEG_OUT,
-    DEG_IN when deg); uint64 [4+L-1(+2), n].
+    DEG_IN when deg, then the four SG size bins when sizes: senders whose
+    intermediate set has exactly k, k+1, k+2 and at least k+3 members);
+    uint64 [4+L-1(+2)(+4), n].
     sg_unordered: an intermediate's gather leg may come before its scatter
     leg (both inside the window).  sg_phase: some split time tau has every
     chosen scatter leg (u's among them) in [t - delta, tau) and every gather
@@ -24,7 +27,8 @@ def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = 
     ts = [int(x) for x in ts]
     n = len(src)
     E = [i for i in range(n) if src[i] != dst[i]]
-    out = np.zeros((4 + L - 1 + (2 if deg else 0), n), dtype=np.uint64)
+    nbase = 4 + L - 1 + (2 if deg else 0)
+    out = np.zeros((nbase + (4 if sizes else 0), n), dtype=np.uint64)
     for e in E:
         u, v, t = src[e], dst[e], ts[e]
         lo = t - delta
@@ -64,6 +68,8 @@ def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = 
                         break
             if len(M) >= k:
                 sg += 1
+                if sizes:
+                    out[nbase + min(len(M) - k, 3), e] += 1
         out[2, e] = sg
         taus = [ts[a] for a in E if dst[a] == u and src[a] != v and lo <= ts[a] < t]
         if taus:
@@ -118,6 +124,68 @@ def brute_counts(src, dst, ts, delta: int, L: int, k: int, sg_unordered: bool = 
         return out
     for c1 in E:
         extend([c1])
+    return out
+
+
+def brute_part(src, dst, ts, delta: int, k: int, sg_unordered: bool = False):
+    """Participation counts (SG_PART, GS_PART), uint64 [2, n], by literal
+    enumeration of realisations.  A scatter-gather instance is (anchor e,
+    sender s) with SG_k(e) counting s; a realisation picks a sender leg
+    s -> u before t (u's gather leg being e) and, for a set of other
+    intermediates with the set at least k - 1 large, one (scatter, gather)
+    leg pair each that meets the order and window conditions.  Every edge of
+    every realisation is credited once per instance.  A gather-scatter
+    instance is (anchor e, sender s in S(e)) with GS_k(e) > 0: its edges are
+    s's legs into u in [t - delta, t) and u's out-edges in (tau, t]."""
+    import itertools
+    src = [int(x) for x in src]
+    dst = [int(x) for x in dst]
+    ts = [int(x) for x in ts]
+    n = len(src)
+    E = [i for i in range(n) if src[i] != dst[i]]
+    out = np.zeros((2, n), dtype=np.uint64)
+    for e in E:
+        u, v, t = src[e], dst[e], ts[e]
+        lo = t - delta
+        S = {src[a] for a in E if dst[a] == u and src[a] != v and lo <= ts[a] < t}
+        for s in S:
+            sender_legs = [a for a in E if src[a] == s and dst[a] == u and lo <= ts[a] < t]
+            pairs = {}
+            for a in E:
+                if src[a] != s or dst[a] == u or not (lo <= ts[a] < t):
+                    continue
+                for b in E:
+                    if src[b] != dst[a] or dst[b] != v or not (lo <= ts[b] <= t):
+                        continue
+                    if sg_unordered or ts[a] < ts[b]:
+                        pairs.setdefault(dst[a], []).append((a, b))
+            others = sorted(pairs)
+            if 1 + len(others) < k:
+                continue
+            members = set()
+            # every choice of (no pair | one pair) per other intermediate
+            for pick in itertools.product(*[[None] + pairs[m] for m in others]):
+                if sum(1 for x in pick if x is not None) < k - 1:
+                    continue
+                for x in pick:
+                    if x is not None:
+                        members.update(x)
+            for a in sender_legs:
+                members.add(a)
+            members.add(e)
+            for f in members:
+                out[0, f] += 1
+        taus = [ts[a] for a in E if dst[a] == u and src[a] != v and lo <= ts[a] < t]
+        if taus:
+            tau = min(taus)
+            scat = [b for b in E if src[b] == u and tau < ts[b] <= t]
+            if len(S) >= k and len({dst[b] for b in scat}) >= k:
+                for s in S:
+                    for a in E:
+                        if src[a] == s and dst[a] == u and lo <= ts[a] < t:
+                            out[1, a] += 1
+                    for b in scat:
+                        out[1, b] += 1
     return out
 
 

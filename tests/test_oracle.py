@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2604_12241_amd import workloads as W
-from tests.brute import brute_counts
+from tests.brute import brute_counts, brute_part
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 T0 = W.T0
@@ -288,6 +288,93 @@ def test_distinct_counterparty_closed_form(K, R):
     np.testing.assert_array_equal(o[3, K:], np.minimum(j + 1, R))
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_participation_matches_brute_force(seed):
+    """SG_PART / GS_PART against the literal enumeration of every
+    realisation of every instance (ordered and unordered legs); the other
+    columns do not move."""
+    rng = np.random.default_rng(5000 + seed)
+    g = W.random_small(seed + 900, n_edges=int(rng.integers(20, 60)), n_vertices=int(rng.integers(3, 7)),
+                       t_range=int(rng.integers(3, 20)))
+    delta, k, un = int(rng.integers(3, 25)), int(rng.integers(1, 4)), bool(seed % 2)
+    pats = oracle.ALL | oracle.PART | (oracle.SG_UNORDERED if un else 0)
+    o = mine(g.src, g.dst, g.ts, g.n_vertices, delta, 3, k, pats)
+    b = brute_part(g.src, g.dst, g.ts, delta, k, sg_unordered=un)
+    np.testing.assert_array_equal(o[6:8].astype(np.uint64), b)
+    np.testing.assert_array_equal(o[:6], mine(g.src, g.dst, g.ts, g.n_vertices, delta, 3, k, pats & ~oracle.PART))
+    assert (o[6] >= o[2]).all() and (o[7] >= o[3]).all()   # an anchor is in its own instances
+    # one column alone, in the last place
+    only = mine(g.src, g.dst, g.ts, g.n_vertices, delta, 3, k, oracle.GS | oracle.PART)
+    np.testing.assert_array_equal(only[1], o[7])
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_size_bins_match_brute_force(seed):
+    """The four SG size bins against the literal enumeration (ordered and
+    unordered legs); they sum to SG_k and leave every other column alone."""
+    rng = np.random.default_rng(6000 + seed)
+    nv = int(rng.integers(4, 12))
+    g = W.random_small(seed + 950, n_edges=int(rng.integers(20, 120)), n_vertices=nv,
+                       t_range=int(rng.integers(3, 40)))
+    delta, k, un = int(rng.integers(3, 40)), int(rng.integers(1, 4)), bool(seed % 2)
+    pats = oracle.ALL | oracle.SG_SIZES | (oracle.SG_UNORDERED if un else 0)
+    o = mine(g.src, g.dst, g.ts, g.n_vertices, delta, 3, k, pats)
+    b = brute_counts(g.src, g.dst, g.ts, delta, 3, k, sg_unordered=un, sizes=True)
+    np.testing.assert_array_equal(o.astype(np.uint64), b)
+    np.testing.assert_array_equal(o[-4:].sum(axis=0), o[2])
+    np.testing.assert_array_equal(o[:-4], mine(g.src, g.dst, g.ts, g.n_vertices, delta, 3, k,
+                                               pats & ~oracle.SG_SIZES))
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 7])
+def test_size_bins_closed_form(K):
+    """The scatter-gather chain: the anchor at gather j has one sender whose
+    intermediate set is {m_1..m_j}, so it lands in bin min(j - k, 3) when
+    j >= k."""
+    s, d, t, nv = _motif_graph(*W.motif_scatter_gather(K))
+    for k in (1, 2, 3):
+        o = mine(s, d, t, nv, 86400, 4, k, oracle.SG | oracle.SG_SIZES)
+        j = np.arange(1, K + 1)
+        for b in range(4):
+            exp = ((j >= k) & (np.minimum(j - k, 3) == b)).astype(np.uint32)
+            np.testing.assert_array_equal(o[1 + b, K:], exp)
+            np.testing.assert_array_equal(o[1 + b, :K], 0)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 8])
+def test_participation_scatter_gather_closed_form(K):
+    """Scatters s -> m_i (times 1..K), then gathers m_i -> v (K+1..2K): the
+    instance anchored at gather j (j >= k) holds its sender leg (scatter j),
+    and scatter i and gather i of every i < j, so scatter i and gather i
+    both belong to the instances j >= max(i, k)."""
+    s, d, t, nv = _motif_graph(*W.motif_scatter_gather(K))
+    for k in (1, 2, 3, 4):
+        o = mine(s, d, t, nv, 86400, 4, k, oracle.SG | oracle.GS | oracle.PART)
+        i = np.arange(1, K + 1)
+        exp = np.maximum(K - np.maximum(i, k) + 1, 0)
+        np.testing.assert_array_equal(o[2, :K], exp)
+        np.testing.assert_array_equal(o[2, K:], exp)
+        # gather-scatter at k = 1: one sender, its leg and the anchor
+        np.testing.assert_array_equal(o[3], np.full(2 * K, 1 if k == 1 else 0))
+
+
+@pytest.mark.parametrize("k_in,k_out", [(2, 2), (3, 5), (6, 2), (8, 8)])
+def test_participation_gather_scatter_closed_form(k_in, k_out):
+    """Sources -> hub (times 1..k_in), hub -> sinks o_j: the anchor o_j
+    (j >= k, k_in >= k) has k_in instances, each holding one source's leg
+    and all of o_1..o_j."""
+    s, d, t, nv = _motif_graph(*W.motif_gather_scatter(k_in, k_out))
+    for k in (1, 2, 3, 6):
+        o = mine(s, d, t, nv, 86400, 4, k, oracle.SG | oracle.GS | oracle.PART)
+        j = np.arange(1, k_out + 1)
+        on = k_in >= k
+        np.testing.assert_array_equal(o[3, :k_in], np.full(k_in, max(k_out - k + 1, 0) * on))
+        np.testing.assert_array_equal(o[3, k_in:], k_in * np.maximum(k_out - np.maximum(j, k) + 1, 0) * on)
+        # scatter-gather at k = 1: each source is a sender of every o_j
+        np.testing.assert_array_equal(o[2, :k_in], np.full(k_in, k_out if k == 1 else 0))
+        np.testing.assert_array_equal(o[2, k_in:], np.full(k_out, k_in if k == 1 else 0))
+
+
 # ---------------------------------------------------------------- invariants
 
 @pytest.fixture(scope="module")
@@ -411,7 +498,18 @@ def test_parameter_errors():
     with pytest.raises(ValueError):
         mine(s, d, t, 2, 10, 4, 2, patterns=oracle.FAN_OUT | oracle.SG_UNORDERED)  # modifier without SG
     with pytest.raises(ValueError):
-        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | 1024)                     # unknown bit
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | 4096)                     # unknown bit
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.FAN_OUT | oracle.CYC | oracle.PART)  # no SG or GS
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.SG | oracle.SG_PHASE | oracle.PART)
+    assert mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | oracle.PART).shape == (9, 2)
+    assert mine(s, d, t, 2, 10, 4, 2, patterns=oracle.GS | oracle.PART).shape == (2, 2)
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.GS | oracle.SG_SIZES)           # sizes without SG
+    with pytest.raises(ValueError):
+        mine(s, d, t, 2, 10, 4, 2, patterns=oracle.SG | oracle.SG_PHASE | oracle.SG_SIZES)
+    assert mine(s, d, t, 2, 10, 4, 2, patterns=oracle.ALL | oracle.PART | oracle.SG_SIZES).shape == (13, 2)
     with pytest.raises(ValueError):
         mine(s, d, t, 2, 10, 4, 2, patterns=oracle.FAN_OUT | oracle.SG_PHASE)      # modifier without SG
     with pytest.raises(ValueError):
@@ -436,7 +534,9 @@ def test_anchor_ranges_add_up(mid_small):
     np.testing.assert_array_equal(acc, full)
 
 
-@pytest.mark.parametrize("pats,ceiling", [(oracle.ALL, 0), (oracle.SG | oracle.CYC, 0), (oracle.ALL, 3)])
+@pytest.mark.parametrize("pats,ceiling", [(oracle.ALL, 0), (oracle.SG | oracle.CYC, 0), (oracle.ALL, 3),
+                                          (oracle.ALL | oracle.DEG_IN | oracle.PART, 0),
+                                          (oracle.SG | oracle.GS | oracle.PART, 2)])
 def test_parallel_driver_equals_one_process(mid_small, pats, ceiling):
     """The multi-process driver (disjoint anchor ranges, cycle credits summed
     then saturated) gives the single-process result, uneven ranges included."""
