@@ -242,6 +242,7 @@ def bench_variants(A, g, reps=3):
     mods = (("default", A.AMLM_ALL, 6, 2), ("sg_unordered", A.AMLM_ALL | A.AMLM_SG_UNORDERED, 6, 2),
             ("sg_phase", A.AMLM_ALL | A.AMLM_SG_PHASE, 6, 2),
             ("deg_columns", A.AMLM_ALL | A.AMLM_DEG_OUT | A.AMLM_DEG_IN, 6, 2),
+            ("participation", A.AMLM_ALL | A.AMLM_PART, 6, 2),
             ("cycles_L4", A.AMLM_CYCLES, 4, 2), ("cycles_any_order_L4", A.AMLM_CYCLES | A.AMLM_CYC_ANY_ORDER, 4, 2))
     for name, pat, L, k in mods:
         p = A.params(pat, 86400, L, k)

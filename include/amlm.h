@@ -42,7 +42,7 @@
  *
  * Output layout: counts[col * n_edges + i] for edge i, with one column per
  * requested pattern in the order FAN_OUT, FAN_IN, SG, GS, CYC_2 .. CYC_L,
- * DEG_OUT, DEG_IN.
+ * DEG_OUT, DEG_IN, SG_PART, GS_PART, then the four SG size bins.
  *
  * Threading: a handle may be used by one host thread at a time.  Errors are
  * reported by the returned status; amlm_last_error() gives a thread-local
@@ -102,6 +102,33 @@ typedef enum {
  * delta, counted once from the edge of greatest (timestamp, edge id) and
  * credited to each of its edges. */
 #define AMLM_CYC_ANY_ORDER 512u
+/* participation columns (Section 8, Table 2: a transaction's feature is the
+ * number of pattern instances it belongs to; Section 5's streaming
+ * integration: a new edge increments every instance it takes part in).
+ * A scatter-gather instance is a pair (anchor e, sender s) that SG_k(e)
+ * counts, a gather-scatter instance a pair (e, s in S(e)) when GS_k(e) > 0.
+ * An edge belongs to an instance when it is an edge of some realisation
+ * of it (one edge per leg, order and window conditions met):
+ *   SG_PART  the anchor; every s -> u in [t - delta, t); for each m in
+ *            M_e(s) other than u, every s -> m in [t - delta, t) earlier
+ *            than m's latest m -> v in [t - delta, t], and every such
+ *            m -> v later than m's first s -> m (any of them with
+ *            AMLM_SG_UNORDERED);
+ *   GS_PART  s's edges into u in [t - delta, t), and u's out-edges at
+ *            times in (tau, t] (the anchor among them), which belong to
+ *            all |S(e)| instances of e.
+ * One column for each of AMLM_SG and AMLM_GS that is requested, after the
+ * DEG columns.  Requires AMLM_SG or AMLM_GS; excludes AMLM_SG_PHASE.  An
+ * anchor credits edges older than itself: with an anchor range (the
+ * server), those credits come back as deltas.  Not available on batched
+ * stores. */
+#define AMLM_PART 1024u
+/* size bins of AMLM_SG (Section 5's streaming passage counts scatter-gathers
+ * of different sizes): four columns, after every other column, with the
+ * number of s in S(e) whose |M_e(s)| is exactly k, k + 1, k + 2 and at
+ * least k + 3 (they sum to SG_k(e)).  Requires AMLM_SG; excludes
+ * AMLM_SG_PHASE.  Not available on batched stores. */
+#define AMLM_SG_SIZES 2048u
 
 /* schedules for the scatter-gather and cycle work (never change a count) */
 #define AMLM_SCHED_STATIC 0u  /* anchors in time order, fixed-size blocks of

@@ -21,6 +21,8 @@ AMLM_SG_UNORDERED = 32  # modifier of AMLM_SG: an intermediate's two legs in eit
 AMLM_DEG_OUT, AMLM_DEG_IN = 64, 128  # distinct counterparties (columns after the cycle columns)
 AMLM_SG_PHASE = 256       # modifier of AMLM_SG: every scatter leg before every gather leg
 AMLM_CYC_ANY_ORDER = 512  # modifier of AMLM_CYCLES: a cycle's edges in any order within delta
+AMLM_PART = 1024          # participation columns: the SG / GS instances each edge belongs to
+AMLM_SG_SIZES = 2048      # four SG size bins: exactly k, k+1, k+2, at least k+3 intermediates (last columns)
 AMLM_SCHED_STATIC, AMLM_SCHED_LEARNED, AMLM_SCHED_LENGTH, AMLM_SCHED_GIVEN = 0, 1, 2, 3
 STATUS = {0: "AMLM_OK", 1: "AMLM_E_INVALID", 2: "AMLM_E_RANGE", 3: "AMLM_E_NOMEM",
           4: "AMLM_E_DEVICE", 5: "AMLM_E_ORDER", 6: "AMLM_E_BUSY"}

@@ -328,8 +328,17 @@ amlm_status check_params(const amlm_params *p) {
     return AMLM_E_INVALID;
   }
   const uint32_t cols = AMLM_ALL | AMLM_DEG_OUT | AMLM_DEG_IN;
-  if ((p->patterns & cols) == 0 || (p->patterns & ~(cols | AMLM_SG_UNORDERED | AMLM_SG_PHASE | AMLM_CYC_ANY_ORDER))) {
-    set_error("patterns must be a non-empty set of pattern bits (plus AMLM_SG_UNORDERED)");
+  if ((p->patterns & cols) == 0 ||
+      (p->patterns & ~(cols | AMLM_SG_UNORDERED | AMLM_SG_PHASE | AMLM_CYC_ANY_ORDER | AMLM_PART | AMLM_SG_SIZES))) {
+    set_error("patterns must be a non-empty set of pattern bits (plus the modifiers)");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_PART) && (!(p->patterns & (AMLM_SG | AMLM_GS)) || (p->patterns & AMLM_SG_PHASE))) {
+    set_error("AMLM_PART needs AMLM_SG or AMLM_GS and excludes AMLM_SG_PHASE");
+    return AMLM_E_INVALID;
+  }
+  if ((p->patterns & AMLM_SG_SIZES) && (!(p->patterns & AMLM_SG) || (p->patterns & AMLM_SG_PHASE))) {
+    set_error("AMLM_SG_SIZES modifies AMLM_SG and excludes AMLM_SG_PHASE");
     return AMLM_E_INVALID;
   }
   if ((p->patterns & AMLM_SG_UNORDERED) && !(p->patterns & AMLM_SG)) {
@@ -377,6 +386,9 @@ extern "C" uint32_t amlm_num_columns(const amlm_params *p) {
   if (p->patterns & AMLM_CYCLES) c += p->max_cycle_len - 1;
   if (p->patterns & AMLM_DEG_OUT) c++;
   if (p->patterns & AMLM_DEG_IN) c++;
+  if ((p->patterns & AMLM_PART) && (p->patterns & AMLM_SG)) c++;
+  if ((p->patterns & AMLM_PART) && (p->patterns & AMLM_GS)) c++;
+  if (p->patterns & AMLM_SG_SIZES) c += 4;
   return c;
 }
 
@@ -487,6 +499,7 @@ static amlm_status mine_impl(amlm_graph *g, const amlm_params *p, uint32_t *coun
     cfg.ev_join = g->ev_join;
   }
   HIP_TRY(mine_launch(mp, g->ms, cfg, s, &g->timer));
+  HIP_TRY(part_launch(mp, p, g->ms, s));
   return AMLM_OK;
 }
 
@@ -515,6 +528,7 @@ amlm_status mine_with_scratch(amlm_graph *g, const amlm_params *p, uint32_t *cou
     MineLaunch cfg = default_launch(g);
     A_TRY(schedule_config(g, p, cfg));
     HIP_TRY(mine_launch(mp, ms, cfg, s, nullptr));
+    HIP_TRY(part_launch(mp, p, ms, s));
     return AMLM_OK;
   };
   return sticky_note(g, run());

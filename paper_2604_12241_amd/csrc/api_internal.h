@@ -85,6 +85,12 @@ amlm_status mine_with_scratch(amlm_graph *g, const amlm_params *p, uint32_t *cou
 // Mining with the edges of id >= anchor_lo as the only anchors (0 = all).
 amlm_status mine_common(amlm_graph *g, const amlm_params *p, uint32_t *counts_dev, unsigned long long *work_dev,
                         hipStream_t s, uint32_t anchor_lo = 0);
+// Instance columns (AMLM_PART, AMLM_SG_SIZES; part.hip): their column
+// indices in p's layout (-1 when absent; c_sz is the first of four), and the
+// pass that fills them for the anchors of mp's range (after mine_launch on
+// the same stream; the columns must start at zero).
+void part_columns(const amlm_params *p, int *c_ps, int *c_pg, int *c_sz);
+hipError_t part_launch(const MineParams &mp, const amlm_params *p, MineScratch &ms, hipStream_t s);
 // Sticky device errors: returns g's sticky status if set; otherwise, if a
 // fault was injected for this call, records it and returns AMLM_E_DEVICE.
 amlm_status sticky_check(amlm_graph *g);

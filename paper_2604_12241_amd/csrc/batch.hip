@@ -223,6 +223,10 @@ static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_
   std::vector<uint32_t> ncols(B.n);
   for (uint32_t i = 0; i < B.n; i++) {
     A_TRY(check_params(&ps[i]));
+    if (ps[i].patterns & (AMLM_PART | AMLM_SG_SIZES)) {
+      set_error("AMLM_PART and AMLM_SG_SIZES are not available on batched stores");
+      return AMLM_E_INVALID;
+    }
     if (ps[i].patterns != ps[0].patterns || ps[i].schedule != ps[0].schedule) {
       set_error("every graph of a batch must use the same patterns and schedule");
       return AMLM_E_INVALID;

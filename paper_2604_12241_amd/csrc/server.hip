@@ -59,7 +59,8 @@ __global__ void k_first_at_or_after(GraphView g, int32_t thr, uint32_t *out) {
   *out = b;
 }
 
-// nonzero cycle credits of context edges [0, n_ctx) -> (global id, column, value)
+// nonzero credits of context edges [0, n_ctx) in columns [col_cyc, col_cyc +
+// ncyc) (cycles, participation) -> (global id, column, value)
 __global__ void k_collect_deltas(const uint32_t *counts, uint64_t stride, uint32_t col_cyc, uint32_t ncyc,
                                  uint32_t n_ctx, const uint32_t *geid, uint32_t *cnt, uint32_t cap, uint32_t *o_eid,
                                  uint32_t *o_col, uint32_t *o_val) {
@@ -358,7 +359,7 @@ static void run_job(amlm_server *S, ServerSlot &sl, ServerJob *job) {
       return fail(AMLM_E_DEVICE);
     }
   }
-  // cycle credits to older edges (store positions [0, lo))
+  // cycle and participation credits to older edges (store positions [0, lo))
   uint32_t nd = 0;
   if (S->ncyc && lo) {
     uint64_t cap = std::max<uint64_t>(1u << 16, lo / 4);
@@ -471,8 +472,12 @@ static amlm_status server_init(const amlm_params *p, uint64_t hbm_budget_bytes, 
   if (p->patterns & AMLM_FAN_IN) c++;
   if (p->patterns & AMLM_SG) c++;
   if (p->patterns & AMLM_GS) c++;
+  // columns that credit older edges: the cycles and the participation
+  // columns (every column from the first cycle column on is collected; the
+  // distinct-counterparty and size columns among them are the anchors' own,
+  // zero there)
   S->col_cyc = c;
-  S->ncyc = (p->patterns & AMLM_CYCLES) ? p->max_cycle_len - 1 : 0;
+  S->ncyc = (p->patterns & (AMLM_CYCLES | AMLM_PART)) ? S->ncols - c : 0;
   max_slots = std::max(1u, std::min(max_slots, 16u));
   S->max_queue = 64 * max_slots;
   S->slots.resize(max_slots);

@@ -37,11 +37,21 @@ def test_library_loads_and_reports_columns():
     # the distinct-counterparty columns come after the cycle columns
     assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | A.AMLM_DEG_OUT | A.AMLM_DEG_IN, L=4)) == 9
     assert A.amlm_num_columns(A.params(patterns=A.AMLM_DEG_IN, L=4)) == 1
+    # participation columns: one per requested SG / GS, last; need SG or GS, not the phase order
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | A.AMLM_DEG_IN | A.AMLM_PART, L=4)) == 10
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_GS | A.AMLM_PART, L=4)) == 2
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_FAN_IN | A.AMLM_CYCLES | A.AMLM_PART, L=4)) == 0
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_SG | A.AMLM_SG_PHASE | A.AMLM_PART, L=4)) == 0
+    # four size bins of SG, last; need SG, not the phase order
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | A.AMLM_PART | A.AMLM_SG_SIZES, L=4)) == 13
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_GS | A.AMLM_SG_SIZES, L=4)) == 0
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_SG | A.AMLM_SG_PHASE | A.AMLM_SG_SIZES, L=4)) == 0
     assert A.amlm_num_columns(A.params(L=9)) == 0          # invalid L
     assert A.amlm_num_columns(A.params(k=0)) == 0          # invalid k
     assert A.amlm_num_columns(A.params(delta=-1)) == 0     # invalid window
     assert A.amlm_num_columns(A.params(patterns=1 << 12)) == 0  # unknown pattern bit
     assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | (1 << 12), L=4)) == 0
+    assert A.amlm_num_columns(A.params(patterns=A.AMLM_ALL | (1 << 13), L=4)) == 0
     assert A.amlm_num_columns(A.params(schedule=4)) == 0   # unknown schedule
 
 

@@ -1,0 +1,153 @@
+"""GPU parity of the instance columns against the oracle: participation
+(AMLM_PART: for every edge, the scatter-gather and gather-scatter instances
+it belongs to) and the scatter-gather size bins (AMLM_SG_SIZES).  Random
+small graphs with ties and self-loops, a 100k-edge graph with hubs, ordered
+and unordered legs, k from 1 to 4, the saturation ceiling, the
+allocation-free entry point, a sliced schedule, and the streaming server,
+whose new anchors credit older edges through deltas."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_12241_amd as A
+from paper_2604_12241_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PART = (A.AMLM_PART, oracle.PART)
+SIZES = (A.AMLM_SG_SIZES, oracle.SG_SIZES)
+
+
+def _mine(g, pat, delta, L, k, sched=A.AMLM_SCHED_STATIC, ceiling=0):
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    if ceiling:
+        A.amlm_graph_set_ceiling(G, ceiling)
+    c = A.to_u32(A.amlm_mine(G, A.params(pat, delta, L, k, sched)))
+    A.amlm_graph_sync(G)
+    G.close()
+    return c
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_participation_random_small(seed):
+    rng = np.random.default_rng(9100 + seed)
+    g = W.random_small(seed + 910, n_edges=int(rng.integers(1, 500)), n_vertices=int(rng.integers(2, 20)),
+                       t_range=int(rng.integers(1, 60)))
+    delta, L, k = int(rng.integers(0, 50)), int(rng.integers(2, 7)), int(rng.integers(1, 5))
+    print(f"seed {seed}: {g.n_edges} edges, delta {delta}, L {L}, k {k}", flush=True)
+    for pat, opat in ((A.AMLM_ALL | PART[0], oracle.ALL | PART[1]),
+                      (A.AMLM_ALL | A.AMLM_SG_UNORDERED | PART[0], oracle.ALL | oracle.SG_UNORDERED | PART[1]),
+                      (A.AMLM_SG | PART[0], oracle.SG | PART[1]),
+                      (A.AMLM_GS | A.AMLM_DEG_IN | PART[0], oracle.GS | oracle.DEG_IN | PART[1]),
+                      (A.AMLM_SG | SIZES[0], oracle.SG | SIZES[1]),
+                      (A.AMLM_ALL | A.AMLM_SG_UNORDERED | PART[0] | SIZES[0],
+                       oracle.ALL | oracle.SG_UNORDERED | PART[1] | SIZES[1])):
+        c = _mine(g, pat, delta, L, k)
+        ref = oracle.mine(g.src, g.dst, g.ts, g.n_vertices, opat, delta, L, k)
+        np.testing.assert_array_equal(c, ref, err_msg=f"pattern {pat}")
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_participation_mid_with_hubs(k):
+    """100k edges with hub accounts: many senders per anchor, long
+    out-windows (several 64-entry wave steps per sender) and parallel
+    edges; the columns before the participation columns are unchanged."""
+    g = W.mid(215, scale=0.02)
+    for pat, opat in ((A.AMLM_ALL | PART[0], oracle.ALL | PART[1]),
+                      (A.AMLM_ALL | A.AMLM_SG_UNORDERED | PART[0], oracle.ALL | oracle.SG_UNORDERED | PART[1])):
+        c = _mine(g, pat, 86400, 5, k)
+        ref = oracle.mine(g.src, g.dst, g.ts, g.n_vertices, opat, 86400, 5, k)
+        np.testing.assert_array_equal(c, ref, err_msg=f"pattern {pat}")
+        assert ref[-2].sum() > 0 and ref[-1].sum() > 0
+        np.testing.assert_array_equal(c[:-2], _mine(g, pat & ~A.AMLM_PART, 86400, 5, k))
+    c = _mine(g, A.AMLM_ALL | SIZES[0], 86400, 5, k)
+    ref = oracle.mine(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL | SIZES[1], 86400, 5, k)
+    np.testing.assert_array_equal(c, ref)
+    np.testing.assert_array_equal(c[-4:].sum(axis=0), c[2])
+
+
+@pytest.mark.parametrize("ceiling", [1, 3, 40])
+def test_participation_saturates(ceiling):
+    g = W.mid(216, scale=0.004)
+    c = _mine(g, A.AMLM_ALL | PART[0] | SIZES[0], 86400, 4, 1, ceiling=ceiling)
+    ref, _, _ = oracle.mine_ex(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL | PART[1] | SIZES[1], 86400, 4, 1,
+                               ceiling=ceiling)
+    np.testing.assert_array_equal(c, ref)
+    assert (ref[-5] == ceiling).any()
+
+
+def test_participation_static_entry_and_sliced_schedule():
+    """amlm_mine_static (scratch in the library's device array) and a sliced
+    schedule (given per-edge costs, small slices) give the same columns."""
+    g = W.mid(217, scale=0.01)
+    p = A.params(A.AMLM_ALL | PART[0], 86400, 5, 2)
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    a = A.to_u32(A.amlm_mine(G, p))
+    b = A.to_u32(A.amlm_mine_static(G, p))
+    np.testing.assert_array_equal(a, b)
+    ref = oracle.mine(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL | PART[1], 86400, 5, 2)
+    np.testing.assert_array_equal(a, ref)
+    cost = torch.full((g.n_edges,), 12.0, dtype=torch.float32, device="cuda")
+    A.amlm_graph_set_costs(G, cost)
+    A.amlm_tune_set(G, split_bytes=512)
+    c = A.to_u32(A.amlm_mine(G, A.params(A.AMLM_ALL | PART[0], 86400, 5, 2, A.AMLM_SCHED_GIVEN)))
+    A.amlm_graph_sync(G)
+    np.testing.assert_array_equal(c, ref)
+    A.amlm_graph_set_costs(G, None)
+    G.close()
+
+
+def test_participation_errors():
+    g = W.random_small(3, n_edges=50, n_vertices=6, t_range=20)
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    for pat in (A.AMLM_FAN_OUT | A.AMLM_CYCLES | A.AMLM_PART, A.AMLM_SG | A.AMLM_SG_PHASE | A.AMLM_PART,
+                A.AMLM_GS | A.AMLM_SG_SIZES):
+        assert A.amlm_num_columns(A.params(pat, 10, 4, 2)) == 0
+        with pytest.raises(A.AmlmError) as ei:
+            A.amlm_mine(G, A.params(pat, 10, 4, 2), torch.zeros((1, g.n_edges), dtype=torch.int32, device="cuda"))
+        assert ei.value.status == 1
+    G.close()
+    B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices)])
+    with pytest.raises(A.AmlmError) as ei:
+        A.amlm_mine_batch(B, [A.params(A.AMLM_ALL | A.AMLM_PART, 10, 4, 2)])
+    assert ei.value.status == 1
+    B.close()
+
+
+def test_participation_through_the_server():
+    """Each batch's anchors credit the edges of their instances, older ones
+    included (deltas): resident counts + new rows + deltas equal the oracle
+    on the union graph."""
+    D, L, K = 86400, 4, 2
+    base = W.mid(321, scale=0.004)
+    batches = W.stream_batches(base, seed=78, n_batches=10, b_min=50, b_max=2500, rate_per_s=0.02,
+                               zipf_a=2.1, max_degree=50)
+    pats = A.AMLM_ALL | A.AMLM_DEG_IN | A.AMLM_PART | A.AMLM_SG_SIZES
+    p = A.params(pats, D, L, K)
+    R = A.Graph(base.src, base.dst, base.ts, base.n_vertices)
+    r_counts = A.to_u32(A.amlm_mine(R, p)).astype(np.uint64)
+    S = A.Server(R, p, max_slots=4)
+    tickets = [S.submit(b.src, b.dst, b.ts) for b in batches]
+    res = [S.wait(t) for t in tickets]
+    S.close()
+    src = np.concatenate([base.src] + [b.src for b in batches])
+    dst = np.concatenate([base.dst] + [b.dst for b in batches])
+    ts = np.concatenate([base.ts] + [b.ts for b in batches])
+    acc = np.zeros((r_counts.shape[0], src.shape[0]), np.uint64)
+    acc[:, :base.n_edges] = r_counts
+    pos = base.n_edges
+    ncol = r_counts.shape[0]
+    part_deltas = 0
+    for (c, (de, dc, dv), _), b in zip(res, batches):
+        acc[:, pos:pos + b.n_edges] += c
+        np.add.at(acc, (dc.astype(np.int64), de.astype(np.int64)), dv)
+        assert (de < pos).all()
+        part_deltas += int(((dc >= ncol - 6) & (dc < ncol - 4)).sum())
+        assert (dc < ncol - 4).all()     # the size bins are the anchor's own
+        pos += b.n_edges
+    full = oracle.mine(src, dst, ts, base.n_vertices, oracle.ALL | oracle.DEG_IN | oracle.PART | oracle.SG_SIZES,
+                       D, L, K)
+    np.testing.assert_array_equal(acc, full.astype(np.uint64))
+    assert part_deltas > 0
+    R.close()
