@@ -112,7 +112,7 @@ def _stream_source(g, n_pool, seed=505):
         rep += 1
 
 
-def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300, inflight=64):
+def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300, inflight=64, loads=(0.5, 0.8)):
     """Config-5 style serving: the graph resident, stream batches of 1k-100k
     edges (log-uniform) strictly after its end.  A saturation run (every
     batch queued as fast as the server takes it) gives the sustained rate;
@@ -147,7 +147,7 @@ def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300, inf
     res = {"sustained_edges_per_s": sustained, "saturation_batches": n_sat, "slots": slots,
            "batches_per_load": n_batches, "latency_excludes_first": skip,
            "batch_edges": "log-uniform 1e3..1e5"}
-    for frac in (0.5, 0.8):
+    for frac in loads:
         rate = frac * sustained / mean_edges          # batches per second
         gaps = rng.exponential(1.0 / rate, n_batches)
         tk = []
@@ -320,6 +320,9 @@ def main():
     ap.add_argument("--model-cache", default=None, help="load / save the trained cost model here")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: no comparisons, plus a 1 GiB copy of known size")
+    ap.add_argument("--profile-serve", type=int, default=0, metavar="N",
+                    help="with --profile: then a serving saturation run of N batches (its dispatches "
+                         "follow the copy kernel in a trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -482,6 +485,9 @@ def main():
     if not args.no_serve:
         out["stream"] = bench_serving(A, G, g, p, slots=args.serve_slots, inflight=args.serve_inflight)
         out["p99_stream_latency_ms"] = out["stream"]["load_80"]["p99_ms"]
+    elif args.profile and args.profile_serve > 0:
+        out["stream"] = bench_serving(A, G, g, p, n_batches=2 * args.profile_serve, slots=args.serve_slots,
+                                      inflight=args.serve_inflight, loads=())
     if not args.no_batch:
         out["batching"] = bench_batching(A)
     if gh is not None and not args.no_variants:

@@ -2,7 +2,8 @@
 processes over disjoint anchor ranges or independent graphs):
 
 * the 5M-edge graph (500k accounts, 16 days, delta 24 h, L 6, k 2), every
-  column of every edge, static and learned schedules;
+  column of every edge, static and learned schedules, and with the
+  participation and size columns;
 * the 256 independent sub-graphs of 1k-200k edges (9.8M edges, windows of
   6 / 24 / 72 h) through one captured batched launch, every sub-graph;
 * serving over the 32M-edge resident graph: every 10th of 60 stream batches
@@ -38,6 +39,21 @@ def test_mid_5M_full_graph_both_schedules():
     bad = int((c != ref).sum())
     assert bad == 0, f"{bad} mismatching counts (learned)"
     G.close()
+
+
+def test_mid_5M_full_graph_instance_columns():
+    """Participation (SG_PART, GS_PART) and the SG size bins beside every
+    other column on the 5M-edge graph: all 15 columns of every edge."""
+    g = W.mid(206)
+    pats = oracle.ALL | oracle.PART | oracle.SG_SIZES
+    ref, _ = mine_parallel(g.src, g.dst, g.ts, g.n_vertices, pats, 86400, 6, 2)
+    assert ref[-6:].sum() > 0
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    c = A.to_u32(A.amlm_mine(G, A.params(A.AMLM_ALL | A.AMLM_PART | A.AMLM_SG_SIZES, 86400, 6, 2)))
+    A.amlm_graph_sync(G)
+    G.close()
+    bad = int((c != ref).sum())
+    assert bad == 0, f"{bad} mismatching counts"
 
 
 def test_all_256_subgraphs_in_one_captured_launch():
