@@ -7,9 +7,10 @@
 // bound vertices (differentiate, difference with a singleton), keep each
 // neighbour once (a stage's output is a vertex set), and folds what its
 // inner cells return: a sum, or how many of its bindings reach a threshold
-// (Section 4's threshold on how many take part).  One lane interprets the program for one
-// anchor with an explicit stack of cell states, so a new pattern needs no
-// new kernel.
+// (Section 4's threshold on how many take part); a loop whose parent only
+// asks whether it reaches a threshold stops once it does.  One lane
+// interprets the program for one anchor with an explicit stack of cell
+// states, so a new pattern needs no new kernel.
 #include "api_internal.h"
 
 #define A_TRY(x)                    \
@@ -118,6 +119,16 @@ __global__ __launch_bounds__(256) void k_interp(GraphView g, Prog P, int64_t del
     if (c.agg == kAggSum) F[i].acc = sat_add(F[i].acc, val, ceil);
     else F[i].acc = sat_add(F[i].acc, val >= thr ? 1u : 0u, ceil);
   };
+  // Early exit (Algorithm 1's break): every fold only grows, so once cell
+  // d's value reaches the threshold its parent compares it with, more
+  // bindings cannot change what the parent counts
+  auto enough = [&](int d) -> bool {
+    if (d == 0) return false;
+    const CellDev &pc = P.c[d - 1];
+    if (pc.agg == kAggSum) return false;
+    const uint32_t thr = pc.agg == kAggAtLeastK ? k : pc.thr;
+    return F[d].acc >= thr;
+  };
   uint32_t result;
   if (P.c[0].op == kOpProbe) {
     result = probe(P.c[0]);
@@ -136,6 +147,10 @@ __global__ __launch_bounds__(256) void k_interp(GraphView g, Prog P, int64_t del
       d--;
       fold(d, val);
       F[d].pos++;
+      continue;
+    }
+    if (enough(d)) {
+      f.pos = f.end;
       continue;
     }
     const uint32_t p = f.pos;
