@@ -120,14 +120,13 @@ typedef enum {
  * One column for each of AMLM_SG and AMLM_GS that is requested, after the
  * DEG columns.  Requires AMLM_SG or AMLM_GS; excludes AMLM_SG_PHASE.  An
  * anchor credits edges older than itself: with an anchor range (the
- * server), those credits come back as deltas.  Not available on batched
- * stores. */
+ * server), those credits come back as deltas. */
 #define AMLM_PART 1024u
 /* size bins of AMLM_SG (Section 5's streaming passage counts scatter-gathers
  * of different sizes): four columns, after every other column, with the
  * number of s in S(e) whose |M_e(s)| is exactly k, k + 1, k + 2 and at
  * least k + 3 (they sum to SG_k(e)).  Requires AMLM_SG; excludes
- * AMLM_SG_PHASE.  Not available on batched stores. */
+ * AMLM_SG_PHASE. */
 #define AMLM_SG_SIZES 2048u
 
 /* schedules for the scatter-gather and cycle work (never change a count) */
@@ -446,7 +445,7 @@ amlm_status amlm_costmodel_get(float *weights, float *mean, float *inv_std);
  * *loss (may be NULL) receives the mean squared error. */
 amlm_status amlm_mlp_forward(const float *weights, const float *x, uint32_t n, float *y);
 /* The scheduler's inference path: the same network on the matrix cores
- * (16x16x16 BF16 MFMA tiles of 16 anchors), BF16 inputs and activations,
+ * (16x16x32 BF16 MFMA tiles of 16 anchors), BF16 inputs and activations,
  * FP32 accumulation. */
 amlm_status amlm_mlp_predict(const float *weights, const float *x, uint32_t n, float *y);
 amlm_status amlm_mlp_grad(const float *weights, const float *x, const float *y, uint32_t n, float *grad,

@@ -74,6 +74,9 @@ uint32_t ncols_of(uint32_t patterns, uint32_t L) {
   if (patterns & AMLM_CYCLES) c += L - 1;
   if (patterns & AMLM_DEG_OUT) c++;
   if (patterns & AMLM_DEG_IN) c++;
+  if ((patterns & AMLM_PART) && (patterns & AMLM_SG)) c++;
+  if ((patterns & AMLM_PART) && (patterns & AMLM_GS)) c++;
+  if (patterns & AMLM_SG_SIZES) c += 4;
   return c;
 }
 
@@ -223,10 +226,6 @@ static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_
   std::vector<uint32_t> ncols(B.n);
   for (uint32_t i = 0; i < B.n; i++) {
     A_TRY(check_params(&ps[i]));
-    if (ps[i].patterns & (AMLM_PART | AMLM_SG_SIZES)) {
-      set_error("AMLM_PART and AMLM_SG_SIZES are not available on batched stores");
-      return AMLM_E_INVALID;
-    }
     if (ps[i].patterns != ps[0].patterns || ps[i].schedule != ps[0].schedule) {
       set_error("every graph of a batch must use the same patterns and schedule");
       return AMLM_E_INVALID;
@@ -273,6 +272,7 @@ static amlm_status mine_batch_impl(amlm_graph *g, const amlm_params *ps, uint32_
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_fill_u32(B.comb, 0, (uint64_t)nc_max * g->E, cs);
     if (e == hipSuccess) e = mine_launch(mp, g->ms, cfg, cs, nullptr);
+    if (e == hipSuccess) e = part_launch(mp, &pm, g->ms, cs);  // participation and size columns, if asked
     if (e == hipSuccess && g->E) {
       const uint32_t ncyc_max = (pm.patterns & AMLM_CYCLES) ? Lmax - 1 : 0;
       const uint32_t cyc0 = mp.col_cyc >= 0 ? (uint32_t)mp.col_cyc : nc_max;

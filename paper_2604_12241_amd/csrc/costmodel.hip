@@ -71,22 +71,31 @@ __device__ __forceinline__ float mlp_forward(const float *W, const float *x, flo
   return y;
 }
 
-// ---- MFMA inference: 16 anchors per v_mfma_f32_16x16x16_bf16 tile ----
-// Operand layout of the 16x16x16 BF16 MFMA (64 lanes, l = lane):
-//   A (16 x 16, M x K): lane l holds row l % 16, k = 4 (l / 16) + 0..3
-//   B (16 x 16, K x N): lane l holds col l % 16, k = 4 (l / 16) + 0..3
+// ---- MFMA inference: 16 anchors per v_mfma_f32_16x16x32_bf16 tile ----
+// Operand layout of gfx950's 16x16x32 BF16 MFMA (64 lanes, l = lane):
+//   A (16 x 32, M x K): lane l holds row l % 16, k = 8 (l / 16) + 0..7
+//   B (32 x 16, K x N): lane l holds col l % 16, k = 8 (l / 16) + 0..7
 //   C (16 x 16):        lane l holds col l % 16, rows 4 (l / 16) + 0..3
-// The three layers are dense products [16 x K] x [K x 64] (K = 16 with the
-// 12 inputs zero-padded, then 64, then 64 x 16 with w3 in column 0); every
-// weight operand stays in registers, and the activations go through a
-// 16 x 64 BF16 tile in LDS to move from the C layout to the A layout.
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+// The three layers are dense products [16 x K] x [K x 64] (K = 32 with the
+// 12 inputs zero-padded, then 64 as two K-steps, then 64 x 16 with w3 in
+// column 0); every weight operand stays in registers, and the activations
+// go through a 16 x 64 BF16 tile in LDS to move from the C layout to the A
+// layout.
+typedef short shortx8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short bf16_bits(float f) { return (short)d_f32_to_bf16(f); }
 
+__device__ __forceinline__ floatx4_t mfma_bf16(const shortx8_t &a, const shortx8_t &b, floatx4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+
 constexpr int kTileRows = 16;
 constexpr int kActPad = kMlpH + 8;  // bf16 per LDS row (pad against bank conflicts)
+constexpr int kKStep = 32;          // K of one MFMA
+constexpr int kKSteps = kMlpH / kKStep;
 
 template <bool kFromRaw>
 __global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const float *norm, const uint32_t *feat,
@@ -96,29 +105,29 @@ __global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const flo
                                                   const SubParams *sub) {
   __shared__ short act[256 / AMLM_WAVE][kTileRows][kActPad];
   const uint32_t lane = lane_id(), w = threadIdx.x / AMLM_WAVE;
-  const uint32_t col = lane % 16, kq = (lane / 16) * 4;
+  const uint32_t col = lane % 16, kq = (lane / 16) * 8, rq = (lane / 16) * 4;
   // weights as B operands, in registers
-  bf16x4_t B1[4], B2[4][4], B3[4];
+  shortx8_t B1[4], B2[kKSteps][4], B3[kKSteps];
   float bias1[4], bias2[4];
 #pragma unroll
   for (int nt = 0; nt < 4; nt++) {
     uint32_t n = nt * 16 + col;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < 8; i++) {
       uint32_t k = kq + i;
       B1[nt][i] = k < kMlpF ? (short)w16[kOffW1 + n * kMlpF + k] : (short)0;
     }
     bias1[nt] = dbf16(w16[kOffB1 + n]);
     bias2[nt] = dbf16(w16[kOffB2 + n]);
 #pragma unroll
-    for (int kt = 0; kt < 4; kt++)
+    for (int kt = 0; kt < kKSteps; kt++)
 #pragma unroll
-      for (int i = 0; i < 4; i++) B2[kt][nt][i] = (short)w16[kOffW2 + n * kMlpH + kt * 16 + kq + i];
+      for (int i = 0; i < 8; i++) B2[kt][nt][i] = (short)w16[kOffW2 + n * kMlpH + kt * kKStep + kq + i];
   }
 #pragma unroll
-  for (int kt = 0; kt < 4; kt++)
+  for (int kt = 0; kt < kKSteps; kt++)
 #pragma unroll
-    for (int i = 0; i < 4; i++) B3[kt][i] = col == 0 ? (short)w16[kOffW3 + kt * 16 + kq + i] : (short)0;
+    for (int i = 0; i < 8; i++) B3[kt][i] = col == 0 ? (short)w16[kOffW3 + kt * kKStep + kq + i] : (short)0;
   const float b3 = dbf16(w16[kOffB3]);
   float nrm[2 * kMlpF];
 #pragma unroll
@@ -130,9 +139,9 @@ __global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const flo
     const uint32_t row = lane % 16;
     const uint32_t item = tile * kTileRows + row;
     const bool valid = item < n;
-    // A operand of layer 1: this lane's four inputs of its row
-    float x[4] = {0.f, 0.f, 0.f, 0.f};
-    if (valid) {
+    // A operand of layer 1: this lane's eight inputs of its row (k >= 12: 0)
+    float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (valid && kq < (uint32_t)kMlpF) {
       if (kFromRaw) {
         uint32_t r[kMlpRaw];
         uint64_t rr = idx ? idx[item] : item;
@@ -147,62 +156,62 @@ __global__ __launch_bounds__(256) void k_mlp_mfma(const uint16_t *w16, const flo
         }
         mlp_input(r, dh_i, L_i, nrm, xf);
 #pragma unroll
-        for (int i = 0; i < 4; i++) x[i] = kq + i < kMlpF ? xf[kq + i] : 0.f;
+        for (int i = 0; i < 8; i++) x[i] = kq + i < kMlpF ? xf[kq + i] : 0.f;
       } else {
 #pragma unroll
-        for (int i = 0; i < 4; i++) x[i] = kq + i < kMlpF ? X[(uint64_t)item * kMlpF + kq + i] : 0.f;
+        for (int i = 0; i < 8; i++) x[i] = kq + i < kMlpF ? X[(uint64_t)item * kMlpF + kq + i] : 0.f;
       }
     }
-    bf16x4_t a1;
+    shortx8_t a1;
 #pragma unroll
-    for (int i = 0; i < 4; i++) a1[i] = bf16_bits(x[i]);
+    for (int i = 0; i < 8; i++) a1[i] = bf16_bits(x[i]);
     // layer 1 -> act (bf16, relu)
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) {
       floatx4_t c = {0.f, 0.f, 0.f, 0.f};
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, B1[nt], c, 0, 0, 0);
+      c = mfma_bf16(a1, B1[nt], c);
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         float h = c[i] + bias1[nt];
-        act[w][kq + i][nt * 16 + col] = bf16_bits(h > 0.f ? h : 0.f);
+        act[w][rq + i][nt * 16 + col] = bf16_bits(h > 0.f ? h : 0.f);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     // layer 2
-    bf16x4_t a2[4];
+    shortx8_t a2[kKSteps];
 #pragma unroll
-    for (int kt = 0; kt < 4; kt++)
+    for (int kt = 0; kt < kKSteps; kt++)
 #pragma unroll
-      for (int i = 0; i < 4; i++) a2[kt][i] = act[w][row][kt * 16 + kq + i];
+      for (int i = 0; i < 8; i++) a2[kt][i] = act[w][row][kt * kKStep + kq + i];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int nt = 0; nt < 4; nt++) {
       floatx4_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kt = 0; kt < 4; kt++) c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[kt], B2[kt][nt], c, 0, 0, 0);
+      for (int kt = 0; kt < kKSteps; kt++) c = mfma_bf16(a2[kt], B2[kt][nt], c);
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         float h = c[i] + bias2[nt];
-        act[w][kq + i][nt * 16 + col] = bf16_bits(h > 0.f ? h : 0.f);
+        act[w][rq + i][nt * 16 + col] = bf16_bits(h > 0.f ? h : 0.f);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     // layer 3 (w3 in column 0)
-    bf16x4_t a3[4];
+    shortx8_t a3[kKSteps];
 #pragma unroll
-    for (int kt = 0; kt < 4; kt++)
+    for (int kt = 0; kt < kKSteps; kt++)
 #pragma unroll
-      for (int i = 0; i < 4; i++) a3[kt][i] = act[w][row][kt * 16 + kq + i];
+      for (int i = 0; i < 8; i++) a3[kt][i] = act[w][row][kt * kKStep + kq + i];
     __builtin_amdgcn_wave_barrier();
     floatx4_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kt = 0; kt < 4; kt++) c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3[kt], B3[kt], c, 0, 0, 0);
+    for (int kt = 0; kt < kKSteps; kt++) c = mfma_bf16(a3[kt], B3[kt], c);
     if (col == 0) {
 #pragma unroll
       for (int i = 0; i < 4; i++) {
-        uint32_t it = tile * kTileRows + kq + i;
+        uint32_t it = tile * kTileRows + rq + i;
         if (it < n) pred[it] = c[i] + b3;
       }
     }

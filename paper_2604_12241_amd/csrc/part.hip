@@ -65,6 +65,7 @@ struct PartLds {
   uint32_t a_u[AMLM_WAVE], a_v[AMLM_WAVE], a_p0[AMLM_WAVE], a_pref[AMLM_WAVE];
   uint32_t a_vrs[AMLM_WAVE], a_vre[AMLM_WAVE], a_vq0[AMLM_WAVE], a_vlen[AMLM_WAVE];
   int32_t a_t[AMLM_WAVE], a_lo[AMLM_WAVE];
+  uint32_t a_k[AMLM_WAVE];  // the anchor's threshold (its sub-graph's in a batched store)
   uint32_t a_inst[AMLM_WAVE], a_bin[4][AMLM_WAVE], a_ns[AMLM_WAVE], a_tau[AMLM_WAVE];
   uint32_t s_r0[AMLM_WAVE], s_pref[AMLM_WAVE], s_cnt[AMLM_WAVE], s_a[AMLM_WAVE], s_s[AMLM_WAVE];
 };
@@ -104,13 +105,12 @@ __device__ void credit_sg_instance(const MineParams &mp, const PartLds &L, uint3
 
 // items: every CSC position (ranged = 0), or the edge ids of the anchor
 // range [anchor_lo, anchor_lo + n_items) (ranged = 1, self-loops skipped).
-// One delta and k: not on batched stores.
+// Each anchor takes its (sub-)graph's window and threshold.
 __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint32_t n_items, uint32_t ranged,
                                              uint32_t *claim) {
   const GraphView &g = mp.g;
   __shared__ PartLds L;
   const uint32_t lane = lane_id();
-  const uint32_t k = mp.k;
   const bool unordered = mp.sg_unordered != 0;
   uint32_t *const col_ps = cols.ps >= 0 ? mp.counts + (uint64_t)cols.ps * mp.stride : nullptr;
   uint32_t *const col_pg = cols.pg >= 0 ? mp.counts + (uint64_t)cols.pg * mp.stride : nullptr;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
       act = g.src[e] != g.dst[e];
       q = act ? g.pos_in[e] : 0u;
     }
-    uint32_t eid = 0, u = 0, v = 0, p0 = 0, p1 = 0, vrs = 0, vre = 0, vq0 = 0, vq1 = 0;
+    uint32_t eid = 0, u = 0, v = 0, p0 = 0, p1 = 0, vrs = 0, vre = 0, vq0 = 0, vq1 = 0, k = 1;
     int32_t t = 0, lo = 0;
     if (act) {
       eid = g.in_eid[q];
@@ -141,7 +141,8 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
       u = g.in_nbr[q];
       v = g.in_dst[q];
       t = g.in_t[q];
-      lo = part_window_lo(t, mp.delta);
+      lo = part_window_lo(t, delta_of(mp, u));
+      k = k_of(mp, u);
       const uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
       p1 = lower_bound_i32(g.in_t, cs, ce, t);
       p0 = lower_bound_i32(g.in_t, cs, p1, lo);
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
     L.a_v[lane] = v;
     L.a_t[lane] = t;
     L.a_lo[lane] = lo;
+    L.a_k[lane] = k;
     L.a_p0[lane] = p0;
     L.a_pref[lane] = aincl - alen;
     L.a_vrs[lane] = vrs;
@@ -248,11 +250,11 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
       }
       __syncthreads();
       // |M_e(s)| = 1 (u) + the intermediates counted: the instance and its bin
-      const uint32_t size = snd ? 1u + L.s_cnt[slot] : 0u;
-      const bool inst = snd && size >= k;
+      const uint32_t size = snd ? 1u + L.s_cnt[slot] : 0u, ka = snd ? L.a_k[a] : 1u;
+      const bool inst = snd && size >= ka;
       if (inst) {
         atomicAdd(&L.a_inst[a], 1u);
-        atomicAdd(&L.a_bin[size - k < 3 ? size - k : 3u][a], 1u);
+        atomicAdd(&L.a_bin[size - ka < 3 ? size - ka : 3u][a], 1u);
       }
       uint64_t imask = col_ps ? __ballot(inst) : 0ull;
       __syncthreads();  // the pair slots are rewritten by the next step

@@ -38,7 +38,7 @@ def test_forward_and_gradient_match_fp64_reference():
 
 
 def test_matrix_core_inference_matches_reference():
-    """The MFMA path (16x16x16 BF16 tiles) against the FP64 reference with the
+    """The MFMA path (16x16x32 BF16 tiles) against the FP64 reference with the
     same BF16 rounding of inputs and activations; sizes cover partial tiles."""
     rng = np.random.default_rng(11)
     w = _weights(3)

@@ -3,8 +3,9 @@
 it belongs to) and the scatter-gather size bins (AMLM_SG_SIZES).  Random
 small graphs with ties and self-loops, a 100k-edge graph with hubs, ordered
 and unordered legs, k from 1 to 4, the saturation ceiling, the
-allocation-free entry point, a sliced schedule, and the streaming server,
-whose new anchors credit older edges through deltas."""
+allocation-free entry point, a sliced schedule, batched stores with mixed
+parameters, and the streaming server, whose new anchors credit older edges
+through deltas."""
 import numpy as np
 import pytest
 
@@ -108,10 +109,28 @@ def test_participation_errors():
             A.amlm_mine(G, A.params(pat, 10, 4, 2), torch.zeros((1, g.n_edges), dtype=torch.int32, device="cuda"))
         assert ei.value.status == 1
     G.close()
-    B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices)])
-    with pytest.raises(A.AmlmError) as ei:
-        A.amlm_mine_batch(B, [A.params(A.AMLM_ALL | A.AMLM_PART, 10, 4, 2)])
-    assert ei.value.status == 1
+
+
+def test_instance_columns_in_a_batch_with_mixed_parameters():
+    """Batched stores: every sub-graph with its own window, threshold and
+    cycle length, through one captured launch (replayed), each sub-graph's
+    columns against the oracle on that sub-graph."""
+    rng = np.random.default_rng(17)
+    subs = []
+    for i in range(6):
+        e = int(rng.integers(100, 4000))
+        g = W.power_law(870 + i, max(20, e // 8), e, 4, 2.1, max(20.0, e / 50), delta_s=86400)
+        subs.append((g, int(rng.choice([3600, 86400])), int(rng.integers(2, 7)), int(rng.integers(1, 4))))
+    B = A.Batch([(g.src, g.dst, g.ts, g.n_vertices) for g, _, _, _ in subs])
+    pats = A.AMLM_ALL | A.AMLM_DEG_IN | A.AMLM_PART | A.AMLM_SG_SIZES
+    ps = [A.params(pats, d, L, k) for _, d, L, k in subs]
+    for rep in range(2):
+        outs = A.amlm_mine_batch(B, ps)
+        torch.cuda.synchronize()
+        for (g, d, L, k), o in zip(subs, outs):
+            ref = oracle.mine(g.src, g.dst, g.ts, g.n_vertices,
+                              oracle.ALL | oracle.DEG_IN | oracle.PART | oracle.SG_SIZES, d, L, k)
+            np.testing.assert_array_equal(A.to_u32(o), ref, err_msg=f"replay {rep}, delta {d}, L {L}, k {k}")
     B.close()
 
 
