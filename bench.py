@@ -317,6 +317,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-slots", type=int, default=4, help="server slots (batches mined concurrently)")
     ap.add_argument("--serve-inflight", type=int, default=64, help="batches submitted and not yet collected")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, set before the runtime starts): "
+                         "the server runs one stream per slot plus its committer's; 0 leaves the environment alone")
     ap.add_argument("--model-cache", default=None, help="load / save the trained cost model here")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: no comparisons, plus a 1 GiB copy of known size")
@@ -330,6 +333,8 @@ def main():
         sys.exit(2)
     if args.profile:
         args.no_serve = args.no_batch = args.no_cpu_baseline = True
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
 
     g, delta, L, k = make_workload(args.workload)
     gh = make_workload("mid_heldout")[0] if not args.profile else None
@@ -468,7 +473,7 @@ def main():
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {E} edges, {g.n_vertices} accounts, "
                                f"delta={delta}s, L={L}, k={k}", "schedule": args.schedule,
-                   "sg_order": args.sg_order,
+                   "sg_order": args.sg_order, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
                    "n_edges": E, "n_vertices": g.n_vertices, "delta": delta, "L": L, "k": k},
         "mine_only_edges_per_s": E / (mine_ms * 1e-3) if mine_ms > 0 else None,
         "stage_ms": avg,
