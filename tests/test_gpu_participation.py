@@ -99,6 +99,39 @@ def test_participation_static_entry_and_sliced_schedule():
     G.close()
 
 
+def test_instance_columns_edge_cases():
+    """Empty graph, only self-loops, one edge, equal timestamps everywhere
+    with many parallel edges (zero and short windows), and a window that
+    spans almost the whole relative-time range."""
+    T0 = W.T0
+    pat = A.AMLM_ALL | A.AMLM_DEG_OUT | PART[0] | SIZES[0]
+    opat = oracle.ALL | oracle.DEG_OUT | PART[1] | SIZES[1]
+    ncols = A.amlm_num_columns(A.params(pat, 10, 4, 2))
+    e = W.EdgeList(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.int64),
+                   np.zeros(0, np.float32), 5)
+    assert _mine(e, pat, 10, 4, 2).shape == (ncols, 0)
+    s = W.EdgeList(np.array([1, 2, 2], np.uint32), np.array([1, 2, 2], np.uint32),
+                   np.array([T0, T0, T0 + 1], np.int64), np.zeros(3, np.float32), 3)
+    assert _mine(s, pat, 10, 4, 2).sum() == 0
+    one = W.EdgeList(np.array([0], np.uint32), np.array([1], np.uint32), np.array([T0], np.int64),
+                     np.zeros(1, np.float32), 2)
+    np.testing.assert_array_equal(_mine(one, pat, 0, 2, 1),
+                                  oracle.mine(one.src, one.dst, one.ts, 2, opat, 0, 2, 1))
+    rng = np.random.default_rng(4)
+    par = W.EdgeList(rng.integers(0, 4, 300).astype(np.uint32), rng.integers(0, 4, 300).astype(np.uint32),
+                     np.full(300, T0, np.int64), np.zeros(300, np.float32), 4)
+    few = W.EdgeList(par.src, par.dst, T0 + rng.integers(0, 3, 300).astype(np.int64), par.amount, 4)
+    for g, d, k in ((par, 0, 1), (par, 5, 2), (few, 0, 1), (few, 1, 2), (few, 5, 1)):
+        ref = oracle.mine(g.src, g.dst, g.ts, 4, opat, d, 4, k)
+        np.testing.assert_array_equal(_mine(g, pat, d, 4, k), ref, err_msg=f"ties d{d} k{k}")
+    assert ref[-6:].sum() > 0   # three distinct times: instances exist
+    big = W.random_small(9, n_edges=200, n_vertices=6, t_range=20)
+    big.ts[::7] += 2**31 - 100
+    for d in (2**31, 10):
+        np.testing.assert_array_equal(_mine(big, pat, d, 4, 2),
+                                      oracle.mine(big.src, big.dst, big.ts, 6, opat, d, 4, 2), err_msg=f"span d{d}")
+
+
 def test_participation_errors():
     g = W.random_small(3, n_edges=50, n_vertices=6, t_range=20)
     G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
