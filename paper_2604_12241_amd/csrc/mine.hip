@@ -444,18 +444,102 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
 
 // Phase-ordered joins of a batch of pairs: one lane per pair, each scanning
 // its slice serially (the filter of the segment rejects most entries).
+// Phase-ordered join of the batch's pairs.  The (pair, out-window entry)
+// items are flattened over the lanes in 64-lane steps, pairs in slot order
+// and each pair's entries in time order: a lane tests its entry (the
+// sender's first edge to an intermediate m != u, a filter hit, m's latest
+// gather leg g_m up to t after it), and the step's hits, in lane order, are
+// folded by each pair's own lane in that order into its k - 1 latest g_m,
+// as the serial scan of sg_phase_pair does.  A pair is decided at the first
+// interval where the condition holds; its later entries are skipped.
 __device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre,
                               uint32_t k) {
+  const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
-  if (lane >= np) return;
-  const uint32_t it = L.pr_item[lane], b = L.pr_b[lane], n = L.pr_n[lane];
-  if (n == 0) return;
-  const uint32_t s = mp.g.out_src[b];
-  const uint32_t hu = vhash(L.i_u[it]);
-  uint32_t scanned;
-  auto filter = [&](uint32_t h) { return h != hu && bloom_test(L.bloom, shift, h); };
-  if (sg_phase_pair(mp, s, L.i_u[it], L.i_lo[it], L.i_t[it], k, b, n, vrs, vre, filter, &scanned))
-    L.pr_cnt[lane] = k - 1;
+  const uint64_t lt = lanemask_lt();
+  const uint32_t need = k - 1;  // k >= 2 here (k < 2 needs no join)
+  // this lane's pair: f_u (the sender's first edge to u in the window) and
+  // the k - 1 latest gather times of its intervals so far
+  int32_t f_u = 0;
+  int32_t top[kPhaseKMax - 1];
+#pragma unroll
+  for (uint32_t i = 0; i < kPhaseKMax - 1; i++) top[i] = AMLM_INT_MIN;
+  uint32_t my_n = 0;
+  if (lane < np) {
+    my_n = L.pr_n[lane];
+    if (my_n) {
+      const uint32_t it = L.pr_item[lane], s = g.out_src[L.pr_b[lane]], u = L.i_u[it];
+      const int32_t lo = L.i_lo[it], t = L.i_t[it];
+      const uint32_t urs = g.in_ptr[u], ure = g.in_ptr[u + 1];
+      const uint64_t ku = nbr_key(s, lo < 0 ? 0 : lo);
+      const uint32_t qu = ku ? upper_bound_u64_interp(g.inn_key, urs, ure, ku - 1) : urs;
+      f_u = t;
+      if (qu < ure && (uint32_t)(g.inn_key[qu] >> 32) == s) f_u = (int32_t)(uint32_t)g.inn_key[qu];
+    }
+  }
+  const uint32_t incl = wave_incl_scan(my_n);
+  const uint32_t T = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
+  L.pr_off[lane] = incl - my_n;
+  __syncthreads();
+  for (uint32_t f0 = 0; f0 < T; f0 += AMLM_WAVE) {
+    const uint32_t f = f0 + lane;
+    bool hit = false;
+    uint32_t a = 0;
+    int32_t fm = 0, gm = 0;
+    if (f < T) {
+      a = owner_of(L.pr_off, np, f);
+      if (L.pr_cnt[a] < need) {  // the pair is not decided yet
+        const uint32_t pos = L.pr_b[a] + (f - L.pr_off[a]);
+        const uint32_t it = L.pr_item[a], u = L.i_u[it];
+        const int32_t lo = L.i_lo[it], t = L.i_t[it];
+        const uint32_t m = g.out_nbr[pos];
+        if (m != u && g.out_prv[pos] < lo && bloom_test(L.bloom, shift, g.out_h[pos])) {
+          const uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+          if (q > vrs) {
+            const uint64_t kk = g.inn_key[q - 1];
+            gm = (int32_t)(uint32_t)kk;
+            fm = g.out_t[pos];
+            hit = (uint32_t)(kk >> 32) == m && gm >= lo && fm < gm;
+          }
+        }
+      }
+    }
+    const uint64_t hm = __ballot(hit);
+    if (!hm) continue;
+    const uint32_t nh = (uint32_t)__popcll(hm);
+    if (hit) {
+      const uint32_t slot = (uint32_t)__popcll(hm & lt);
+      L.cq_pos[slot] = (uint32_t)fm;
+      L.cq_pos[AMLM_WAVE + slot] = (uint32_t)gm;
+      L.cq_pair[slot] = (uint8_t)a;
+    }
+    __syncthreads();
+    if (lane < np && L.pr_cnt[lane] < need) {
+      for (uint32_t j = 0; j < nh; j++) {
+        if (L.cq_pair[j] != lane) continue;
+        int32_t x = (int32_t)L.cq_pos[AMLM_WAVE + j];
+        const int32_t fj = (int32_t)L.cq_pos[j];
+        // insert g into the descending list of the k - 1 largest
+#pragma unroll
+        for (uint32_t i = 0; i < kPhaseKMax - 1; i++) {
+          if (i < need && x > top[i]) {
+            const int32_t y = top[i];
+            top[i] = x;
+            x = y;
+          }
+        }
+        int32_t kth = top[0];
+#pragma unroll
+        for (uint32_t i = 1; i < kPhaseKMax - 1; i++)
+          if (i == need - 1) kth = top[i];
+        if (kth > max(fj, f_u)) {
+          L.pr_cnt[lane] = need;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Reverse join of the pairs in `rev` (degree-ordered intersection, Section

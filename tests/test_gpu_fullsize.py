@@ -2,8 +2,9 @@
 processes over disjoint anchor ranges or independent graphs):
 
 * the 5M-edge graph (500k accounts, 16 days, delta 24 h, L 6, k 2), every
-  column of every edge, static and learned schedules, and with the
-  participation and size columns;
+  column of every edge, static and learned schedules, with the
+  participation and size columns, and with the phase-ordered scatter-gather
+  and any-order cycles;
 * the 256 independent sub-graphs of 1k-200k edges (9.8M edges, windows of
   6 / 24 / 72 h) through one captured batched launch, every sub-graph;
 * serving over the 32M-edge resident graph: every 10th of 60 stream batches
@@ -50,6 +51,22 @@ def test_mid_5M_full_graph_instance_columns():
     assert ref[-6:].sum() > 0
     G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
     c = A.to_u32(A.amlm_mine(G, A.params(A.AMLM_ALL | A.AMLM_PART | A.AMLM_SG_SIZES, 86400, 6, 2)))
+    A.amlm_graph_sync(G)
+    G.close()
+    bad = int((c != ref).sum())
+    assert bad == 0, f"{bad} mismatching counts"
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_mid_5M_full_graph_phase_order_and_any_order_cycles(k):
+    """The phase-ordered scatter-gather and any-order cycles beside every
+    other column on the 5M-edge graph, every edge."""
+    g = W.mid(206)
+    ref, _ = mine_parallel(g.src, g.dst, g.ts, g.n_vertices, oracle.ALL | oracle.SG_PHASE | oracle.CYC_ANY_ORDER,
+                           86400, 4, k)
+    assert ref[2].sum() > 0
+    G = A.Graph(g.src, g.dst, g.ts, g.n_vertices)
+    c = A.to_u32(A.amlm_mine(G, A.params(A.AMLM_ALL | A.AMLM_SG_PHASE | A.AMLM_CYC_ANY_ORDER, 86400, 4, k)))
     A.amlm_graph_sync(G)
     G.close()
     bad = int((c != ref).sum())
