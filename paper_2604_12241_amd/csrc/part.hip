@@ -14,22 +14,25 @@
 // the shorter of s's out-window [t - delta, t) (found through the out-row
 // time index) and v's in-window, whose entries are tested by one search
 // each: in v's (source, time)-sorted in-row for the intermediate's latest
-// gather leg g_m, or in the intermediate's sorted in-row for a leg from s.  Per-pair counts in LDS give
-// |M_e(s)| (u included), hence the instance and its size bin.  The pass
-// re-derives what it needs from the graph store (it does not read the SG /
-// GS columns, which may be saturated).  Credits, one instance at a time,
-// the whole wave:
+// gather leg g_m, or in the intermediate's sorted in-row for a leg from s.
+// Per-pair counts in LDS give |M_e(s)| (u included), hence the instance and
+// its size bin.  The pass re-derives what it needs from the graph store (it
+// does not read the SG / GS columns, which may be saturated).  Credits:
 //  * scatter-gather: 1 to the anchor, to s's legs into u (a key range of
 //    u's sorted in-row), to every scatter leg earlier than g_m and, from m's
 //    first scatter leg f_m, to the gather legs in (f_m, t] (a key range of
-//    v's sorted in-row);
+//    v's sorted in-row), the instances' out-window entries flattened over
+//    the lanes like the counts;
 //  * gather-scatter (|S(e)| from the last-edge-of-its-pair test, tau from
-//    the first sender entry, k distinct first legs of u in (tau, t]): u's
-//    out-row slice (tau, t] gets |S(e)| each, the sender entries 1 each.
+//    the first sender entry, k distinct first legs of u in (tau, t] counted
+//    by ballots): u's out-row slice (tau, t] gets |S(e)| each, the sender
+//    entries 1 each, as range adds into difference arrays summed afterwards
+//    (direct atomics on small graphs and narrow anchor ranges).
 // Credits saturate at the graph's ceiling like every other count.
 #include <algorithm>
 
 #include "api_internal.h"
+#include "costmodel.h"
 
 namespace {
 
@@ -37,6 +40,7 @@ constexpr uint32_t kPartAnchors = AMLM_WAVE;  // anchors per claim: one per lane
 constexpr uint32_t kPartWaves = 28;           // waves per CU in the grid (7 per SIMD: the register limit)
 constexpr uint32_t kCtrPart = 40;             // claim counter word in the mining scratch
 constexpr uint32_t kNoPos = 0xffffffffu;
+constexpr uint32_t kDiffMinEdges = 4096;      // graphs with fewer valid edges credit gather-scatter directly
 
 __device__ __forceinline__ int32_t part_window_lo(int32_t t, int64_t delta) {
   const int64_t lo = (int64_t)t - delta;
@@ -70,44 +74,64 @@ struct PartLds {
   uint32_t s_r0[AMLM_WAVE], s_pref[AMLM_WAVE], s_cnt[AMLM_WAVE], s_a[AMLM_WAVE], s_s[AMLM_WAVE];
 };
 
-// The edges of scatter-gather instance (anchor a of the chunk, sender s),
-// whose out-window is [r0, r1): s's legs into u, the scatter legs earlier
-// than their intermediate's latest gather leg, and the gather legs later
-// than its first scatter leg (the whole wave).
-__device__ void credit_sg_instance(const MineParams &mp, const PartLds &L, uint32_t a, uint32_t s, uint32_t r0,
-                                   uint32_t r1, uint32_t *col, bool unordered) {
+// One out-window entry x (an edge s -> m) of scatter-gather instance
+// (anchor a of the chunk, sender s): x is credited when m != u has a gather
+// leg into v after it in the window (any, unordered); s's first leg to m
+// also credits m's gather legs after it (all in the window, unordered).
+__device__ void credit_sg_entry(const MineParams &mp, const PartLds &L, uint32_t a, uint32_t x, uint32_t *col,
+                                bool unordered) {
   const GraphView &g = mp.g;
-  const uint32_t lane = lane_id();
   const uint32_t u = L.a_u[a], vrs = L.a_vrs[a], vre = L.a_vre[a];
   const int32_t t = L.a_t[a], lo = L.a_lo[a];
-  const int32_t klo = lo < 0 ? 0 : lo;  // times are >= 0: the same bound for the keys
-  const uint32_t cs = g.in_ptr[u], ce = g.in_ptr[u + 1];
-  const uint32_t a0 = lower_bound_u64(g.inn_key, cs, ce, nbr_key(s, klo));
-  const uint32_t a1 = lower_bound_u64(g.inn_key, a0, ce, nbr_key(s, t));
-  for (uint32_t x = a0 + lane; x < a1; x += AMLM_WAVE) credit(col + g.inn_eid[x], 1u, mp.ceil);
-  for (uint32_t x = r0 + lane; x < r1; x += AMLM_WAVE) {
-    const uint32_t m = g.out_nbr[x];
-    if (m == u) continue;
-    const uint32_t qk = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
-    if (qk == vrs) continue;
-    const uint64_t key = g.inn_key[qk - 1];
-    const int32_t gm = (int32_t)(uint32_t)key;
-    if ((uint32_t)(key >> 32) != m || gm < lo) continue;  // m has no gather leg in the window
-    const int32_t ta = g.out_t[x];
-    if (unordered || ta < gm) credit(col + g.out_eid[x], 1u, mp.ceil);
-    if (g.out_prv[x] < lo) {  // s's first leg to m: the gather legs after it
-      const uint32_t b0 = unordered ? lower_bound_u64(g.inn_key, vrs, qk, nbr_key(m, klo))
-                                    : upper_bound_u64_interp(g.inn_key, vrs, qk, nbr_key(m, ta));
-      for (uint32_t y = b0; y < qk; y++) credit(col + g.inn_eid[y], 1u, mp.ceil);
-    }
+  const uint32_t m = g.out_nbr[x];
+  if (m == u) return;
+  const uint32_t qk = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+  if (qk == vrs) return;
+  const uint64_t key = g.inn_key[qk - 1];
+  const int32_t gm = (int32_t)(uint32_t)key;
+  if ((uint32_t)(key >> 32) != m || gm < lo) return;  // m has no gather leg in the window
+  const int32_t ta = g.out_t[x];
+  if (unordered || ta < gm) credit(col + g.out_eid[x], 1u, mp.ceil);
+  if (g.out_prv[x] < lo) {  // s's first leg to m: the gather legs after it
+    const uint32_t b0 = unordered ? lower_bound_u64(g.inn_key, vrs, qk, nbr_key(m, lo < 0 ? 0 : lo))
+                                  : upper_bound_u64_interp(g.inn_key, vrs, qk, nbr_key(m, ta));
+    for (uint32_t y = b0; y < qk; y++) credit(col + g.inn_eid[y], 1u, mp.ceil);
   }
+}
+
+// The same edges found from the gather side: entry x of v's in-window (an
+// edge m -> v) stands for intermediate m when it is m's latest gather leg up
+// to t; m belongs to the instance when m's sorted in-row holds a leg from s
+// in [lo, g_m) ([lo, t) unordered).  Those legs (a key range of m's in-row)
+// and m's gather legs after the first of them (all in the window,
+// unordered; a key range of v's in-row) are credited.
+__device__ void credit_sg_gather_entry(const MineParams &mp, const PartLds &L, uint32_t a, uint32_t s, uint32_t x,
+                                       uint32_t *col, bool unordered) {
+  const GraphView &g = mp.g;
+  const uint32_t u = L.a_u[a], vrs = L.a_vrs[a], vre = L.a_vre[a];
+  const int32_t t = L.a_t[a], lo = L.a_lo[a];
+  const int32_t klo = lo < 0 ? 0 : lo;
+  const uint32_t m = g.in_nbr[x];
+  if (m == u || g.in_nxt[x] <= t) return;
+  const int32_t gm = g.in_t[x];
+  const uint32_t mrs = g.in_ptr[m], mre = g.in_ptr[m + 1];
+  const uint32_t y0 = lower_bound_u64(g.inn_key, mrs, mre, nbr_key(s, klo));
+  const uint32_t y1 = lower_bound_u64(g.inn_key, y0, mre, nbr_key(s, unordered ? t : gm));
+  if (y0 == y1) return;  // no leg from s: m is not an intermediate of s
+  for (uint32_t y = y0; y < y1; y++) credit(col + g.inn_eid[y], 1u, mp.ceil);
+  const int32_t fm = (int32_t)(uint32_t)g.inn_key[y0];
+  const uint32_t qk = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
+  const uint32_t b0 = unordered ? lower_bound_u64(g.inn_key, vrs, qk, nbr_key(m, klo))
+                                : upper_bound_u64_interp(g.inn_key, vrs, qk, nbr_key(m, fm));
+  for (uint32_t b = b0; b < qk; b++) credit(col + g.inn_eid[b], 1u, mp.ceil);
 }
 
 // items: every CSC position (ranged = 0), or the edge ids of the anchor
 // range [anchor_lo, anchor_lo + n_items) (ranged = 1, self-loops skipped).
 // Each anchor takes its (sub-)graph's window and threshold.
 __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint32_t n_items, uint32_t ranged,
-                                             uint32_t *claim) {
+                                             uint32_t *claim, unsigned long long *diff_r,
+                                             unsigned long long *diff_c) {
   const GraphView &g = mp.g;
   __shared__ PartLds L;
   const uint32_t lane = lane_id();
@@ -229,6 +253,9 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
         const uint32_t j = slot_of(L.s_pref, nsnd, h);
         const uint32_t x = L.s_r0[j] + (h - L.s_pref[j]);
         const uint32_t pa = L.s_a[j] & 0x7fffffffu;
+        // a pair's count matters up to k - 1 (the instance), or k + 2 (the
+        // size bins): entries after that are skipped
+        if (L.s_cnt[j] >= (col_sz ? L.a_k[pa] + 2 : L.a_k[pa] - 1)) continue;
         const int32_t plo = L.a_lo[pa];
         if (L.s_a[j] >> 31) {
           const uint32_t m = g.in_nbr[x];
@@ -249,21 +276,50 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
         if ((uint32_t)(key >> 32) == m && gm >= plo && (unordered || gm > g.out_t[x])) atomicAdd(&L.s_cnt[j], 1u);
       }
       __syncthreads();
-      // |M_e(s)| = 1 (u) + the intermediates counted: the instance and its bin
+      // |M_e(s)| = 1 (u) + the intermediates counted (at least the cap once
+      // it is reached): the instance and its bin
       const uint32_t size = snd ? 1u + L.s_cnt[slot] : 0u, ka = snd ? L.a_k[a] : 1u;
       const bool inst = snd && size >= ka;
       if (inst) {
         atomicAdd(&L.a_inst[a], 1u);
         atomicAdd(&L.a_bin[size - ka < 3 ? size - ka : 3u][a], 1u);
       }
-      uint64_t imask = col_ps ? __ballot(inst) : 0ull;
-      __syncthreads();  // the pair slots are rewritten by the next step
-      while (imask) {
-        const uint32_t j = first_lane(imask);
-        imask &= imask - 1;
-        credit_sg_instance(mp, L, __shfl(a, (int)j, AMLM_WAVE), __shfl(s, (int)j, AMLM_WAVE),
-                           __shfl(r0, (int)j, AMLM_WAVE), __shfl(r1, (int)j, AMLM_WAVE), col_ps, unordered);
+      const uint64_t imask = col_ps ? __ballot(inst) : 0ull;
+      __syncthreads();  // the pair slots are rewritten below and by the next step
+      if (!imask) continue;
+      // 3b. the instances' edges.  Each instance's lane credits s's legs
+      //     into u in [lo, t) (a key range of u's sorted in-row); the
+      //     instances' out-window entries are flattened over the lanes
+      // (the shorter of s's out-window and v's in-window, as for the counts)
+      const uint32_t ilen = inst ? (rev ? rv : r1 - r0) : 0u;
+      const uint32_t iincl = wave_incl_scan(ilen);
+      const uint32_t itotal = __shfl(iincl, AMLM_WAVE - 1, AMLM_WAVE);
+      const uint32_t ni = (uint32_t)__popcll(imask);
+      if (inst) {
+        const uint32_t islot = (uint32_t)__popcll(imask & lanemask_lt());
+        L.s_r0[islot] = rev ? L.a_vq0[a] : r0;
+        L.s_pref[islot] = iincl - ilen;
+        L.s_a[islot] = a | (rev ? 0x80000000u : 0u);
+        L.s_s[islot] = s;
+        const uint32_t ua = L.a_u[a];
+        const int32_t la = L.a_lo[a];
+        const uint32_t cs = g.in_ptr[ua], ce = g.in_ptr[ua + 1];
+        const uint32_t a0 = lower_bound_u64(g.inn_key, cs, ce, nbr_key(s, la < 0 ? 0 : la));
+        const uint32_t a1 = lower_bound_u64(g.inn_key, a0, ce, nbr_key(s, L.a_t[a]));
+        for (uint32_t x = a0; x < a1; x++) credit(col_ps + g.inn_eid[x], 1u, mp.ceil);
       }
+      __syncthreads();
+      for (uint32_t h0 = 0; h0 < itotal; h0 += AMLM_WAVE) {
+        const uint32_t h = h0 + lane;
+        if (h >= itotal) continue;
+        const uint32_t j = slot_of(L.s_pref, ni, h);
+        const uint32_t x = L.s_r0[j] + (h - L.s_pref[j]), pa = L.s_a[j] & 0x7fffffffu;
+        if (L.s_a[j] >> 31)
+          credit_sg_gather_entry(mp, L, pa, L.s_s[j], x, col_ps, unordered);
+        else
+          credit_sg_entry(mp, L, pa, x, col_ps, unordered);
+      }
+      __syncthreads();  // the pair slots are rewritten by the next step
     }
     __syncthreads();
 
@@ -271,28 +327,52 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
     //    (tau, t]; its edges are u's out-edges there (|S(e)| instances each)
     //    and the sender entries
     if (col_pg) {
-      bool gs = false;
+      bool cand = false;
       uint32_t ns = 0, d0 = 0, d1 = 0;
+      int32_t tau = 0;
       if (act && L.a_tau[lane] != kNoPos && L.a_ns[lane] >= k) {
+        cand = true;
         ns = L.a_ns[lane];
-        const int32_t tau = g.in_t[L.a_tau[lane]];
+        tau = g.in_t[L.a_tau[lane]];
         const uint32_t rs = g.out_ptr[u], re = g.out_ptr[u + 1];
         d0 = upper_bound_i32(g.out_t, rs, re, tau);
         d1 = upper_bound_i32(g.out_t, d0, re, t);
-        uint32_t nd = 0;
-        for (uint32_t p = d0; p < d1 && nd < k; p++) nd += g.out_prv[p] <= tau;
-        gs = nd >= k;
       }
-      uint64_t gmask = __ballot(gs);
-      while (gmask) {
-        const uint32_t j = first_lane(gmask);
-        gmask &= gmask - 1;
-        const uint32_t nj = __shfl(ns, (int)j, AMLM_WAVE), vj = __shfl(v, (int)j, AMLM_WAVE);
+      uint64_t cmask = __ballot(cand);
+      while (cmask) {
+        const uint32_t j = first_lane(cmask);
+        cmask &= cmask - 1;
+        const uint32_t kj = __shfl(k, (int)j, AMLM_WAVE), nj = __shfl(ns, (int)j, AMLM_WAVE);
+        const int32_t tj = __shfl(tau, (int)j, AMLM_WAVE);
         const uint32_t dj0 = __shfl(d0, (int)j, AMLM_WAVE), dj1 = __shfl(d1, (int)j, AMLM_WAVE);
+        // k distinct destinations: first edges of their pairs in (tau, t], by ballots
+        uint32_t nd = 0;
+        for (uint32_t b = dj0; b < dj1 && nd < kj; b += AMLM_WAVE) {
+          const uint32_t p = b + lane;
+          nd += (uint32_t)__popcll(__ballot(p < dj1 && g.out_prv[p] <= tj));
+        }
+        if (nd < kj) continue;
+        const uint32_t vj = __shfl(v, (int)j, AMLM_WAVE);
         const uint32_t pj0 = __shfl(p0, (int)j, AMLM_WAVE), pj1 = __shfl(p1, (int)j, AMLM_WAVE);
-        for (uint32_t p = dj0 + lane; p < dj1; p += AMLM_WAVE) credit(col_pg + g.out_eid[p], nj, mp.ceil);
-        for (uint32_t p = pj0 + lane; p < pj1; p += AMLM_WAVE)
-          if (g.in_nbr[p] != vj) credit(col_pg + g.in_eid[p], 1u, mp.ceil);
+        if (diff_r) {
+          // range adds: u's out-row slice [d0, d1) by |S(e)|, the sender
+          // entries [p0, p1) by 1, less the entries from v (summed later)
+          if (lane == 0) {
+            atomicAdd(&diff_r[dj0], (unsigned long long)nj);
+            atomicAdd(&diff_r[dj1], 0ull - nj);
+            atomicAdd(&diff_c[pj0], 1ull);
+            atomicAdd(&diff_c[pj1], ~0ull);
+          }
+          for (uint32_t p = pj0 + lane; p < pj1; p += AMLM_WAVE)
+            if (g.in_nbr[p] == vj) {
+              atomicAdd(&diff_c[p], ~0ull);
+              atomicAdd(&diff_c[p + 1], 1ull);
+            }
+        } else {
+          for (uint32_t p = dj0 + lane; p < dj1; p += AMLM_WAVE) credit(col_pg + g.out_eid[p], nj, mp.ceil);
+          for (uint32_t p = pj0 + lane; p < pj1; p += AMLM_WAVE)
+            if (g.in_nbr[p] != vj) credit(col_pg + g.in_eid[p], 1u, mp.ceil);
+        }
       }
     }
 
@@ -303,6 +383,85 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
         if (L.a_bin[b][lane]) credit(col_sz + (uint64_t)b * mp.stride + eid, L.a_bin[b][lane], mp.ceil);
     }
     __syncthreads();  // the tables are rewritten by the next chunk
+  }
+}
+
+// Range adds of the gather-scatter credits, summed: positions are split in
+// tiles of kDiffTile; the tiles' sums, their exclusive scan, then each
+// position's running sum credited to its edge (values are sums of
+// non-negative counts modulo 2^64, so the wrapped negative markers cancel).
+constexpr uint32_t kDiffThreads = 256, kDiffItems = 8, kDiffTile = kDiffThreads * kDiffItems;
+
+__global__ __launch_bounds__(kDiffThreads) void k_diff_tile_sums(const unsigned long long *diff, uint32_t n,
+                                                                 unsigned long long *sums) {
+  __shared__ unsigned long long ws[kDiffThreads / AMLM_WAVE];
+  const uint32_t base = blockIdx.x * kDiffTile;
+  unsigned long long x = 0;
+  for (uint32_t i = threadIdx.x; i < kDiffTile; i += kDiffThreads)
+    if (base + i < n) x += diff[base + i];
+  for (int o = AMLM_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, AMLM_WAVE);
+  if (lane_id() == 0) ws[threadIdx.x / AMLM_WAVE] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (uint32_t w = 0; w < kDiffThreads / AMLM_WAVE; w++) t += ws[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < AMLM_WAVE; d <<= 1) {
+    const unsigned long long y = __shfl_up(x, d, AMLM_WAVE);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// exclusive scan of the nt tile sums, in place (one block)
+__global__ __launch_bounds__(1024) void k_diff_scan_sums(unsigned long long *sums, uint32_t nt) {
+  __shared__ unsigned long long ws[1024 / AMLM_WAVE];
+  __shared__ unsigned long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t b = 0; b < nt; b += 1024) {
+    const uint32_t i = b + threadIdx.x;
+    const unsigned long long x = i < nt ? sums[i] : 0ull;
+    const unsigned long long y = wave_incl_scan_u64(x);
+    if (lane_id() == AMLM_WAVE - 1) ws[threadIdx.x / AMLM_WAVE] = y;
+    __syncthreads();
+    unsigned long long before = carry;
+    for (uint32_t w = 0; w < threadIdx.x / AMLM_WAVE; w++) before += ws[w];
+    if (i < nt) sums[i] = before + y - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = before + y;
+    __syncthreads();
+  }
+}
+
+// position p's running sum, credited to edge eid[p]
+__global__ __launch_bounds__(kDiffThreads) void k_diff_apply(const unsigned long long *diff, uint32_t n,
+                                                             const unsigned long long *offs, const uint32_t *eid,
+                                                             uint32_t *col, uint32_t ceil) {
+  __shared__ unsigned long long ws[kDiffThreads / AMLM_WAVE];
+  const uint32_t base = blockIdx.x * kDiffTile + threadIdx.x * kDiffItems;
+  unsigned long long v[kDiffItems];
+  unsigned long long run = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kDiffItems; j++) {
+    run += base + j < n ? diff[base + j] : 0ull;
+    v[j] = run;
+  }
+  const unsigned long long incl = wave_incl_scan_u64(run);
+  if (lane_id() == AMLM_WAVE - 1) ws[threadIdx.x / AMLM_WAVE] = incl;
+  __syncthreads();
+  unsigned long long before = offs[blockIdx.x] + incl - run;
+  for (uint32_t w = 0; w < threadIdx.x / AMLM_WAVE; w++) before += ws[w];
+#pragma unroll
+  for (uint32_t j = 0; j < kDiffItems; j++) {
+    const unsigned long long x = before + v[j];
+    if (base + j < n && x) credit(col + eid[base + j], x < 0xffffffffull ? (uint32_t)x : 0xffffffffu, ceil);
   }
 }
 
@@ -344,8 +503,37 @@ hipError_t part_launch(const MineParams &mp, const amlm_params *p, MineScratch &
   uint32_t *claim = ms.ctr + kCtrPart;
   hipError_t e = launch_fill_u32(claim, 0, 1, s);
   if (e != hipSuccess) return e;
+  // gather-scatter credits as range adds into two difference arrays (CSR
+  // and CSC positions), in the cost model's feature buffer, which the
+  // mining no longer needs: Ev + 1 entries each, then the tile sums; small
+  // graphs and narrow anchor ranges (stream batches) credit directly
+  const uint32_t Ev = mp.g.Ev, nt = (Ev + kDiffTile - 1) / kDiffTile;
+  unsigned long long *diff_r = nullptr, *diff_c = nullptr, *sums_r = nullptr, *sums_c = nullptr;
+  const uint64_t need = 2ull * (Ev + 1) + 2ull * nt;  // 64-bit words
+  if (cols.pg >= 0 && !ranged && Ev >= kDiffMinEdges && need * 2 <= (uint64_t)kMlpRaw * ms.cap_ev) {
+    diff_r = (unsigned long long *)ms.feat;
+    diff_c = diff_r + Ev + 1;
+    sums_r = diff_c + Ev + 1;
+    sums_c = sums_r + nt;
+    e = launch_fill_u32(ms.feat, 0, 4ull * (Ev + 1), s);
+    if (e != hipSuccess) return e;
+  }
   const uint32_t blocks = std::min<uint32_t>((uint32_t)device_info().num_cu * kPartWaves,
                                              (n_items + kPartAnchors - 1) / kPartAnchors);
-  hipLaunchKernelGGL(k_part, dim3(blocks), dim3(64), 0, s, mp, cols, n_items, ranged ? 1u : 0u, claim);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_part, dim3(blocks), dim3(64), 0, s, mp, cols, n_items, ranged ? 1u : 0u, claim, diff_r,
+                     diff_c);
+  e = hipGetLastError();
+  if (e != hipSuccess || !diff_r) return e;
+  uint32_t *col_pg = mp.counts + (uint64_t)cols.pg * mp.stride;
+  for (int side = 0; side < 2; side++) {
+    unsigned long long *d = side ? diff_c : diff_r, *sm = side ? sums_c : sums_r;
+    const uint32_t *eids = side ? mp.g.in_eid : mp.g.out_eid;
+    hipLaunchKernelGGL(k_diff_tile_sums, dim3(nt), dim3(kDiffThreads), 0, s, d, Ev, sm);
+    hipLaunchKernelGGL(k_diff_scan_sums, dim3(1), dim3(1024), 0, s, sm, nt);
+    hipLaunchKernelGGL(k_diff_apply, dim3(nt), dim3(kDiffThreads), 0, s, d, Ev, (const unsigned long long *)sm, eids,
+                       col_pg, mp.ceil);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
