@@ -40,7 +40,9 @@ constexpr uint32_t kPartAnchors = AMLM_WAVE;  // anchors per claim: one per lane
 constexpr uint32_t kPartWaves = 28;           // waves per CU in the grid (7 per SIMD: the register limit)
 constexpr uint32_t kCtrPart = 40;             // claim counter word in the mining scratch
 constexpr uint32_t kNoPos = 0xffffffffu;
-constexpr uint32_t kDiffMinEdges = 4096;      // graphs with fewer valid edges credit gather-scatter directly
+constexpr uint32_t kDiffMinEdges = 4096;
+constexpr uint32_t kFiltLog2 = 9, kFiltWords = 1u << kFiltLog2;  // 2 KB filter
+constexpr int kFiltShift = 32 - (int)kFiltLog2;      // graphs with fewer valid edges credit gather-scatter directly
 
 __device__ __forceinline__ int32_t part_window_lo(int32_t t, int64_t delta) {
   const int64_t lo = (int64_t)t - delta;
@@ -72,7 +74,14 @@ struct PartLds {
   uint32_t a_k[AMLM_WAVE];  // the anchor's threshold (its sub-graph's in a batched store)
   uint32_t a_inst[AMLM_WAVE], a_bin[4][AMLM_WAVE], a_ns[AMLM_WAVE], a_tau[AMLM_WAVE];
   uint32_t s_r0[AMLM_WAVE], s_pref[AMLM_WAVE], s_cnt[AMLM_WAVE], s_a[AMLM_WAVE], s_s[AMLM_WAVE];
+  uint32_t filt[kFiltWords];  // v's in-neighbours, when the chunk's anchors share v
 };
+
+// Blocked Bloom filter over vertex hashes (vhash): the top bits pick a word,
+// four 5-bit fields of the low bits pick its bits.
+__device__ __forceinline__ uint32_t filt_bits(uint32_t h) {
+  return (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31)) | (1u << ((h >> 15) & 31));
+}
 
 // One out-window entry x (an edge s -> m) of scatter-gather instance
 // (anchor a of the chunk, sender s): x is credited when m != u has a gather
@@ -195,6 +204,31 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
     for (int b = 0; b < 4; b++) L.a_bin[b][lane] = 0u;
     L.a_ns[lane] = 0u;
     L.a_tau[lane] = kNoPos;
+    // a chunk inside one v's in-row (a hub's, typically): a filter of v's
+    // in-neighbours over the union of the anchors' windows rejects most
+    // forward join entries before their search (no false negatives: every
+    // anchor's window lies inside the union)
+    const uint64_t amask = __ballot(act);
+    bool use_filt = false;
+    if (want_sg && amask) {
+      const uint32_t v0 = __shfl(v, (int)first_lane(amask), AMLM_WAVE);
+      use_filt = !__ballot(act && v != v0);
+      if (use_filt) {
+        int32_t wlo = act ? lo : AMLM_INT_MAX, whi = act ? t : AMLM_INT_MIN;
+        for (int o = AMLM_WAVE / 2; o > 0; o >>= 1) {
+          wlo = min(wlo, __shfl_xor(wlo, o, AMLM_WAVE));
+          whi = max(whi, __shfl_xor(whi, o, AMLM_WAVE));
+        }
+        const uint32_t frs = g.in_ptr[v0], fre = g.in_ptr[v0 + 1];
+        const uint32_t f0 = lower_bound_i32(g.in_t, frs, fre, wlo), f1 = upper_bound_i32(g.in_t, f0, fre, whi);
+        for (uint32_t w = lane; w < kFiltWords; w += AMLM_WAVE) L.filt[w] = 0u;
+        __syncthreads();
+        for (uint32_t q = f0 + lane; q < f1; q += AMLM_WAVE) {
+          const uint32_t h = g.in_h[q];
+          atomicOr(&L.filt[h >> kFiltShift], filt_bits(h));
+        }
+      }
+    }
     __syncthreads();
 
     // 2. every (anchor, sender-window entry) item over the lanes: distinct
@@ -268,6 +302,10 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
         }
         const uint32_t m = g.out_nbr[x];
         if (m == L.a_u[pa] || g.out_prv[x] >= plo) continue;
+        if (use_filt) {
+          const uint32_t h = g.out_h[x], fb = filt_bits(h);
+          if ((L.filt[h >> kFiltShift] & fb) != fb) continue;  // no edge m -> v in the chunk's windows
+        }
         const uint32_t pvrs = L.a_vrs[pa], pvre = L.a_vre[pa];
         const uint32_t qk = upper_bound_u64_interp(g.inn_key, pvrs, pvre, nbr_key(m, L.a_t[pa]));
         if (qk == pvrs) continue;
@@ -314,10 +352,15 @@ __global__ __launch_bounds__(64) void k_part(MineParams mp, InstCols cols, uint3
         if (h >= itotal) continue;
         const uint32_t j = slot_of(L.s_pref, ni, h);
         const uint32_t x = L.s_r0[j] + (h - L.s_pref[j]), pa = L.s_a[j] & 0x7fffffffu;
-        if (L.s_a[j] >> 31)
+        if (L.s_a[j] >> 31) {
           credit_sg_gather_entry(mp, L, pa, L.s_s[j], x, col_ps, unordered);
-        else
+        } else {
+          if (use_filt) {  // m without an edge to v in the windows credits nothing
+            const uint32_t hx = g.out_h[x], fb = filt_bits(hx);
+            if ((L.filt[hx >> kFiltShift] & fb) != fb) continue;
+          }
           credit_sg_entry(mp, L, pa, x, col_ps, unordered);
+        }
       }
       __syncthreads();  // the pair slots are rewritten by the next step
     }
