@@ -69,14 +69,28 @@ __device__ __forceinline__ void cell_window(const CellDev &c, const Ctx &x, int3
   hi = c.thi == kThiIncl ? x.t : x.t - 1;
 }
 
+// Blocked Bloom filter over vertex hashes (vhash): the top bits pick a word,
+// four 5-bit fields of the low bits pick its bits.
+constexpr uint32_t kPFiltLog2 = 9, kPFiltWords = 1u << kPFiltLog2;  // 2 KB
+constexpr int kPFiltShift = 32 - (int)kPFiltLog2;
+__device__ __forceinline__ uint32_t pfilt_bits(uint32_t h) {
+  return (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31)) | (1u << ((h >> 15) & 31));
+}
+
 // edges var[node] -> var[peer] inside the cell's window: a key range of the
-// peer's neighbour-sorted in-row (keys (source, time))
-__device__ uint32_t cell_probe(const GraphView &g, const CellDev &c, const Ctx &x) {
+// peer's neighbour-sorted in-row (keys (source, time)).  filt (may be NULL):
+// a filter of the peer's in-neighbours over a window containing the cell's;
+// a vertex it rejects has no such edge.
+__device__ uint32_t cell_probe(const GraphView &g, const CellDev &c, const Ctx &x, const uint32_t *filt) {
   int32_t lo, hi;
   cell_window(c, x, lo, hi);
   if (lo > hi) return 0u;
   const uint32_t a = x.var[c.node], b = x.var[c.peer];
   if (a == b) return 0u;
+  if (filt) {
+    const uint32_t h = vhash(a), fb = pfilt_bits(h);
+    if ((filt[h >> kPFiltShift] & fb) != fb) return 0u;
+  }
   const uint32_t rs = g.in_ptr[b], re = g.in_ptr[b + 1];
   const uint32_t q0 = lower_bound_u64(g.inn_key, rs, re, nbr_key(a, lo));
   const uint32_t q1 = lower_bound_u64(g.inn_key, q0, re, nbr_key(a, hi) + 1);
@@ -144,8 +158,9 @@ __device__ bool cell_bind(const GraphView &g, const CellDev &c, Ctx &x, uint32_t
 // whether it reaches a threshold stops once it does (Algorithm 1's break:
 // every fold only grows, so more bindings cannot change what the parent
 // counts).
-__device__ uint32_t run_from(const GraphView &g, const Prog &P, uint32_t k, uint32_t ceil, Ctx &x, uint32_t d0) {
-  if (P.c[d0].op == kOpProbe) return cell_probe(g, P.c[d0], x);
+__device__ uint32_t run_from(const GraphView &g, const Prog &P, uint32_t k, uint32_t ceil, Ctx &x, uint32_t d0,
+                             const uint32_t *filt) {
+  if (P.c[d0].op == kOpProbe) return cell_probe(g, P.c[d0], x, filt);
   auto open = [&](uint32_t i) {
     cell_slice(g, P.c[i], x, i);
     if (plain_count(P, i)) {  // the slice's length, without walking it
@@ -185,7 +200,7 @@ __device__ uint32_t run_from(const GraphView &g, const Prog &P, uint32_t k, uint
       continue;
     }
     if (P.c[d + 1].op == kOpProbe) {  // a probe is always the last cell
-      fold(d, cell_probe(g, P.c[d + 1], x));
+      fold(d, cell_probe(g, P.c[d + 1], x, filt));
       f.pos++;
       continue;
     }
@@ -215,7 +230,7 @@ __global__ __launch_bounds__(256) void k_interp(GraphView g, Prog P, int64_t del
   }
   Ctx x;
   ctx_init(g, x, e, delta);
-  const uint32_t r = run_from(g, P, k, ceil, x, 0);
+  const uint32_t r = run_from(g, P, k, ceil, x, 0, nullptr);
   out[e] = r < ceil ? r : ceil;
 }
 
@@ -242,10 +257,16 @@ __global__ __launch_bounds__(64) void k_interp_wave(GraphView g, Prog P, int64_t
   __shared__ unsigned long long acc1[AMLM_WAVE];
   __shared__ uint32_t b_w0[AMLM_WAVE], b_pos1[AMLM_WAVE], b_pref[AMLM_WAVE];
   __shared__ int32_t b_t0[AMLM_WAVE], b_lo1[AMLM_WAVE], b_hi1[AMLM_WAVE];
+  __shared__ uint32_t pfilt[kPFiltWords];
   const uint32_t lane = lane_id();
   const CellDev &c0 = P.c[0], &c1 = P.c[1];
   const bool probe1 = c1.op == kOpProbe;
   const bool plain1 = !probe1 && plain_count(P, 1);
+  // a last probe into u or v (fixed for the anchor): filter the peer's
+  // in-neighbours over the anchor's window [t - delta, t], which contains
+  // every window the probe can have
+  const CellDev &cl = P.c[P.n - 1];
+  const bool pf = cl.op == kOpProbe && cl.peer <= kVarV;
   for (;;) {
     uint32_t e0 = 0;
     if (lane == 0) e0 = atomicAdd(claim, kWaveAnchors);
@@ -261,6 +282,20 @@ __global__ __launch_bounds__(64) void k_interp_wave(GraphView g, Prog P, int64_t
       ctx_init(g, x, e, delta);
       cell_slice(g, c0, x, 0);
       const uint32_t pos0 = x.F[0].pos, end0 = x.F[0].end;
+      const uint32_t *filt = nullptr;
+      if (pf && pos0 < end0) {
+        const uint32_t peer = x.var[cl.peer], prs = g.in_ptr[peer], pre = g.in_ptr[peer + 1];
+        const uint32_t f0 = lower_bound_i32(g.in_t, prs, pre, x.wlo), f1 = upper_bound_i32(g.in_t, f0, pre, x.t);
+        __syncthreads();
+        for (uint32_t w = lane; w < kPFiltWords; w += AMLM_WAVE) pfilt[w] = 0u;
+        __syncthreads();
+        for (uint32_t q = f0 + lane; q < f1; q += AMLM_WAVE) {
+          const uint32_t h = g.in_h[q];
+          atomicOr(&pfilt[h >> kPFiltShift], pfilt_bits(h));
+        }
+        __syncthreads();
+        filt = pfilt;
+      }
       unsigned long long acc0 = 0;  // this lane's share of cell 0's fold
       for (uint32_t b = pos0; b < end0; b += AMLM_WAVE) {
         const uint32_t p = b + lane;
@@ -272,7 +307,7 @@ __global__ __launch_bounds__(64) void k_interp_wave(GraphView g, Prog P, int64_t
           continue;
         }
         if (probe1) {
-          if (take) acc0 += contribution(c0, cell_probe(g, c1, x), k);
+          if (take) acc0 += contribution(c0, cell_probe(g, c1, x, filt), k);
           continue;
         }
         uint32_t len1 = 0;
@@ -313,7 +348,7 @@ __global__ __launch_bounds__(64) void k_interp_wave(GraphView g, Prog P, int64_t
             uint32_t w1;
             if (!cell_bind(g, c1, y, 1, b_pos1[j] + (h - b_pref[j]), w1)) continue;
             y.var[3] = w1;
-            const uint32_t val = P.n == 2 ? 1u : run_from(g, P, k, ceil, y, 2);
+            const uint32_t val = P.n == 2 ? 1u : run_from(g, P, k, ceil, y, 2, filt);
             atomicAdd(&acc1[j], (unsigned long long)contribution(c1, val, k));
           }
         }
