@@ -20,8 +20,12 @@ constexpr int kSgThreads = 64;   // one wave per block
 #define AMLM_PREFETCH_CLAIM 0
 #endif
 constexpr bool kPrefetchClaim = AMLM_PREFETCH_CLAIM != 0;
-// optional occupancy target for k_sg (waves per SIMD), for sweeps
-#ifdef AMLM_SG_WAVES_PER_EU
+// occupancy target for k_sg (waves per SIMD): six keep it within 80 VGPRs
+// without spills, and its LDS allows about as many
+#ifndef AMLM_SG_WAVES_PER_EU
+#define AMLM_SG_WAVES_PER_EU 6
+#endif
+#if AMLM_SG_WAVES_PER_EU > 0
 #define AMLM_SG_OCCUPANCY __attribute__((amdgpu_waves_per_eu(AMLM_SG_WAVES_PER_EU, AMLM_SG_WAVES_PER_EU)))
 #else
 #define AMLM_SG_OCCUPANCY
@@ -48,6 +52,13 @@ constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
 // slower, 256 and more no faster
 constexpr uint32_t kBloomBitsPerEntry = AMLM_BLOOM_BITS_PER_ENTRY;
 constexpr int kBloomK = AMLM_BLOOM_K;                   // bits set per key, all in one 32-bit word
+#ifndef AMLM_GROUP_CAP
+#define AMLM_GROUP_CAP 256
+#endif
+// segments of a k_sg chunk (runs of anchors into one vertex) share one filter
+// and one flattened pass while their gather windows total at most this many
+// entries (256: each keeps kBloomBitsPerEntry bits of the largest filter)
+constexpr uint32_t kGroupCap = AMLM_GROUP_CAP;
 constexpr int kJoinUnroll = AMLM_JOIN_UNROLL;
 constexpr uint32_t kSgChunkMax = AMLM_SG_CHUNK_MAX;     // anchors per k_sg chunk (<= 64)
 // default anchors per work unit: the static schedule's blocks of the list

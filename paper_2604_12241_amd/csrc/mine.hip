@@ -344,13 +344,19 @@ struct SgLds {
   // anchors of the current chunk
   uint32_t i_eid[kSgChunkMax], i_u[kSgChunkMax], i_p0[kSgChunkMax], i_ns[kSgChunkMax], i_sg[kSgChunkMax];
   uint32_t i_work[kSgChunkMax], i_wlen[kSgChunkMax];
-  uint32_t seg_off[AMLM_WAVE];  // exclusive offsets of the segment's sender windows
+  uint32_t i_v[kSgChunkMax];    // the anchor's destination v
+  uint32_t i_vk[kSgChunkMax];   // v's filter key mask (pair keys: vhash(m) ^ i_vk)
+  uint32_t i_hu[kSgChunkMax];   // vhash(u): u is never an intermediate
+  uint32_t i_vrs[kSgChunkMax], i_vre[kSgChunkMax];  // v's in-row, for the candidate checks
+  // exclusive offsets: the group's segment windows (filter build), then the
+  // group's sender windows
+  uint32_t seg_off[kSgChunkMax];
   int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax];
-  uint32_t i_q[kSgChunkMax];    // CSC position of each anchor
   uint32_t i_r0[kSgChunkMax], i_r1[kSgChunkMax];  // its v-window [r0, r1) in v's in-row
   uint32_t i_k[kSgChunkMax];    // threshold k of each anchor
-  uint32_t i_join[kSgChunkMax]; // 1 if the anchor's senders need the join
-  uint32_t i_gsd[kSgChunkMax];  // 1 if u has k scatter destinations after tau
+  uint8_t i_join[kSgChunkMax];  // 1 if the anchor's senders need the join
+  uint8_t i_gsd[kSgChunkMax];   // 1 if u has k scatter destinations after tau
+  uint8_t grp_seg[kSgChunkMax]; // first anchor of each segment of the current group
   // (anchor, sender) pairs of one batch
   uint32_t pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
   uint8_t pr_item[AMLM_WAVE];
@@ -359,6 +365,11 @@ struct SgLds {
   uint32_t cq_pos[kCandCap];
   uint8_t cq_pair[kCandCap];  // byte-wide slot fields keep the LDS, and so the waves per CU, in bounds
 };
+
+// Key mask of a gather vertex v: the filter of a group of segments holds the
+// pairs (v, m) of their gather windows as vhash(m) ^ vkey(v), a bijection of
+// vhash(m) for each v, so one filter serves segments into different vertices.
+__device__ __forceinline__ uint32_t vkey(uint32_t v) { return __builtin_rotateleft32(vhash(v), 16); }
 
 // Register-blocked Bloom filter over vertex hashes (vhash): a key selects
 // one 32-bit word by its top bits and sets kBloomK bits inside it chosen by
@@ -398,10 +409,9 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t *off, uint32_t n, ui
 // an edge to v later than the (s, m) entry and no later than the anchor, and
 // the entry must be the first (s, m) edge inside the window.  The search in
 // v's CSC-N row comes first: it rejects the filter's false positives from
-// lines that the segment's other candidates keep in cache, before any read
+// lines that other candidates into the same v keep in cache, before any read
 // of the sender's row.
-__device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint32_t take, uint32_t vrs,
-                          uint32_t vre) {
+__device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint32_t take) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   if (lane < take) {
@@ -409,6 +419,7 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
     uint32_t a = L.cq_pair[idx], pos = L.cq_pos[idx];
     uint32_t it = L.pr_item[a];
     int32_t lo = L.i_lo[it], t = L.i_t[it];
+    const uint32_t vrs = L.i_vrs[it], vre = L.i_vre[it];
     uint32_t m = vhash_inv(g.out_h[pos]);  // the scan has just read this line
     uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
     if (q > vrs) {
@@ -427,7 +438,7 @@ __device__ void sg_verify(const MineParams &mp, SgLds &L, uint32_t cq_top, uint3
 // position pos0 + l) and verify a full batch of 64 when the queue holds at
 // least that many.  Steps without a candidate cost one scalar test.
 __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t &cq, bool cand, uint32_t a,
-                                        uint32_t pos, uint32_t vrs, uint32_t vre) {
+                                        uint32_t pos) {
   uint64_t bc = __builtin_amdgcn_ballot_w64(cand);
   if (bc == 0) return;
   if (cand) {
@@ -437,7 +448,7 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
   }
   cq += __popcll(bc);
   if (cq >= AMLM_WAVE) {
-    sg_verify(mp, L, cq, AMLM_WAVE, vrs, vre);
+    sg_verify(mp, L, cq, AMLM_WAVE);
     cq -= AMLM_WAVE;
   }
 }
@@ -452,8 +463,7 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
 // folded by each pair's own lane in that order into its k - 1 latest g_m,
 // as the serial scan of sg_phase_pair does.  A pair is decided at the first
 // interval where the condition holds; its later entries are skipped.
-__device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t vrs, uint32_t vre,
-                              uint32_t k) {
+__device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
@@ -493,7 +503,8 @@ __device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int s
         const uint32_t it = L.pr_item[a], u = L.i_u[it];
         const int32_t lo = L.i_lo[it], t = L.i_t[it];
         const uint32_t m = g.out_nbr[pos];
-        if (m != u && g.out_prv[pos] < lo && bloom_test(L.bloom, shift, g.out_h[pos])) {
+        if (m != u && g.out_prv[pos] < lo && bloom_test(L.bloom, shift, g.out_h[pos] ^ L.i_vk[it])) {
+          const uint32_t vrs = L.i_vrs[it], vre = L.i_vre[it];
           const uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
           if (q > vrs) {
             const uint64_t kk = g.inn_key[q - 1];
@@ -593,8 +604,7 @@ __device__ void sg_join_rev(const MineParams &mp, SgLds &L, uint32_t np, uint64_
 // its slice [pr_b, pr_b + pr_n) of the sender's out-row.  Long slices are
 // scanned one pair at a time by the whole wave with the pair's fields in
 // scalar registers; short ones are flattened over the lanes.
-__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, int shift, uint32_t vrs,
-                        uint32_t vre, uint32_t k) {
+__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, int shift, uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint32_t need = k - 1;  // intermediates needed besides u
@@ -607,7 +617,8 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
     uint32_t a = __ffsll((long long)longs) - 1;
     longs &= longs - 1;
     const uint32_t b = rfl(L.pr_b[a]), n = rfl(L.pr_n[a]);
-    const uint32_t hu = vhash(rfl(L.i_u[rfl(L.pr_item[a])]));  // u itself is never a candidate
+    const uint32_t it = rfl((uint32_t)L.pr_item[a]);
+    const uint32_t hu = rfl(L.i_hu[it]), vk = rfl(L.i_vk[it]);  // u itself is never a candidate
     for (uint32_t f0 = 0; f0 < n; f0 += U * AMLM_WAVE) {
       if (rfl(L.pr_cnt[a]) >= need) break;
       const uint32_t *src = g.out_h + b + f0 + lane;
@@ -615,8 +626,8 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
       auto step = [&]() {
 #pragma unroll
         for (int r = 0; r < U; r++) {
-          bool cand = (h[r] != hu) & bloom_test(L.bloom, shift, h[r]);
-          sg_push(mp, L, cq, cand, a, b + f0 + r * AMLM_WAVE + lane, vrs, vre);
+          bool cand = (h[r] != hu) & bloom_test(L.bloom, shift, h[r] ^ vk);
+          sg_push(mp, L, cq, cand, a, b + f0 + r * AMLM_WAVE + lane);
         }
       };
       if (f0 + U * AMLM_WAVE <= n) {
@@ -630,7 +641,7 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
       }
       if (need <= kEagerNeed && cq > 0) {
         // few intermediates needed: confirm now, so the scan can stop
-        sg_verify(mp, L, cq, cq, vrs, vre);
+        sg_verify(mp, L, cq, cq);
         cq = 0;
       }
     }
@@ -649,68 +660,108 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
       pos = L.pr_b[a] + (f - L.pr_off[a]);
       if (L.pr_cnt[a] < need) {
         uint32_t h = g.out_h[pos];
-        cand = h != vhash(L.i_u[L.pr_item[a]]) && bloom_test(L.bloom, shift, h);
+        const uint32_t it = L.pr_item[a];
+        cand = h != L.i_hu[it] && bloom_test(L.bloom, shift, h ^ L.i_vk[it]);
       }
     }
-    sg_push(mp, L, cq, cand, a, pos, vrs, vre);
+    sg_push(mp, L, cq, cand, a, pos);
     if (kEagerShort && need <= kEagerNeed && cq > 0) {
-      sg_verify(mp, L, cq, cq, vrs, vre);
+      sg_verify(mp, L, cq, cq);
       cq = 0;
     }
   }
   while (cq > 0) {
     uint32_t take = min(cq, (uint32_t)AMLM_WAVE);
-    sg_verify(mp, L, cq, take, vrs, vre);
+    sg_verify(mp, L, cq, take);
     cq -= take;
   }
   if (rev) sg_join_rev(mp, L, np, rev, need);
 }
 
-// Anchors [s0, s1) of the chunk, all into vertex v.
-__device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t v) {
+// Anchors [s0, s1) of the chunk: a group of nseg segments whose first
+// anchors are grp_seg[0 .. nseg).  A segment is a run of anchors into one v
+// inside one time bucket; its gather window, v's in-edges from its first
+// anchor's window start to its last anchor's time, covers each anchor's.  One
+// filter holds the pairs (v, m) of every segment window of the group, so the
+// senders, pairs and joins of the whole group are flattened over the lanes
+// together (a chunk of anchors into many light vertices is one pass, not one
+// per vertex).
+__device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t nseg) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
   const uint32_t nit = s1 - s0;
-  const uint32_t k = rfl(L.i_k[s0]);  // the anchors of a segment share v, hence the (sub-)graph
+  const uint32_t k = rfl(L.i_k[s0]);  // groups are cut where k changes
   const bool need_join = mp.col_sg >= 0 && k >= 2 &&
                          __ballot(lane >= s0 && lane < s1 && L.i_join[min(lane, kSgChunkMax - 1)] != 0) != 0;
   int shift = 0;
-  uint32_t vrs = 0, vre = 0;
   if (need_join) {
-    vrs = g.in_ptr[v];  // v's row, for the candidate checks
-    vre = g.in_ptr[v + 1];
-    // gather side of the whole segment: v's in-neighbours in [lo_first, t_last]
-    // (the anchors are time-sorted inside the segment)
-    uint32_t r0 = rfl(L.i_r0[s0]), r1 = rfl(L.i_r1[s1 - 1]);
-    uint32_t nin = r1 - r0;
+    // segment j holds anchors [grp_seg[j], grp_seg[j + 1]) (the last ends at
+    // s1); the anchors are time-sorted inside it
+    uint32_t len = 0;
+    if (lane < nseg) {
+      const uint32_t a0 = L.grp_seg[lane], a1 = lane + 1 < nseg ? L.grp_seg[lane + 1] : s1;
+      len = L.i_r1[a1 - 1] - L.i_r0[a0];
+    }
+    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t nin = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
+    if (lane < kSgChunkMax) L.seg_off[lane] = incl - len;
     int lg = 9;
     while (lg < kBloomLog2Max && (1u << lg) < nin * kBloomBitsPerEntry) lg++;
     uint32_t words = (1u << lg) >> 5;
     for (uint32_t q = lane; q < words; q += AMLM_WAVE) L.bloom[q] = 0;
     shift = 32 - (lg - 5);  // word index = top (lg - 5) bits
-    for (uint32_t q0 = r0; q0 < r1; q0 += 4 * AMLM_WAVE) {
-      uint32_t mm[4];
+    if (nseg == 1) {
+      // one window (a hub's row, typically): strided loads, four in flight
+      const uint32_t r0 = rfl(L.i_r0[s0]), r1 = r0 + nin, vk = rfl(L.i_vk[s0]);
+      for (uint32_t q0 = r0; q0 < r1; q0 += 4 * AMLM_WAVE) {
+        uint32_t mm[4];
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        uint32_t q = q0 + r * AMLM_WAVE + lane;
-        mm[r] = q < r1 ? g.in_h[q] : 0u;
+        for (int r = 0; r < 4; r++) {
+          uint32_t q = q0 + r * AMLM_WAVE + lane;
+          mm[r] = q < r1 ? g.in_h[q] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          if (q0 + r * AMLM_WAVE + lane < r1) bloom_insert(L.bloom, shift, mm[r] ^ vk);
+        }
       }
+    } else {
+      // the segment windows flattened over the lanes (at most kGroupCap entries)
+      for (uint32_t f0 = 0; f0 < nin; f0 += 4 * AMLM_WAVE) {
+        uint32_t mm[4];
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        if (q0 + r * AMLM_WAVE + lane < r1) bloom_insert(L.bloom, shift, mm[r]);
+        for (int r = 0; r < 4; r++) {
+          const uint32_t f = f0 + r * AMLM_WAVE + lane;
+          mm[r] = 0;
+          if (f < nin) {
+            const uint32_t j = owner_of(L.seg_off, nseg, f);
+            const uint32_t a0 = L.grp_seg[j];
+            mm[r] = L.i_vk[a0];
+            mm[r] ^= g.in_h[L.i_r0[a0] + (f - L.seg_off[j])];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          if (f0 + r * AMLM_WAVE + lane < nin) bloom_insert(L.bloom, shift, mm[r]);
+        }
       }
     }
     if (mp.work && lane < nit) {
-      uint32_t share = kBytesGatherEntry * nin;
-      L.i_work[s0 + lane] += share / nit + (lane == 0 ? share % nit : 0);
+      // each segment's gather entries, shared evenly by its anchors
+      const uint32_t x = s0 + lane;
+      uint32_t j = 0;
+      for (uint32_t i = 1; i < nseg; i++) j = L.grp_seg[i] <= x ? i : j;
+      const uint32_t a0 = L.grp_seg[j], a1 = j + 1 < nseg ? L.grp_seg[j + 1] : s1;
+      const uint32_t share = kBytesGatherEntry * (L.i_r1[a1 - 1] - L.i_r0[a0]);
+      L.i_work[x] += share / (a1 - a0) + (x == a0 ? share % (a1 - a0) : 0);
     }
   }
   // senders: flatten the anchors' windows [p0, p1) over the lanes
   uint32_t w = lane < nit ? L.i_wlen[s0 + lane] : 0u;
   uint32_t incl = wave_incl_scan(w);
   uint32_t W = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
-  L.seg_off[lane] = incl - w;
+  if (lane < kSgChunkMax) L.seg_off[lane] = incl - w;
   for (uint32_t f0 = 0; f0 < W; f0 += AMLM_WAVE) {
     uint32_t f = f0 + lane;
     bool is_s = false;
@@ -720,7 +771,7 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
       it = s0 + a;
       j = L.i_p0[it] + (f - L.seg_off[a]);
       nb = g.in_nbr[j];
-      if (nb != v) {
+      if (nb != L.i_v[it]) {
         is_s = g.in_nxt[j] >= L.i_t[it];  // last sender edge before t: one per distinct s
         if (is_s) atomicAdd(&L.i_ns[it], 1u);
       }
@@ -762,9 +813,9 @@ __device__ void sg_segment(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t
     // reverse pairs by slot
     const uint64_t rev = __ballot(lane < np && L.pr_rev[lane] != 0);
     if (mp.sg_phase)
-      sg_join_phase(mp, L, np, shift, vrs, vre, k);
+      sg_join_phase(mp, L, np, shift, k);
     else
-      sg_join(mp, L, np, rev, shift, vrs, vre, k);
+      sg_join(mp, L, np, rev, shift, k);
     if (lane < np && L.pr_cnt[lane] >= k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
   }
 }
@@ -952,7 +1003,7 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
     const uint2 un = units ? units[c] : make_uint2(c * block, min(block, n_count - c * block));
     const bool heavy = (un.y & kUnitHeavy) != 0;
     const uint32_t nr = heavy ? 1u : un.y;
-    uint32_t v = 0xffffffffu;
+    uint32_t v = 0xffffffffu, r0v = 0, r1v = 0, kv = 0;
     int64_t dl = 1;
     if (lane < nr) {
       uint32_t q = items[un.x + lane];
@@ -968,18 +1019,26 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
         first_slice = sl == 0;
       }
       v = g.in_dst[q];
-      L.i_q[lane] = q;
+      const uint32_t u = g.in_nbr[q];
       L.i_eid[lane] = eid;
-      L.i_u[lane] = g.in_nbr[q];
+      L.i_u[lane] = u;
+      L.i_hu[lane] = vhash(u);
+      L.i_v[lane] = v;
+      L.i_vk[lane] = vkey(v);
+      L.i_vrs[lane] = g.in_ptr[v];
+      L.i_vre[lane] = g.in_ptr[v + 1];
       L.i_t[lane] = t;
       dl = delta_of(mp, v);
       L.i_lo[lane] = window_lo(t, dl);
-      L.i_k[lane] = k_of(mp, v);
+      kv = k_of(mp, v);
+      L.i_k[lane] = kv;
       const uint8_t fl = flags_sg[q];
-      L.i_join[lane] = (fl & kFlagSgNoJoin) ? 0u : 1u;
-      L.i_gsd[lane] = (fl & kFlagGsDest) ? 1u : 0u;
+      L.i_join[lane] = (fl & kFlagSgNoJoin) ? 0 : 1;
+      L.i_gsd[lane] = (fl & kFlagGsDest) ? 1 : 0;
       L.i_p0[lane] = pw.x;
       L.i_wlen[lane] = pw.y - pw.x;
+      r0v = pw.z;
+      r1v = pw.w;
       L.i_r0[lane] = pw.z;
       L.i_r1[lane] = pw.w;
       L.i_ns[lane] = 0;
@@ -993,13 +1052,38 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
     int32_t tb = lane < nr ? L.i_t[lane] / seg_span : 0;
     uint32_t vprev = __shfl_up(v, 1, AMLM_WAVE);
     int32_t tbprev = __shfl_up(tb, 1, AMLM_WAVE);
-    uint64_t heads = __ballot(lane < nr && (lane == 0 || v != vprev || tb != tbprev));
-    while (heads) {
-      uint32_t s0 = __ffsll((long long)heads) - 1;
-      heads &= heads - 1;
-      uint32_t s1 = heads ? (uint32_t)(__ffsll((long long)heads) - 1) : nr;
-      uint32_t vs = rfl((uint32_t)__shfl(v, s0, AMLM_WAVE));
-      sg_segment(mp, L, s0, s1, vs);
+    const uint64_t heads = __ballot(lane < nr && (lane == 0 || v != vprev || tb != tbprev));
+    // each segment's gather window (at its head lane): from its first
+    // anchor's r0 to the r1 of the lane before the next head
+    const uint64_t later = heads & ~((2ull << lane) - 1);
+    const uint32_t send = later ? (uint32_t)(__ffsll((long long)later) - 1) : nr;
+    const uint32_t r1_end = (uint32_t)__shfl(r1v, (int)(send > 0 ? send - 1 : 0), AMLM_WAVE);
+    const uint32_t segw = r1_end - r0v;
+    // groups: consecutive segments of one k whose windows total at most
+    // kGroupCap entries (a longer window is a group of its own)
+    uint64_t gheads = 0, hs = heads;
+    uint32_t gk = 0;
+    uint64_t gsum = 0;
+    while (hs) {
+      const uint32_t h0 = __ffsll((long long)hs) - 1;
+      hs &= hs - 1;
+      const uint32_t sw = rfl((uint32_t)__shfl(segw, h0, AMLM_WAVE));
+      const uint32_t kk = rfl((uint32_t)__shfl(kv, h0, AMLM_WAVE));
+      if (gheads == 0 || gsum + sw > kGroupCap || kk != gk) {
+        gheads |= 1ull << h0;
+        gsum = 0;
+      }
+      gsum += sw;
+      gk = kk;
+    }
+    while (gheads) {
+      const uint32_t g0 = __ffsll((long long)gheads) - 1;
+      gheads &= gheads - 1;
+      const uint32_t g1 = gheads ? (uint32_t)(__ffsll((long long)gheads) - 1) : nr;
+      // the group's segment heads, in order
+      const uint64_t sh = heads & ((1ull << g1) - 1) & ~((1ull << g0) - 1);  // g1 <= nr <= 16
+      if ((sh >> lane) & 1ull) L.grp_seg[__popcll(sh & lanemask_lt())] = (uint8_t)lane;
+      sg_group(mp, L, g0, g1, (uint32_t)__popcll(sh));
     }
     // gather-scatter and the outputs, one lane per anchor
     uint32_t sg = 0, gs = 0, work = 0;
