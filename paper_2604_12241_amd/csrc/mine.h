@@ -46,7 +46,13 @@ constexpr bool kPrefetchClaim = AMLM_PREFETCH_CLAIM != 0;
 #define AMLM_JOIN_UNROLL 8
 #endif
 constexpr int kBloomLog2Max = AMLM_BLOOM_LOG2_MAX;      // 32 Kbit (4 KB) filter: occupancy beats a lower false-positive rate
-constexpr uint32_t kBloomWordsMax = (1u << kBloomLog2Max) / 32;
+#ifndef AMLM_BLOOM_WORDS_MAX
+#define AMLM_BLOOM_WORDS_MAX 960
+#endif
+// the largest filter, in 32-bit words: 960 (3840 bytes) rather than 1024
+// keeps a k_sg wave's LDS within 6400 bytes, 24 waves per CU
+constexpr uint32_t kBloomWordsMax = AMLM_BLOOM_WORDS_MAX < (1u << kBloomLog2Max) / 32 ? AMLM_BLOOM_WORDS_MAX
+                                                                                       : (1u << kBloomLog2Max) / 32;
 // filter bits per gathered entry, up to the maximum size: 128 gives short
 // segments a sparse filter (fewer false positives to verify); 32 and 64 were
 // slower, 256 and more no faster

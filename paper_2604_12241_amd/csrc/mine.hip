@@ -342,10 +342,9 @@ constexpr uint32_t kCandCap = 2 * AMLM_WAVE;
 struct SgLds {
   uint32_t bloom[kBloomWordsMax];
   // anchors of the current chunk
-  uint32_t i_eid[kSgChunkMax], i_u[kSgChunkMax], i_p0[kSgChunkMax], i_ns[kSgChunkMax], i_sg[kSgChunkMax];
+  uint32_t i_u[kSgChunkMax], i_p0[kSgChunkMax], i_ns[kSgChunkMax], i_sg[kSgChunkMax];
   uint32_t i_work[kSgChunkMax], i_wlen[kSgChunkMax];
-  uint32_t i_v[kSgChunkMax];    // the anchor's destination v
-  uint32_t i_vk[kSgChunkMax];   // v's filter key mask (pair keys: vhash(m) ^ i_vk)
+  uint32_t i_vk[kSgChunkMax];   // vkey of the anchor's v (pair keys: vhash(m) ^ i_vk)
   uint32_t i_hu[kSgChunkMax];   // vhash(u): u is never an intermediate
   uint32_t i_vrs[kSgChunkMax], i_vre[kSgChunkMax];  // v's in-row, for the candidate checks
   // exclusive offsets: the group's segment windows (filter build), then the
@@ -353,17 +352,24 @@ struct SgLds {
   uint32_t seg_off[kSgChunkMax];
   int32_t i_t[kSgChunkMax], i_lo[kSgChunkMax];
   uint32_t i_r0[kSgChunkMax], i_r1[kSgChunkMax];  // its v-window [r0, r1) in v's in-row
-  uint32_t i_k[kSgChunkMax];    // threshold k of each anchor
   uint8_t i_join[kSgChunkMax];  // 1 if the anchor's senders need the join
   uint8_t i_gsd[kSgChunkMax];   // 1 if u has k scatter destinations after tau
   uint8_t grp_seg[kSgChunkMax]; // first anchor of each segment of the current group
   // (anchor, sender) pairs of one batch
-  uint32_t pr_b[AMLM_WAVE], pr_n[AMLM_WAVE], pr_off[AMLM_WAVE], pr_cnt[AMLM_WAVE];
+  uint32_t pr_b[AMLM_WAVE], pr_cnt[AMLM_WAVE];
+  // each pair's slice length until the join has read it into a register,
+  // then the exclusive offsets of the slices flattened over the lanes
+  union {
+    uint32_t pr_n[AMLM_WAVE];
+    uint32_t pr_off[AMLM_WAVE];
+  };
   uint8_t pr_item[AMLM_WAVE];
   uint8_t pr_rev[AMLM_WAVE];   // 1: the pair joins from the gather side (sg_join_rev)
   // Bloom-positive candidates awaiting the exact check
   uint32_t cq_pos[kCandCap];
-  uint8_t cq_pair[kCandCap];  // byte-wide slot fields keep the LDS, and so the waves per CU, in bounds
+  uint8_t cq_pair[kCandCap];
+  // (the byte-wide fields, the shared pair arrays and a filter of at most
+  // 960 words keep the LDS of a wave within 6400 bytes: 24 waves per CU)
 };
 
 // Key mask of a gather vertex v: the filter of a group of segments holds the
@@ -372,26 +378,27 @@ struct SgLds {
 __device__ __forceinline__ uint32_t vkey(uint32_t v) { return __builtin_rotateleft32(vhash(v), 16); }
 
 // Register-blocked Bloom filter over vertex hashes (vhash): a key selects
-// one 32-bit word by its top bits and sets kBloomK bits inside it chosen by
-// consecutive 5-bit fields of its low bits, so a test is a single LDS read and
-// a few shifts.  The word index uses at most 10 bits (wshift >= 22).
+// one of the filter's `words` 32-bit words by its top 12 bits (scaled to the
+// word count, which need not be a power of two) and sets kBloomK bits inside
+// it chosen by consecutive 5-bit fields of its low bits, so a test is a
+// single LDS read, a multiply and a few shifts.
 struct BloomProbe {
   uint32_t word, mask;
 };
-__device__ __forceinline__ BloomProbe bloom_probe(uint32_t h, int wshift) {
+__device__ __forceinline__ BloomProbe bloom_probe(uint32_t h, uint32_t words) {
   BloomProbe p;
-  p.word = h >> wshift;
+  p.word = ((h >> 20) * words) >> 12;
   p.mask = 0;
 #pragma unroll
   for (int i = 0; i < kBloomK; i++) p.mask |= 1u << ((h >> (5 * i)) & 31u);
   return p;
 }
-__device__ __forceinline__ bool bloom_test(const uint32_t *bloom, int wshift, uint32_t h) {
-  BloomProbe p = bloom_probe(h, wshift);
+__device__ __forceinline__ bool bloom_test(const uint32_t *bloom, uint32_t words, uint32_t h) {
+  BloomProbe p = bloom_probe(h, words);
   return (bloom[p.word] & p.mask) == p.mask;
 }
-__device__ __forceinline__ void bloom_insert(uint32_t *bloom, int wshift, uint32_t h) {
-  BloomProbe p = bloom_probe(h, wshift);
+__device__ __forceinline__ void bloom_insert(uint32_t *bloom, uint32_t words, uint32_t h) {
+  BloomProbe p = bloom_probe(h, words);
   atomicOr(&bloom[p.word], p.mask);
 }
 
@@ -463,7 +470,7 @@ __device__ __forceinline__ void sg_push(const MineParams &mp, SgLds &L, uint32_t
 // folded by each pair's own lane in that order into its k - 1 latest g_m,
 // as the serial scan of sg_phase_pair does.  A pair is decided at the first
 // interval where the condition holds; its later entries are skipped.
-__device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int shift, uint32_t k) {
+__device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, uint32_t words, uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
@@ -476,7 +483,7 @@ __device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int s
   for (uint32_t i = 0; i < kPhaseKMax - 1; i++) top[i] = AMLM_INT_MIN;
   uint32_t my_n = 0;
   if (lane < np) {
-    my_n = L.pr_n[lane];
+    my_n = L.pr_n[lane];  // before the offsets take its place
     if (my_n) {
       const uint32_t it = L.pr_item[lane], s = g.out_src[L.pr_b[lane]], u = L.i_u[it];
       const int32_t lo = L.i_lo[it], t = L.i_t[it];
@@ -503,7 +510,7 @@ __device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int s
         const uint32_t it = L.pr_item[a], u = L.i_u[it];
         const int32_t lo = L.i_lo[it], t = L.i_t[it];
         const uint32_t m = g.out_nbr[pos];
-        if (m != u && g.out_prv[pos] < lo && bloom_test(L.bloom, shift, g.out_h[pos] ^ L.i_vk[it])) {
+        if (m != u && g.out_prv[pos] < lo && bloom_test(L.bloom, words, g.out_h[pos] ^ L.i_vk[it])) {
           const uint32_t vrs = L.i_vrs[it], vre = L.i_vre[it];
           const uint32_t q = upper_bound_u64_interp(g.inn_key, vrs, vre, nbr_key(m, t));
           if (q > vrs) {
@@ -563,11 +570,10 @@ __device__ void sg_join_phase(const MineParams &mp, SgLds &L, uint32_t np, int s
 // search in m's neighbour-sorted in-row, comes before that edge (ordered) or
 // before t (unordered).  A pair stops once k - 1 intermediates besides u
 // have qualified.
-__device__ void sg_join_rev(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, uint32_t need) {
+__device__ void sg_join_rev(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, uint32_t need,
+                            uint32_t nr) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
-  const bool mine = (rev >> lane) & 1ull;
-  const uint32_t nr = mine ? L.pr_n[lane] : 0u;
   const uint32_t incl = wave_incl_scan(nr);
   const uint32_t T = rfl((uint32_t)__shfl(incl, AMLM_WAVE - 1, AMLM_WAVE));
   L.pr_off[lane] = incl - nr;
@@ -604,19 +610,21 @@ __device__ void sg_join_rev(const MineParams &mp, SgLds &L, uint32_t np, uint64_
 // its slice [pr_b, pr_b + pr_n) of the sender's out-row.  Long slices are
 // scanned one pair at a time by the whole wave with the pair's fields in
 // scalar registers; short ones are flattened over the lanes.
-__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, int shift, uint32_t k) {
+__device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t rev, uint32_t words, uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint32_t need = k - 1;  // intermediates needed besides u
   uint32_t cq = 0;
   constexpr int U = kJoinUnroll;  // independent 256-byte loads in flight per wave
   const bool my_rev = (rev >> lane) & 1ull;
-  const uint32_t my_n = lane < np && !my_rev ? L.pr_n[lane] : 0u;
+  // the slice lengths, before the offsets take their place
+  const uint32_t pn = lane < np ? L.pr_n[lane] : 0u;
+  const uint32_t my_n = my_rev ? 0u : pn;
   uint64_t longs = __ballot(my_n >= kLongPair);
   while (longs) {
     uint32_t a = __ffsll((long long)longs) - 1;
     longs &= longs - 1;
-    const uint32_t b = rfl(L.pr_b[a]), n = rfl(L.pr_n[a]);
+    const uint32_t b = rfl(L.pr_b[a]), n = rfl((uint32_t)__shfl(my_n, a, AMLM_WAVE));
     const uint32_t it = rfl((uint32_t)L.pr_item[a]);
     const uint32_t hu = rfl(L.i_hu[it]), vk = rfl(L.i_vk[it]);  // u itself is never a candidate
     for (uint32_t f0 = 0; f0 < n; f0 += U * AMLM_WAVE) {
@@ -626,7 +634,7 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
       auto step = [&]() {
 #pragma unroll
         for (int r = 0; r < U; r++) {
-          bool cand = (h[r] != hu) & bloom_test(L.bloom, shift, h[r] ^ vk);
+          bool cand = (h[r] != hu) & bloom_test(L.bloom, words, h[r] ^ vk);
           sg_push(mp, L, cq, cand, a, b + f0 + r * AMLM_WAVE + lane);
         }
       };
@@ -661,7 +669,7 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
       if (L.pr_cnt[a] < need) {
         uint32_t h = g.out_h[pos];
         const uint32_t it = L.pr_item[a];
-        cand = h != L.i_hu[it] && bloom_test(L.bloom, shift, h ^ L.i_vk[it]);
+        cand = h != L.i_hu[it] && bloom_test(L.bloom, words, h ^ L.i_vk[it]);
       }
     }
     sg_push(mp, L, cq, cand, a, pos);
@@ -675,7 +683,7 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
     sg_verify(mp, L, cq, take);
     cq -= take;
   }
-  if (rev) sg_join_rev(mp, L, np, rev, need);
+  if (rev) sg_join_rev(mp, L, np, rev, need, my_rev ? pn : 0u);
 }
 
 // Anchors [s0, s1) of the chunk: a group of nseg segments whose first
@@ -686,15 +694,14 @@ __device__ void sg_join(const MineParams &mp, SgLds &L, uint32_t np, uint64_t re
 // senders, pairs and joins of the whole group are flattened over the lanes
 // together (a chunk of anchors into many light vertices is one pass, not one
 // per vertex).
-__device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t nseg) {
+__device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s1, uint32_t nseg, uint32_t k) {
   const GraphView &g = mp.g;
   const uint32_t lane = lane_id();
   const uint64_t lt = lanemask_lt();
   const uint32_t nit = s1 - s0;
-  const uint32_t k = rfl(L.i_k[s0]);  // groups are cut where k changes
   const bool need_join = mp.col_sg >= 0 && k >= 2 &&
                          __ballot(lane >= s0 && lane < s1 && L.i_join[min(lane, kSgChunkMax - 1)] != 0) != 0;
-  int shift = 0;
+  uint32_t words = 0;
   if (need_join) {
     // segment j holds anchors [grp_seg[j], grp_seg[j + 1]) (the last ends at
     // s1); the anchors are time-sorted inside it
@@ -708,9 +715,8 @@ __device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s
     if (lane < kSgChunkMax) L.seg_off[lane] = incl - len;
     int lg = 9;
     while (lg < kBloomLog2Max && (1u << lg) < nin * kBloomBitsPerEntry) lg++;
-    uint32_t words = (1u << lg) >> 5;
+    words = min((1u << lg) >> 5, kBloomWordsMax);
     for (uint32_t q = lane; q < words; q += AMLM_WAVE) L.bloom[q] = 0;
-    shift = 32 - (lg - 5);  // word index = top (lg - 5) bits
     if (nseg == 1) {
       // one window (a hub's row, typically): strided loads, four in flight
       const uint32_t r0 = rfl(L.i_r0[s0]), r1 = r0 + nin, vk = rfl(L.i_vk[s0]);
@@ -723,7 +729,7 @@ __device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          if (q0 + r * AMLM_WAVE + lane < r1) bloom_insert(L.bloom, shift, mm[r] ^ vk);
+          if (q0 + r * AMLM_WAVE + lane < r1) bloom_insert(L.bloom, words, mm[r] ^ vk);
         }
       }
     } else {
@@ -743,7 +749,7 @@ __device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          if (f0 + r * AMLM_WAVE + lane < nin) bloom_insert(L.bloom, shift, mm[r]);
+          if (f0 + r * AMLM_WAVE + lane < nin) bloom_insert(L.bloom, words, mm[r]);
         }
       }
     }
@@ -771,7 +777,7 @@ __device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s
       it = s0 + a;
       j = L.i_p0[it] + (f - L.seg_off[a]);
       nb = g.in_nbr[j];
-      if (nb != L.i_v[it]) {
+      if (vkey(nb) != L.i_vk[it]) {  // nb != v (vkey is a bijection)
         is_s = g.in_nxt[j] >= L.i_t[it];  // last sender edge before t: one per distinct s
         if (is_s) atomicAdd(&L.i_ns[it], 1u);
       }
@@ -813,9 +819,9 @@ __device__ void sg_group(const MineParams &mp, SgLds &L, uint32_t s0, uint32_t s
     // reverse pairs by slot
     const uint64_t rev = __ballot(lane < np && L.pr_rev[lane] != 0);
     if (mp.sg_phase)
-      sg_join_phase(mp, L, np, shift, k);
+      sg_join_phase(mp, L, np, words, k);
     else
-      sg_join(mp, L, np, rev, shift, k);
+      sg_join(mp, L, np, rev, words, k);
     if (lane < np && L.pr_cnt[lane] >= k - 1) atomicAdd(&L.i_sg[L.pr_item[lane]], 1u);
   }
 }
@@ -1003,11 +1009,11 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
     const uint2 un = units ? units[c] : make_uint2(c * block, min(block, n_count - c * block));
     const bool heavy = (un.y & kUnitHeavy) != 0;
     const uint32_t nr = heavy ? 1u : un.y;
-    uint32_t v = 0xffffffffu, r0v = 0, r1v = 0, kv = 0;
+    uint32_t v = 0xffffffffu, r0v = 0, r1v = 0, kv = 0, eid = 0;
     int64_t dl = 1;
     if (lane < nr) {
       uint32_t q = items[un.x + lane];
-      uint32_t eid = g.in_eid[q];
+      eid = g.in_eid[q];
       int32_t t = g.in_t[q];
       uint4 pw = sg_win[q];
       uint32_t first_slice = 1;
@@ -1020,10 +1026,8 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
       }
       v = g.in_dst[q];
       const uint32_t u = g.in_nbr[q];
-      L.i_eid[lane] = eid;
       L.i_u[lane] = u;
       L.i_hu[lane] = vhash(u);
-      L.i_v[lane] = v;
       L.i_vk[lane] = vkey(v);
       L.i_vrs[lane] = g.in_ptr[v];
       L.i_vre[lane] = g.in_ptr[v + 1];
@@ -1031,7 +1035,6 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
       dl = delta_of(mp, v);
       L.i_lo[lane] = window_lo(t, dl);
       kv = k_of(mp, v);
-      L.i_k[lane] = kv;
       const uint8_t fl = flags_sg[q];
       L.i_join[lane] = (fl & kFlagSgNoJoin) ? 0 : 1;
       L.i_gsd[lane] = (fl & kFlagGsDest) ? 1 : 0;
@@ -1083,19 +1086,19 @@ __global__ __launch_bounds__(AMLM_WAVE) AMLM_SG_OCCUPANCY void k_sg(MineParams m
       // the group's segment heads, in order
       const uint64_t sh = heads & ((1ull << g1) - 1) & ~((1ull << g0) - 1);  // g1 <= nr <= 16
       if ((sh >> lane) & 1ull) L.grp_seg[__popcll(sh & lanemask_lt())] = (uint8_t)lane;
-      sg_group(mp, L, g0, g1, (uint32_t)__popcll(sh));
+      // groups are cut where k changes: the group's k is its first anchor's
+      sg_group(mp, L, g0, g1, (uint32_t)__popcll(sh), rfl((uint32_t)__shfl(kv, g0, AMLM_WAVE)));
     }
     // gather-scatter and the outputs, one lane per anchor
     uint32_t sg = 0, gs = 0, work = 0;
     if (lane < nr) {
-      const uint32_t k = L.i_k[lane], ns = L.i_ns[lane];
+      const uint32_t k = kv, ns = L.i_ns[lane];
       sg = k == 1 ? ns : L.i_sg[lane];
       work = L.i_work[lane];
       // k == 1: v follows tau, so D is never empty
       if (mp.col_gs >= 0 && ns >= k && ns > 0 && (k == 1 || L.i_gsd[lane])) gs = ns;
     }
     if (lane < nr) {
-      uint32_t eid = L.i_eid[lane];
       if (heavy) {
         // a slice: partial SG_k, and its senders towards the GS_k of k_split_gs
         // (plain adds: the sums are at most the number of accounts; the
