@@ -136,8 +136,10 @@ __global__ void k_reltime(const int64_t *ts, int64_t tmin, const uint32_t *src, 
 // ---------------------------------------------------------------- scan
 constexpr uint32_t kScanBlock = 2048;  // elements per block (256 threads x 8)
 
-__global__ void k_scan_block(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *block_sums) {
+__global__ void k_scan_block(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *block_sums,
+                             const uint32_t *n_dev) {
   __shared__ uint32_t wsum[kThreads / AMLM_WAVE];
+  if (n_dev) n = min(n, *n_dev);
   uint32_t tid = threadIdx.x, w = tid / AMLM_WAVE;
   uint32_t base = blockIdx.x * kScanBlock + tid * 8;
   uint32_t v[8], s = 0;
@@ -162,8 +164,10 @@ __global__ void k_scan_block(const uint32_t *in, uint32_t *out, uint32_t n, uint
   if (tid == kThreads - 1 && block_sums) block_sums[blockIdx.x] = woff + incl;
 }
 
-__global__ void k_scan_add(uint32_t *out, uint32_t n, const uint32_t *block_offsets) {
+__global__ void k_scan_add(uint32_t *out, uint32_t n, const uint32_t *block_offsets, const uint32_t *n_dev) {
+  if (n_dev) n = min(n, *n_dev);
   uint32_t b = blockIdx.x;
+  if (b * kScanBlock >= n) return;
   uint32_t add = block_offsets[b];
   uint32_t base = b * kScanBlock;
   for (uint32_t j = threadIdx.x; j < kScanBlock; j += blockDim.x) {
@@ -172,7 +176,9 @@ __global__ void k_scan_add(uint32_t *out, uint32_t n, const uint32_t *block_offs
   }
 }
 
-__global__ void k_scan_total(const uint32_t *in, const uint32_t *out, uint32_t n, uint32_t *total) {
+__global__ void k_scan_total(const uint32_t *in, const uint32_t *out, uint32_t n, uint32_t *total,
+                             const uint32_t *n_dev) {
+  if (n_dev) n = min(n, *n_dev);
   if (threadIdx.x == 0) *total = n ? out[n - 1] + in[n - 1] : 0;
 }
 
@@ -412,27 +418,30 @@ size_t scan_tmp_words(uint64_t n) {
   return w + 64;
 }
 
-static hipError_t scan_rec(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tmp, hipStream_t s) {
+// (blocks past a device-side count write zero block sums, so the scan of
+// the block sums is a plain one)
+static hipError_t scan_rec(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tmp, hipStream_t s,
+                           const uint32_t *n_dev) {
   if (n == 0) return hipSuccess;
   uint32_t nb = nblk(n, kScanBlock);
   if (nb == 1) {
-    hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kThreads), 0, s, in, out, n, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(kThreads), 0, s, in, out, n, (uint32_t *)nullptr, n_dev);
     return hipGetLastError();
   }
   uint32_t *sums = tmp, *sums_scan = tmp + nb, *rest = tmp + 2 * nb + 64;
-  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kThreads), 0, s, in, out, n, sums);
-  hipError_t e = scan_rec(sums, sums_scan, nb, rest, s);
+  hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kThreads), 0, s, in, out, n, sums, n_dev);
+  hipError_t e = scan_rec(sums, sums_scan, nb, rest, s, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kThreads), 0, s, out, n, sums_scan);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kThreads), 0, s, out, n, sums_scan, n_dev);
   return hipGetLastError();
 }
 
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *total, uint32_t *tmp,
-                              hipStream_t s) {
-  hipError_t e = scan_rec(in, out, n, tmp, s);
+                              hipStream_t s, const uint32_t *n_dev) {
+  hipError_t e = scan_rec(in, out, n, tmp, s, n_dev);
   if (e != hipSuccess) return e;
   if (total) {
-    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, in, out, n, total);
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, in, out, n, total, n_dev);
     e = hipGetLastError();
   }
   return e;

@@ -505,10 +505,17 @@ hipError_t model_upload(MlpModel &m) {
   return hipMemcpy(m.d_norm, nrm, sizeof(nrm), hipMemcpyHostToDevice);
 }
 
+#ifndef AMLM_MLP_INFER_BPC
+#define AMLM_MLP_INFER_BPC 2
+#endif
+// inference blocks per CU: the kernel runs beside the cycle search, which
+// needs the rest of the chip
+constexpr uint32_t kMlpInferBlocksPerCu = AMLM_MLP_INFER_BPC;
+
 hipError_t mlp_infer(const MlpModel &m, const uint32_t *feat, const uint32_t *idx, uint32_t n_host,
                      const uint32_t *n_dev, float delta_hours, float L, float *pred, hipStream_t s,
                      const uint32_t *in_dst, const uint32_t *vgraph, const SubParams *sub) {
-  uint32_t blocks = 2 * device_info().num_cu;
+  uint32_t blocks = kMlpInferBlocksPerCu * device_info().num_cu;
   hipLaunchKernelGGL(k_mlp_mfma<true>, dim3(blocks), dim3(256), 0, s, m.d_w16, m.d_norm, feat, idx,
                      (const float *)nullptr, n_dev, n_host, delta_hours, L, pred, in_dst, vgraph, sub);
   return hipGetLastError();

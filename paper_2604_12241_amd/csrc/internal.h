@@ -30,10 +30,12 @@ struct BuildBuffers {
 };
 
 // Exclusive scan of n u32 values; out may alias nothing.  total (device,
-// optional) receives the sum.  tmp must hold scan_tmp_words(n) words.
+// optional) receives the sum.  tmp must hold scan_tmp_words(n) words.  With
+// n_dev (device, optional) only the first min(*n_dev, n) values are scanned
+// (a count known on the device only; n bounds the launch).
 size_t scan_tmp_words(uint64_t n);
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *total, uint32_t *tmp,
-                              hipStream_t s);
+                              hipStream_t s, const uint32_t *n_dev = nullptr);
 
 // Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
 // key.  Input in (ka, va); result pointers returned through *kout, *vout

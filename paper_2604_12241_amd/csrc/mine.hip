@@ -879,6 +879,7 @@ __global__ __launch_bounds__(256) void k_split_weight(MineParams mp, const uint3
                                                       const float *pred, uint32_t min_size, unsigned long long *W) {
   __shared__ unsigned long long ws[256 / AMLM_WAVE];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x * blockDim.x >= *n_items_p) return;  // the grid covers Ev items, the list fewer
   unsigned long long w = 0;
   if (i < *n_items_p) {
     uint32_t x;
@@ -916,6 +917,7 @@ __global__ __launch_bounds__(256) void k_unit_count(MineParams mp, const uint32_
   __shared__ uint32_t sl[256];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = *n_items_p;
+  if (blockIdx.x * blockDim.x >= n) return;  // the grid covers Ev items, the list fewer
   const unsigned long long W = *W_p;
   uint32_t ns = 0;
   if (i < n) {
@@ -925,11 +927,7 @@ __global__ __launch_bounds__(256) void k_unit_count(MineParams mp, const uint32_
   }
   sl[threadIdx.x] = ns;
   __syncthreads();
-  if (i >= n_max) return;
-  if (i >= n) {
-    cnt[i] = 0;
-    return;
-  }
+  if (i >= n || i >= n_max) return;  // the scan of the counts stops at n
   bool start = false;
   if (!ns) {
     // the previous item's slices: from this block, or recomputed at its edge
@@ -1481,7 +1479,7 @@ static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineL
                          (const uint4 *)ms.sg_win, pred, cfg.split_bytes, (const unsigned long long *)W, block, Ev,
                          ms.nsub, ms.ucnt);
       CK(hipGetLastError());
-      CK(scan_exclusive_u32(ms.ucnt, ms.uoff, Ev, n_units, ms.scan_tmp, s));
+      CK(scan_exclusive_u32(ms.ucnt, ms.uoff, Ev, n_units, ms.scan_tmp, s, n_sg));
       hipLaunchKernelGGL(k_unit_fill, dim3(nb), dim3(256), 0, s, mp, ms.list_sg, n_sg, ms.nsub, ms.ucnt, ms.uoff,
                          block, ms.units);
       CK(hipGetLastError());
