@@ -486,9 +486,10 @@ static amlm_status mine_impl(amlm_graph *g, const amlm_params *p, uint32_t *coun
   MineLaunch cfg = default_launch(g);
   A_TRY(schedule_config(g, p, cfg));
   if (anchor_lo == 0) {
-    // full mining: the cycle kernel overlaps the cost model on a second
-    // stream (incremental mining of small serving windows stays on one
-    // stream: the server's slots already run concurrently)
+    // full mining: the cycle search runs on a second stream beside the
+    // anchor passes, the cost model and the work units (incremental mining of
+    // small serving windows stays on one stream: the server's slots already
+    // run concurrently)
     if (!g->aux) {
       HIP_TRY(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
       HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));

@@ -98,6 +98,16 @@ constexpr bool kEagerShort = AMLM_EAGER_SHORT != 0;
 // sender's intervals in registers: k is at most this
 constexpr uint32_t kPhaseKMax = 8;
 
+#ifndef AMLM_CYC_EARLY
+#define AMLM_CYC_EARLY 1
+#endif
+// 1: when a second stream is given, the cycle roots are found by a pass of
+// their own and the cycle search starts on that stream before the anchor
+// passes (static schedule: mining 15.27 -> 14.68 ms on the 32M-edge graph,
+// the search no longer alone on the critical path; learned schedule
+// unchanged, 12.17 ms: the anchor passes beside the search take as long as
+// the search takes beside the cost model and the work units)
+constexpr bool kCycEarly = AMLM_CYC_EARLY != 0;
 constexpr int kCycThreads = 64;  // one wave per block: ~13 KB of LDS each
 constexpr uint32_t kMaxDepth = 6;    // L <= 8: at most 6 path edges before the closing hop
 constexpr uint32_t kCycSmallL = 6;   // cycle kernel built with fewer frames for L <= 6

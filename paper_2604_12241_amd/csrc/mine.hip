@@ -163,18 +163,35 @@ __global__ __launch_bounds__(256) void k_anchor_in(MineParams mp, uint8_t *flags
       }
     }
   }
-  if (mp.col_cyc >= 0 || (is_sg && feat)) {
+  if ((flags_cy && mp.col_cyc >= 0) || (is_sg && feat)) {
     uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
     uint32_t q1 = lower_bound_i32(g.out_t, vs, ve, t);
     // any order: v's first hop may also leave at time t itself
     const uint32_t qc = mp.cyc_any ? upper_bound_i32(g.out_t, q1, ve, t) : q1;
-    if (mp.col_cyc >= 0 && qc > vs && g.out_t[qc - 1] >= lo) flags_cy[eid] = kFlagCYC;
+    if (flags_cy && mp.col_cyc >= 0 && qc > vs && g.out_t[qc - 1] >= lo) flags_cy[eid] = kFlagCYC;
     if (is_sg && feat) {
       uint32_t q0 = gallop_lower_left(g.out_t, vs, q1, lo);
       feat[(uint64_t)q * kMlpRaw + 3] = q1 - q0;
       feat[(uint64_t)q * kMlpRaw + 6] = ve - vs;
     }
   }
+}
+
+// Cycle roots alone (the cycle search then starts before the anchor passes):
+// the same test as k_anchor_in's, v has a first hop inside the window.
+__global__ __launch_bounds__(256) void k_cyc_roots(MineParams mp, uint8_t *flags_cy) {
+  const GraphView &g = mp.g;
+  uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.Ev) return;
+  uint32_t eid = g.in_eid[q];
+  if (eid < mp.anchor_lo || eid >= mp.anchor_hi) return;
+  uint32_t v = g.in_dst[q], u = g.in_nbr[q];
+  int32_t t = g.in_t[q];
+  int32_t lo = window_lo(t, delta_of(mp, u));
+  uint32_t vs = g.out_ptr[v], ve = g.out_ptr[v + 1];
+  uint32_t q1 = lower_bound_i32(g.out_t, vs, ve, t);
+  const uint32_t qc = mp.cyc_any ? upper_bound_i32(g.out_t, q1, ve, t) : q1;
+  if (qc > vs && g.out_t[qc - 1] >= lo) flags_cy[eid] = kFlagCYC;
 }
 
 // Phase order for one (anchor, sender) pair, scanning the sender's
@@ -1393,42 +1410,22 @@ static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineL
   const bool learned = cfg.sched != kSchedStatic && mp.col_sg >= 0 && mp.k >= 2;
   const bool use_mlp = learned && cfg.sched == kSchedLearned;
   uint32_t *feat = use_mlp ? ms.feat : (uint32_t *)nullptr;
-  hipLaunchKernelGGL(k_anchor_out, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, ms.sg_win, feat);
-  CK(hipGetLastError());
-  hipLaunchKernelGGL(k_anchor_in, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, flags_cy, ms.sg_win, feat);
-  CK(hipGetLastError());
-  CK(tm->end(kStAnchor, s));
-  if (mp.work && (mp.col_sg >= 0 || mp.col_gs >= 0)) {
-    // accounting run: the method's scatter-gather bytes of every anchor
-    hipLaunchKernelGGL(k_alg_sg, dim3(std::min<uint32_t>((Ev + 3) / 4, 65536)), dim3(256), 0, s, mp);
-    CK(hipGetLastError());
-  }
   const bool want_sg = mp.col_sg >= 0 || mp.col_gs >= 0;
   const bool want_cyc = mp.col_cyc >= 0;
-  if (!want_sg && !want_cyc) return hipSuccess;
-  CK(tm->begin(kStLists, s));
   uint32_t *n_sg = ms.ctr + kCtrNSg, *n_cy = ms.ctr + kCtrNCy;
-  if (want_sg) {
-    uint32_t nb = (Ev + kFlagTile - 1) / kFlagTile;
-    hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, Ev, ms.bcnt_sg);
-    CK(hipGetLastError());
-    CK(scan_exclusive_u32(ms.bcnt_sg, ms.boff_sg, nb, n_sg, ms.scan_tmp, s));
-    hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, Ev, ms.boff_sg, ms.list_sg);
-    CK(hipGetLastError());
-  }
-  if (want_cyc) {
+  // the cycle roots' list, then the cycle search: on the second stream if
+  // given, joined before k_sg
+  auto cyc_list = [&]() -> hipError_t {
+    hipError_t e;
     uint32_t nb = (E + kFlagTile - 1) / kFlagTile;
     hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_cy, E, ms.bcnt_cy);
     CK(hipGetLastError());
     CK(scan_exclusive_u32(ms.bcnt_cy, ms.boff_cy, nb, n_cy, ms.scan_tmp, s));
     hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_cy, E, ms.boff_cy, ms.list_cy);
-    CK(hipGetLastError());
-  }
-  CK(tm->end(kStLists, s));
-  if (want_cyc) {
-    // independent of the scatter-gather stage: on the second stream if
-    // given, beside the cost model and the work units, and joined before
-    // k_sg, which keeps the chip to itself
+    return hipGetLastError();
+  };
+  auto cyc_search = [&]() -> hipError_t {
+    hipError_t e;
     hipStream_t cs = s;
     if (cfg.aux) {
       CK(hipEventRecord(cfg.ev_fork, s));
@@ -1445,7 +1442,41 @@ static hipError_t mine_stages(const MineParams &mp, MineScratch &ms, const MineL
     CK(hipGetLastError());
     CK(tm->end(kStCyc, cs));
     if (cfg.aux) CK(hipEventRecord(cfg.ev_join, cs));
+    return hipSuccess;
+  };
+  const bool cyc_early = kCycEarly && want_cyc && cfg.aux;
+  if (cyc_early) {
+    hipLaunchKernelGGL(k_cyc_roots, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_cy);
+    CK(hipGetLastError());
+    CK(cyc_list());
+    CK(cyc_search());
   }
+  hipLaunchKernelGGL(k_anchor_out, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg, ms.sg_win, feat);
+  CK(hipGetLastError());
+  hipLaunchKernelGGL(k_anchor_in, dim3((Ev + 255) / 256), dim3(256), 0, s, mp, flags_sg,
+                     cyc_early ? (uint8_t *)nullptr : flags_cy, ms.sg_win, feat);
+  CK(hipGetLastError());
+  CK(tm->end(kStAnchor, s));
+  if (mp.work && (mp.col_sg >= 0 || mp.col_gs >= 0)) {
+    // accounting run: the method's scatter-gather bytes of every anchor
+    hipLaunchKernelGGL(k_alg_sg, dim3(std::min<uint32_t>((Ev + 3) / 4, 65536)), dim3(256), 0, s, mp);
+    CK(hipGetLastError());
+  }
+  if (!want_sg && !want_cyc) return hipSuccess;
+  CK(tm->begin(kStLists, s));
+  if (want_sg) {
+    uint32_t nb = (Ev + kFlagTile - 1) / kFlagTile;
+    hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, Ev, ms.bcnt_sg);
+    CK(hipGetLastError());
+    CK(scan_exclusive_u32(ms.bcnt_sg, ms.boff_sg, nb, n_sg, ms.scan_tmp, s));
+    hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(kFlagThreads), 0, s, flags_sg, Ev, ms.boff_sg, ms.list_sg);
+    CK(hipGetLastError());
+  }
+  if (want_cyc && !cyc_early) CK(cyc_list());
+  CK(tm->end(kStLists, s));
+  // independent of the scatter-gather stage: beside the cost model and the
+  // work units, and joined before k_sg, which keeps the chip to itself
+  if (want_cyc && !cyc_early) CK(cyc_search());
   if (want_sg) {
     // learned schedule: the cost model predicts each item's work, which sets
     // how finely the heavy anchors are sliced
