@@ -246,7 +246,7 @@ amlm_status amlm_stage_times(amlm_graph *g, float *ms);
  * sg_blocks, cyc_blocks = persistent grid sizes; split_bytes = learned
  * schedule only: an anchor whose predicted scatter-gather bytes exceed this
  * is cut into slices of about this size, each its own work unit (default
- * 65536).  Never changes a count.  AMLM_E_INVALID for a NULL g. */
+ * 32768).  Never changes a count.  AMLM_E_INVALID for a NULL g. */
 amlm_status amlm_tune_set(amlm_graph *g, uint32_t block, uint32_t sg_blocks, uint32_t cyc_blocks,
                           uint32_t split_bytes);
 
