@@ -112,7 +112,7 @@ def _stream_source(g, n_pool, seed=505):
         rep += 1
 
 
-def bench_serving(A, G, g, p, n_batches=2100, skip=100, slots=4, n_pool=300, inflight=64, loads=(0.5, 0.8)):
+def bench_serving(A, G, g, p, n_batches=6100, skip=100, slots=4, n_pool=300, inflight=64, loads=(0.5, 0.8)):
     """Config-5 style serving: the graph resident, stream batches of 1k-100k
     edges (log-uniform) strictly after its end.  A saturation run (every
     batch queued as fast as the server takes it) gives the sustained rate;
